@@ -1,0 +1,87 @@
+"""Brute-force DTW by enumeration of every warping path (test infrastructure only).
+
+Pure Python, for M, N <= 8.  It shares nothing with the C oracle: it walks the
+definition of a warping path (Sec. 2.1 of Tralie & Dempsey, arXiv 2008.02734:
+W_1 = (0,0), W_K = (M-1,N-1), steps (0,1), (1,0), (1,1)) and the objective of
+Eq. 1 (sum of the frame cost along the path) directly, with no recurrence.
+
+The number of warping paths of an M x N grid is the Delannoy number
+D(M-1, N-1) = sum_k binom(M-1,k) binom(N-1,k) 2^k, which pins the enumerator.
+
+Tie rule: among all minimisers, the path whose move sequence read backwards
+from (M-1,N-1) is lexicographically smallest under DIAG < UP < LEFT, with
+UP = (i-1,j) and LEFT = (i,j-1).  A greedy backtrace that prefers DIAG, then
+UP, then LEFT yields exactly this path.
+"""
+from __future__ import annotations
+
+import math
+from math import comb
+
+DIAG, UP, LEFT = 0, 1, 2
+
+
+def delannoy(m: int, n: int) -> int:
+    """Delannoy number D(m, n): lattice paths from (0,0) to (m,n) with steps E, N, NE."""
+    return sum(comb(m, k) * comb(n, k) * 2**k for k in range(min(m, n) + 1))
+
+
+def frame_cost(x, y) -> float:
+    """Euclidean distance between two frames (Sec. 4.1), summed in dimension order."""
+    s = 0.0
+    for a, b in zip(x, y):
+        e = float(a) - float(b)
+        s += e * e
+    return math.sqrt(s)
+
+
+def enumerate_paths(M: int, N: int):
+    """Yield every warping path of an M x N grid as a tuple of (i, j) cells."""
+    def rec(i, j, acc):
+        if i == M - 1 and j == N - 1:
+            yield tuple(acc)
+            return
+        for di, dj in ((1, 1), (1, 0), (0, 1)):
+            a, b = i + di, j + dj
+            if a < M and b < N:
+                acc.append((a, b))
+                yield from rec(a, b, acc)
+                acc.pop()
+
+    yield from rec(0, 0, [(0, 0)])
+
+
+def backward_moves(path):
+    """Move labels read from the end of the path back to its start."""
+    out = []
+    for q in range(len(path) - 1, 0, -1):
+        (i, j), (pi, pj) = path[q], path[q - 1]
+        if (i - pi, j - pj) == (1, 1):
+            out.append(DIAG)
+        elif (i - pi, j - pj) == (1, 0):
+            out.append(UP)
+        else:
+            out.append(LEFT)
+    return tuple(out)
+
+
+def brute_dtw(X, Y, cost=frame_cost):
+    """Return (optimal cost, tie-broken optimal path, number of paths enumerated).
+
+    Path costs are summed sequentially from (0,0), in path order.
+    """
+    M, N = len(X), len(Y)
+    if M > 8 or N > 8:
+        raise ValueError("brute force is limited to M, N <= 8")
+    C = [[cost(X[i], Y[j]) for j in range(N)] for i in range(M)]
+    best = math.inf
+    best_path = None
+    count = 0
+    for p in enumerate_paths(M, N):
+        count += 1
+        s = 0.0
+        for (i, j) in p:
+            s += C[i][j]
+        if s < best or (s == best and backward_moves(p) < backward_moves(best_path)):
+            best, best_path = s, p
+    return best, best_path, count

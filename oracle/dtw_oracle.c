@@ -1,0 +1,337 @@
+/*
+ * CPU oracle for exact DTW -- test infrastructure only (see dtw_oracle.h).
+ *
+ * Plain single-threaded FP64.  Every function follows one passage of
+ * Tralie & Dempsey, arXiv 2008.02734, cited at the function.  Build with
+ * floating-point contraction off (-ffp-contract=off) so that the only fused
+ * operation is the explicit fma() of the frame cost.
+ *
+ * Readings taken where the paper is silent, garbled or ambiguous (each is
+ * restated where it is used):
+ *   R1  Indexing is 0-based everywhere; the boundary equation covers row 0
+ *       and column 0 (Sec. 2.1 mixes 0- and 1-based indices).
+ *   R2  The three backpointers are LEFT, UP and DIAG as labelled in the
+ *       recurrence (Sec. 2.1 lists "LEFT, RIGHT, and UP").
+ *   R3  Lemma 2's split cost reads D(i,j) + D_{X_R,Y_R}(...) - C(i,j), i.e.
+ *       S = F + B - C (the printed equation has C and D swapped; the prose
+ *       after it and Algorithm 2 give this form).
+ *   R4  DiagDTW(kstop) returns diagonals kstop-2, kstop-1, kstop, oldest
+ *       first; Algorithm 2 pairs forward diagonal q with reversed diagonal
+ *       (kb - q'), which with kf = ceil(K/2) and kb = kf + [K even] is the
+ *       same cell set (kf + kb = K + 1).
+ *   R5  Pivot ties ("breaking ties arbitrarily", Sec. 3.2) go to the smallest
+ *       diagonal, then the smallest row.
+ *   R6  The cutoff m must be >= 3: for M',N' >= 3 the band excludes both
+ *       corner diagonals, so each child is strictly smaller.
+ *   R7  Both children include the pivot; the right child's first cell is
+ *       dropped on concatenation (Algorithm 2's return statement).
+ *   R8  The reported cost is the sequential FP64 sum of C along the returned
+ *       path (Eq. 1).
+ */
+#include "dtw_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Euclidean frame cost, Sec. 4.1. */
+double dtwo_frame_cost(const double* x, const double* y, int32_t d) {
+  double s = 0.0;
+  for (int32_t t = 0; t < d; ++t) {
+    double e = x[t] - y[t];
+    s = fma(e, e, s);
+  }
+  return sqrt(s);
+}
+
+enum { MOVE_DIAG = 0, MOVE_UP = 1, MOVE_LEFT = 2 };
+
+/* Textbook DTW, Sec. 2.1: boundary equation, recurrence, backpointers,
+ * backtrace from (M-1,N-1) to (0,0). */
+int dtwo_full(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
+              double* cost, int32_t* path, int64_t path_cap, int64_t* path_len,
+              double* F_out) {
+  if (!X || !Y || M < 1 || N < 1 || d < 1 || !cost || !path_len) return -1;
+  double* F = F_out ? F_out : (double*)malloc(sizeof(double) * (size_t)(M * N));
+  unsigned char* P = (unsigned char*)malloc((size_t)(M * N));
+  if (!F || !P) {
+    if (!F_out) free(F);
+    free(P);
+    return -3;
+  }
+  for (int64_t i = 0; i < M; ++i) {
+    for (int64_t j = 0; j < N; ++j) {
+      double c = dtwo_frame_cost(X + i * d, Y + j * d, d);
+      double f;
+      unsigned char p;
+      if (i == 0 && j == 0) {
+        f = c;
+        p = MOVE_DIAG; /* unused */
+      } else if (i == 0) { /* boundary: prefix sum along row 0 */
+        f = F[j - 1] + c;
+        p = MOVE_LEFT;
+      } else if (j == 0) { /* boundary: prefix sum along column 0 */
+        f = F[(i - 1) * N] + c;
+        p = MOVE_UP;
+      } else {
+        double dg = F[(i - 1) * N + (j - 1)];
+        double up = F[(i - 1) * N + j];
+        double lf = F[i * N + (j - 1)];
+        double best;
+        if (dg <= up && dg <= lf) {
+          best = dg;
+          p = MOVE_DIAG;
+        } else if (up <= lf) {
+          best = up;
+          p = MOVE_UP;
+        } else {
+          best = lf;
+          p = MOVE_LEFT;
+        }
+        f = best + c;
+      }
+      F[i * N + j] = f;
+      P[i * N + j] = p;
+    }
+  }
+  *cost = F[(M - 1) * N + (N - 1)];
+  /* Backtrace into a reversed list, then flip it. */
+  int64_t len = 0;
+  int64_t i = M - 1, j = N - 1;
+  int rc = 0;
+  for (;;) {
+    if (len >= path_cap) { rc = -2; break; }
+    if (path) {
+      path[2 * len] = (int32_t)i;
+      path[2 * len + 1] = (int32_t)j;
+    }
+    ++len;
+    if (i == 0 && j == 0) break;
+    unsigned char p = P[i * N + j];
+    if (p == MOVE_DIAG) { --i; --j; }
+    else if (p == MOVE_UP) { --i; }
+    else { --j; }
+  }
+  if (rc == 0 && path) {
+    for (int64_t a = 0, b = len - 1; a < b; ++a, --b) {
+      int32_t ti = path[2 * a], tj = path[2 * a + 1];
+      path[2 * a] = path[2 * b];
+      path[2 * a + 1] = path[2 * b + 1];
+      path[2 * b] = ti;
+      path[2 * b + 1] = tj;
+    }
+  }
+  *path_len = len;
+  if (!F_out) free(F);
+  free(P);
+  return rc;
+}
+
+/* Number of cells of an Mb x Nb block on local diagonal k (cells (a,k-a)). */
+static int64_t diag_len(int64_t Mb, int64_t Nb, int64_t k) {
+  int64_t lo = k - (Nb - 1) > 0 ? k - (Nb - 1) : 0;
+  int64_t hi = k < Mb - 1 ? k : Mb - 1;
+  return hi >= lo ? hi - lo + 1 : 0;
+}
+
+/* DiagDTW, Algorithm 1 (Sec. 3.1): the accumulated cost is filled one
+ * anti-diagonal at a time; diagonal k needs only diagonals k-1 and k-2, kept
+ * in three buffers that rotate after each diagonal.  Buffers are indexed by
+ * local row a (length Mb) so the neighbour lookups read as in the
+ * recurrence: (a-1,b-1) on k-2, (a-1,b) and (a,b-1) on k-1. */
+int dtwo_diag(const double* X, const double* Y, int32_t d,
+              int64_t i0, int64_t j0, int64_t i1, int64_t j1,
+              int32_t reverse, int64_t kstop, double* out) {
+  if (!X || !Y || !out || d < 1 || i1 < i0 || j1 < j0) return -1;
+  const int64_t Mb = i1 - i0 + 1, Nb = j1 - j0 + 1;
+  if (kstop < 2 || kstop > Mb + Nb - 2) return -1;
+  double* buf = (double*)malloc(sizeof(double) * (size_t)(3 * Mb));
+  if (!buf) return -3;
+  double* dm2 = buf;          /* diagonal k-2 */
+  double* dm1 = buf + Mb;     /* diagonal k-1 */
+  double* dk = buf + 2 * Mb;  /* diagonal k   */
+  for (int64_t a = 0; a < 3 * Mb; ++a) buf[a] = NAN;
+  for (int64_t k = 0; k <= kstop; ++k) {
+    int64_t lo = k - (Nb - 1) > 0 ? k - (Nb - 1) : 0;
+    int64_t hi = k < Mb - 1 ? k : Mb - 1;
+    for (int64_t a = 0; a < Mb; ++a) dk[a] = NAN;
+    for (int64_t a = lo; a <= hi; ++a) {
+      int64_t b = k - a;
+      int64_t gi = reverse ? i1 - a : i0 + a;
+      int64_t gj = reverse ? j1 - b : j0 + b;
+      double c = dtwo_frame_cost(X + gi * d, Y + gj * d, d);
+      double f;
+      if (a == 0 && b == 0) f = c;
+      else if (a == 0) f = dm1[0] + c;          /* F(0,b-1) + C */
+      else if (b == 0) f = dm1[a - 1] + c;      /* F(a-1,0) + C */
+      else {
+        double dg = dm2[a - 1], up = dm1[a - 1], lf = dm1[a];
+        double best = dg;
+        if (up < best) best = up;
+        if (lf < best) best = lf;
+        f = best + c;
+      }
+      dk[a] = f;
+    }
+    if (k == kstop) break;
+    /* circular shift of the three buffers */
+    double* t = dm2;
+    dm2 = dm1;
+    dm1 = dk;
+    dk = t;
+  }
+  memcpy(out, dm2, sizeof(double) * (size_t)Mb);
+  memcpy(out + Mb, dm1, sizeof(double) * (size_t)Mb);
+  memcpy(out + 2 * Mb, dk, sizeof(double) * (size_t)Mb);
+  free(buf);
+  return 0;
+}
+
+typedef struct {
+  const double* X;
+  const double* Y;
+  int32_t d;
+  int32_t m;
+  int32_t* path;
+  int64_t cap;
+  int64_t len;
+  int64_t cells;
+  int32_t* piv;
+  int64_t piv_cap;
+  int64_t n_piv;
+  int depth;
+  double s_min;
+  int err;
+} rec_state;
+
+/* Append a segment; when the accumulated path already ends at the segment's
+ * first cell, that cell is not repeated (R7). */
+static void append_segment(rec_state* st, const int32_t* seg, int64_t n) {
+  int64_t start = 0;
+  if (st->len > 0 && n > 0 && st->path[2 * (st->len - 1)] == seg[0] &&
+      st->path[2 * (st->len - 1) + 1] == seg[1])
+    start = 1;
+  for (int64_t q = start; q < n; ++q) {
+    if (st->len >= st->cap) { st->err = -2; return; }
+    st->path[2 * st->len] = seg[2 * q];
+    st->path[2 * st->len + 1] = seg[2 * q + 1];
+    ++st->len;
+  }
+}
+
+/* One call of Algorithm 2 on the block rows i0..i1, columns j0..j1. */
+static void linm_rec(rec_state* st, int64_t i0, int64_t j0, int64_t i1, int64_t j1) {
+  if (st->err) return;
+  const int64_t Mb = i1 - i0 + 1, Nb = j1 - j0 + 1;
+  const int32_t d = st->d;
+  if (Mb < st->m || Nb < st->m) {
+    /* Cutoff: brute-force (textbook) path on the sub-block. */
+    int32_t* seg = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(Mb + Nb - 1));
+    if (!seg) { st->err = -3; return; }
+    double c;
+    int64_t n = 0;
+    int rc = dtwo_full(st->X + i0 * d, Mb, st->Y + j0 * d, Nb, d, &c, seg, Mb + Nb - 1, &n, NULL);
+    if (rc) { free(seg); st->err = rc; return; }
+    if (st->depth == 0) st->s_min = c;
+    for (int64_t q = 0; q < n; ++q) {
+      seg[2 * q] += (int32_t)i0;
+      seg[2 * q + 1] += (int32_t)j0;
+    }
+    st->cells += Mb * Nb;
+    append_segment(st, seg, n);
+    free(seg);
+    return;
+  }
+  const int64_t K = Mb + Nb - 1;        /* number of diagonals */
+  const int64_t kf = (K + 1) / 2;       /* ceil(K/2) */
+  const int64_t kb = kf + (K % 2 == 0); /* one more when K is even */
+  double* fw = (double*)malloc(sizeof(double) * 3 * (size_t)Mb);
+  double* bw = (double*)malloc(sizeof(double) * 3 * (size_t)Mb);
+  if (!fw || !bw) { free(fw); free(bw); st->err = -3; return; }
+  int rc = dtwo_diag(st->X, st->Y, d, i0, j0, i1, j1, 0, kf, fw);
+  if (!rc) rc = dtwo_diag(st->X, st->Y, d, i0, j0, i1, j1, 1, kb, bw);
+  if (rc) { free(fw); free(bw); st->err = rc; return; }
+  for (int64_t k = 0; k <= kf; ++k) st->cells += diag_len(Mb, Nb, k);
+  for (int64_t k = 0; k <= kb; ++k) st->cells += diag_len(Mb, Nb, k);
+  /* Split cost on the three central diagonals (Lemma 2, R3, R4), argmin (R5). */
+  double best = INFINITY;
+  int64_t ba = -1, bk = -1;
+  for (int64_t k = kf - 2; k <= kf; ++k) {
+    int64_t kr = K - 1 - k; /* the same cells on the reversed sweep */
+    int64_t lo = k - (Nb - 1) > 0 ? k - (Nb - 1) : 0;
+    int64_t hi = k < Mb - 1 ? k : Mb - 1;
+    for (int64_t a = lo; a <= hi; ++a) {
+      int64_t ar = Mb - 1 - a;
+      double f = fw[(k - (kf - 2)) * Mb + a];
+      double b = bw[(kr - (kb - 2)) * Mb + ar];
+      double c = dtwo_frame_cost(st->X + (i0 + a) * d, st->Y + (j0 + k - a) * d, d);
+      double s = (f + b) - c;
+      if (s < best) { best = s; ba = a; bk = k; }
+    }
+  }
+  free(fw);
+  free(bw);
+  if (ba < 0) { st->err = -1; return; }
+  if (st->depth == 0) st->s_min = best;
+  const int64_t pi = i0 + ba, pj = j0 + (bk - ba);
+  if (st->piv) {
+    if (st->n_piv < st->piv_cap) {
+      st->piv[2 * st->n_piv] = (int32_t)pi;
+      st->piv[2 * st->n_piv + 1] = (int32_t)pj;
+    }
+  }
+  ++st->n_piv;
+  st->depth++;
+  linm_rec(st, i0, j0, pi, pj); /* left: X(0..i), Y(0..j) */
+  linm_rec(st, pi, pj, i1, j1); /* right: X(i..), Y(j..), pivot included */
+  st->depth--;
+}
+
+int dtwo_linmdtw(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
+                 int32_t min_block, double* cost, int32_t* path, int64_t path_cap,
+                 int64_t* path_len, double* s_min, int64_t* cells,
+                 int32_t* pivots, int64_t pivots_cap, int64_t* n_pivots) {
+  if (!X || !Y || M < 1 || N < 1 || d < 1 || min_block < 3 || !cost || !path || !path_len)
+    return -1;
+  if (path_cap < M + N - 1) return -2;
+  rec_state st;
+  memset(&st, 0, sizeof(st));
+  st.X = X;
+  st.Y = Y;
+  st.d = d;
+  st.m = min_block;
+  st.path = path;
+  st.cap = path_cap;
+  st.piv = pivots;
+  st.piv_cap = pivots ? pivots_cap : 0;
+  st.s_min = NAN;
+  linm_rec(&st, 0, 0, M - 1, N - 1);
+  if (st.err) return st.err;
+  *path_len = st.len;
+  *cost = dtwo_path_cost(X, M, Y, N, d, path, st.len);
+  if (s_min) *s_min = st.s_min;
+  if (cells) *cells = st.cells;
+  if (n_pivots) *n_pivots = st.n_piv;
+  if (pivots && st.n_piv > pivots_cap) return -2;
+  return 0;
+}
+
+/* Eq. 1 evaluated along a path, after checking the path definition of
+ * Sec. 2.1 (start, end, allowed steps). */
+double dtwo_path_cost(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
+                      const int32_t* path, int64_t path_len) {
+  if (!X || !Y || !path || path_len < 1) return NAN;
+  if (path[0] != 0 || path[1] != 0) return NAN;
+  if (path[2 * (path_len - 1)] != M - 1 || path[2 * (path_len - 1) + 1] != N - 1) return NAN;
+  double s = 0.0;
+  for (int64_t q = 0; q < path_len; ++q) {
+    int32_t i = path[2 * q], j = path[2 * q + 1];
+    if (i < 0 || j < 0 || i >= M || j >= N) return NAN;
+    if (q > 0) {
+      int32_t di = i - path[2 * (q - 1)], dj = j - path[2 * (q - 1) + 1];
+      if (!((di == 0 && dj == 1) || (di == 1 && dj == 0) || (di == 1 && dj == 1))) return NAN;
+    }
+    s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d);
+  }
+  return s;
+}

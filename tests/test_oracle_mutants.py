@@ -1,0 +1,118 @@
+"""Plant plausible mistakes in a copy of the oracle and check that the pins
+catch every one of them (mutation testing on the CPU).
+
+Each mutant is compiled from an edited copy of oracle/dtw_oracle.c into a
+temporary library and exercised in a child process, so that a mutant that
+reads out of bounds cannot take the test runner down.  A mutant "survives"
+when all checks pass; every mutant listed here must be killed.
+"""
+import os
+import subprocess
+import sys
+import textwrap
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "drop_diag_move": ("if (dg <= up && dg <= lf) {", "if (0) {"),
+    "tie_up_before_diag": ("if (dg <= up && dg <= lf) {", "if (dg < up && dg < lf) {"),
+    "row0_boundary_no_prefix": ("f = F[j - 1] + c;", "f = c;"),
+    "col0_boundary_no_prefix": ("f = F[(i - 1) * N] + c;", "f = c;"),
+    "squared_distance": ("return sqrt(s);", "return s;"),
+    "sign_error_in_cost": ("double e = x[t] - y[t];", "double e = x[t] + y[t];"),
+    "kf_floor_not_ceil": ("const int64_t kf = (K + 1) / 2;", "const int64_t kf = K / 2;"),
+    "kb_not_incremented": ("const int64_t kb = kf + (K % 2 == 0);", "const int64_t kb = kf;"),
+    "split_adds_cost": ("double s = (f + b) - c;", "double s = (f + b) + c;"),
+    "split_drops_cost": ("double s = (f + b) - c;", "double s = f + b;"),
+    "backward_not_reversed": ("int64_t gi = reverse ? i1 - a : i0 + a;", "int64_t gi = i0 + a;"),
+    "diag_wrong_neighbour": ("double dg = dm2[a - 1], up = dm1[a - 1], lf = dm1[a];",
+                             "double dg = dm2[a], up = dm1[a - 1], lf = dm1[a];"),
+    "duplicate_pivot_kept": ("    start = 1;\n", "    start = 0;\n"),
+    "pivot_tie_last": ("if (s < best) { best = s; ba = a; bk = k; }",
+                       "if (s <= best) { best = s; ba = a; bk = k; }"),
+    "path_cost_scaled": ("s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d);",
+                          "s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d) * 1.0000001;"),
+}
+
+CHECKS = textwrap.dedent(r'''
+    import sys, json, numpy as np
+    sys.path.insert(0, sys.argv[2])
+    import oracle
+    from oracle.brute import brute_dtw
+    from paper_2008_02734_amd import synth
+    L = oracle.load(sys.argv[1])
+    fails = []
+    def check(name, ok):
+        if not ok: fails.append(name)
+    # golden hand-worked examples
+    ex = json.load(open(sys.argv[2] + "/tests/golden/hand_examples.json"))["examples"]
+    for e in ex:
+        X, Y = np.array(e["X"], float), np.array(e["Y"], float)
+        c, p, F = oracle.full(X, Y, return_table=True, L=L)
+        check("golden", F.tolist() == e["F"] and p.tolist() == e["path"] and c == e["cost"])
+    # brute force, continuous and tie-heavy
+    for s in range(12):
+        X, Y = synth.random_pair(100 + s, 3 + s % 5, 2 + s % 6, 1 + s % 3, "normal")
+        c, p = oracle.full(X, Y, L=L)
+        b, bp, _ = brute_dtw(X, Y)
+        check("brute", p.tolist() == [list(q) for q in bp] and abs(c - b) <= 1e-12 * max(1, b))
+        X, Y = synth.random_pair(500 + s, 3 + s % 6, 4 + s % 5, 1, "int3")
+        c, p = oracle.full(X, Y, L=L)
+        b, bp, _ = brute_dtw(X, Y)
+        check("brute_ties", p.tolist() == [list(q) for q in bp] and c == b)
+    # DiagDTW against the row-major table, forward and reversed
+    X, Y = synth.random_pair(7, 11, 8, 3, "normal")
+    _, _, F = oracle.full(X, Y, return_table=True, L=L)
+    _, _, FR = oracle.full(X[::-1].copy(), Y[::-1].copy(), return_table=True, L=L)
+    for kstop in (2, 5, 9, 17):
+        for rev, T in ((0, F), (1, FR)):
+            out = oracle.diag(X, Y, 0, 0, 10, 7, rev, kstop, L=L)
+            for q in range(3):
+                for a in range(11):
+                    b = kstop - 2 + q - a
+                    if 0 <= b < 8:
+                        check("diag", out[q, a] == T[a, b])
+    # linmdtw against the textbook path (tie-free) and optimum (ties)
+    for s in range(4):
+        X, Y = synth.random_pair(3000 + s, 25 + 5 * s, 19 + 3 * s, 3, "normal")
+        c, p = oracle.full(X, Y, L=L)
+        for m in (3, 7):
+            r = oracle.linmdtw(X, Y, min_block=m, L=L)
+            check("linm", r["path"].tolist() == p.tolist() and abs(r["cost"] - c) <= 1e-12 * c)
+        X, Y = synth.random_pair(4000 + s, 17 + s, 23 - s, 1, "int3")
+        c, _ = oracle.full(X, Y, L=L)
+        r = oracle.linmdtw(X, Y, min_block=3, L=L)
+        check("linm_ties", r["cost"] == c)
+    # pivot tie rule on an all-tie input (every split cost is 0)
+    Z = np.zeros((40, 1)); W = np.zeros((33, 1))
+    r = oracle.linmdtw(Z, W, min_block=3, L=L)
+    K = 40 + 33 - 1; kf = (K + 1) // 2; k = kf - 2
+    check("pivot_tie", tuple(r["pivots"][0]) == (max(0, k - 32), k - max(0, k - 32)))
+    sys.exit(1 if fails else 0)
+''')
+
+
+def _run(lib_path):
+    return subprocess.run([sys.executable, "-c", CHECKS, lib_path, ROOT],
+                          capture_output=True, timeout=120)
+
+
+def test_unmutated_oracle_passes_checks(tmp_path):
+    src = oracle.source()
+    lib = oracle.build_variant(src, str(tmp_path / "liborig.so"))
+    r = _run(lib)
+    assert r.returncode == 0, r.stderr.decode()[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_killed(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = oracle.source()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    lib = oracle.build_variant(src.replace(old, new), str(tmp_path / f"lib{name}.so"))
+    r = _run(lib)
+    assert r.returncode != 0, f"mutant {name} survived every pin"
