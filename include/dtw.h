@@ -1,0 +1,166 @@
+/*
+ * dtw.h -- C-ABI of the MI355X (gfx950) linear-memory exact DTW library
+ * (libdtw_hip.so).
+ *
+ * The library computes an optimal dynamic-time-warping alignment between two
+ * multivariate series with the divide-and-conquer method of Tralie & Dempsey,
+ * "Exact, Parallelizable Dynamic Time Warping Alignment with Linear Memory"
+ * (arXiv 2008.02734), Algorithm 2: forward and backward anti-diagonal
+ * wavefront sweeps (Algorithm 1, "DiagDTW") to the three central diagonals,
+ * the split cost F + B - C on them (Lemma 2), an argmin pivot that lies on an
+ * optimal path, recursion on the two sub-rectangles, and a full-table solve
+ * with backtrace for blocks whose shorter side is below the cutoff m
+ * (Sec. 3.2).  Working memory is O(M + N) plus the leaf tables.
+ *
+ * Conventions for every entry point:
+ *   - X is M x d and Y is N x d, row-major, one frame per row, contiguous, in
+ *     device memory.  Element type is given by dtw_dtype.
+ *   - The frame cost is the Euclidean distance (Sec. 4.1).
+ *   - The warping path (Sec. 2.1) is written as int32 pairs (i, j) from (0,0)
+ *     to (M-1, N-1); its length lies in [max(M,N), M+N-1].
+ *   - Ownership: the caller owns X, Y, the outputs and the workspace; the
+ *     library allocates no device memory in dtw_align / dtw_align_batched /
+ *     dtw_diag.  Buffers must stay valid until the stream has completed.
+ *   - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *     Calls are stream-ordered and return before the work completes, unless
+ *     a host-visible result is requested (stats != NULL or
+ *     opts->validate_finite != 0), in which case the call synchronises the
+ *     stream before returning.
+ *   - Errors: a negative dtw_status.  Argument errors are detected before any
+ *     work is enqueued.  No partial output is promised after an error.
+ *     DTW_ERR_HIP carries the HIP error code, readable with
+ *     dtw_last_hip_error().
+ *   - Floating point: in DTW_PREC_FP64 the frame cost is the sum over the
+ *     dimensions in index order of fma(e, e, s) with e = x - y, followed by a
+ *     correctly rounded square root; every accumulated cost is one rounded
+ *     addition of the exact minimum of its three predecessors.
+ */
+#ifndef DTW_H
+#define DTW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DTW_OK = 0,
+  DTW_ERR_INVALID_ARG = -1, /* null pointer, size < 1, unsupported combination */
+  DTW_ERR_CAPACITY = -2,    /* path capacity below M + N - 1                    */
+  DTW_ERR_WORKSPACE = -3,   /* workspace smaller than dtw_workspace_size()      */
+  DTW_ERR_NONFINITE = -4,   /* NaN/Inf in X or Y (only with validate_finite)    */
+  DTW_ERR_HIP = -5,         /* a HIP runtime call failed                        */
+  DTW_ERR_BUSY = -6,        /* serving: result not ready yet                     */
+  DTW_ERR_NOT_FOUND = -7,   /* serving: unknown ticket                          */
+  DTW_ERR_UNSUPPORTED = -8, /* feature dimension or mode not built              */
+  DTW_ERR_INTERNAL = -9     /* device-side consistency check failed             */
+} dtw_status;
+
+/* Element type of X and Y. */
+typedef enum { DTW_F64 = 0, DTW_F32 = 1 } dtw_dtype;
+
+/* Arithmetic of the sweeps.  The split cost F + B - C, the argmin that picks
+ * the pivot, and the reported path cost are FP64 in every mode. */
+typedef enum {
+  DTW_PREC_FP64 = 0,     /* exact method: frame cost and accumulation in FP64          */
+  DTW_PREC_FP32 = 1,     /* frame cost and accumulation in FP32 on the vector ALUs     */
+  DTW_PREC_BF16_COST = 2 /* frame cost from a BF16 Gram tile on MFMA, FP32 accumulation */
+} dtw_precision;
+
+typedef struct dtw_opts {
+  int32_t precision;       /* dtw_precision, default DTW_PREC_FP64                       */
+  int32_t min_block;       /* m of Algorithm 2: a block is solved with the full table when
+                              its shorter side is below m.  Default 500 (Sec. 3.2);
+                              valid range [3, 1024]: below 3 the recursion would not
+                              terminate, above 1024 a leaf no longer fits one workgroup */
+  int32_t validate_finite; /* nonzero: scan X and Y for NaN/Inf first (synchronises)    */
+  int32_t reserved[5];     /* must be zero                                                */
+} dtw_opts;
+
+typedef struct dtw_stats {
+  double s_min;            /* min of F + B - C at the top split (the optimal cost up to
+                              rounding), or the full-table cost when the whole problem is
+                              one leaf                                                     */
+  double cost_lowp;        /* reserved: internal reduced-precision cost (0 in FP64 mode)  */
+  int64_t cells_processed; /* cells evaluated by both half sweeps of every split plus the
+                              cells of every leaf table (progress measure of Sec. 3.2)     */
+  int64_t path_len;        /* number of (i,j) pairs written                               */
+  int64_t workspace_bytes; /* bytes of the workspace this problem needs                  */
+  int32_t levels;          /* split levels executed                                       */
+  int32_t leaves;          /* leaf blocks solved with the full table                      */
+  int32_t device_error;    /* 0, or a device-side consistency code                        */
+  int32_t reserved[5];
+} dtw_stats;
+
+/* Fill *opts with the defaults (FP64, m = 500, no validation). */
+void dtw_default_opts(dtw_opts* opts);
+
+/* Human-readable name of a status code (static string). */
+const char* dtw_status_string(int32_t status);
+
+/* HIP error code of the most recent DTW_ERR_HIP on the calling thread. */
+int32_t dtw_last_hip_error(void);
+
+/* Workspace bytes needed by dtw_align for an M x N problem of dimension d.
+ * opts may be NULL (defaults).  Returns DTW_OK and writes *bytes. */
+dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
+                              const dtw_opts* opts, size_t* bytes);
+
+/* Optimal warping path and its cost (Algorithm 2 of arXiv 2008.02734).
+ *   X, Y        device, M x d and N x d, element type in_dtype
+ *   workspace   device, at least dtw_workspace_size() bytes, any contents
+ *   cost_out    device, 1 double: FP64 sum of the FP64 frame costs along the path
+ *   path_out    device, 2 * path_cap int32: the (i, j) pairs
+ *   path_cap    capacity in pairs, must be >= M + N - 1
+ *   path_len_out device, 1 int64
+ *   stats       host, may be NULL; when set the call synchronises `stream`
+ *   stream      hipStream_t or NULL
+ * Supported feature dimensions: 1 <= d <= 32 for DTW_PREC_FP64 / FP32,
+ * d a multiple of 32 up to 256 for DTW_PREC_BF16_COST. */
+dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t d,
+                     int32_t in_dtype, const dtw_opts* opts, void* workspace,
+                     size_t ws_bytes, double* cost_out, int32_t* path_out,
+                     int64_t path_cap, int64_t* path_len_out, dtw_stats* stats,
+                     void* stream);
+
+/* DiagDTW (Algorithm 1): one wavefront sweep over the block rows i0..i1,
+ * columns j0..j1 of X, Y, stopping at local diagonal kstop
+ * (2 <= kstop <= Mb + Nb - 2, Mb = i1-i0+1, Nb = j1-j0+1).
+ *   reverse = 0: the sweep starts at (i0, j0); local cell (a, b) = (i0+a, j0+b).
+ *   reverse = 1: the sweep runs on the reversed series from (i1, j1); local cell
+ *                (a, b) = (i1-a, j1-b).
+ *   out (device, 3 * Mb doubles): out[q*Mb + a] = accumulated cost of local cell
+ *   (a, kstop-2+q-a), q = 0,1,2, or NaN where that cell is outside the block.
+ * X holds at least i1+1 frames and Y at least j1+1.  Uses the same wavefront
+ * kernel as dtw_align; needs dtw_workspace_size(i1+1, j1+1, d, in_dtype, opts)
+ * bytes of workspace, opts->precision = precision. */
+dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype,
+                    int64_t i0, int64_t j0, int64_t i1, int64_t j1, int32_t reverse,
+                    int64_t kstop, int32_t precision, void* workspace, size_t ws_bytes,
+                    double* out, void* stream);
+
+/* Batched form: B independent pairs packed back to back.
+ *   x_offsets, y_offsets  host, B+1 frame offsets (pair b uses frames
+ *                         x_offsets[b] .. x_offsets[b+1]-1 of X_packed)
+ *   path_offsets          host, B+1 pair offsets into paths_out; pair b needs
+ *                         capacity >= M_b + N_b - 1
+ *   costs_out             device, B doubles; paths_out device int32 pairs;
+ *   path_lens_out         device, B int64
+ * All pairs share one launch per recursion level.  Results are identical to
+ * calling dtw_align on each pair.  Workspace: dtw_workspace_size_batched(). */
+dtw_status dtw_workspace_size_batched(int32_t B, const int64_t* x_offsets,
+                                      const int64_t* y_offsets, int32_t d, int32_t in_dtype,
+                                      const dtw_opts* opts, size_t* bytes);
+dtw_status dtw_align_batched(int32_t B, const void* X_packed, const int64_t* x_offsets,
+                             const void* Y_packed, const int64_t* y_offsets, int32_t d,
+                             int32_t in_dtype, const dtw_opts* opts, void* workspace,
+                             size_t ws_bytes, double* costs_out, int32_t* paths_out,
+                             const int64_t* path_offsets, int64_t* path_lens_out,
+                             dtw_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTW_H */

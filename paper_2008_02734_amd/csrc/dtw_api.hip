@@ -1,0 +1,458 @@
+// Host runtime of libdtw_hip.so: argument checks, workspace planning and the
+// launch sequence of one alignment (Algorithm 2 of arXiv 2008.02734 run
+// level-synchronously, every level's work lists resident on the device).
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "dtw.h"
+#include "dtw_internal.h"
+
+namespace dtw {
+hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t st);
+hipError_t launch_leaf(const Work& w, bool f32, int grid, size_t lds_bytes, int64_t lds_leaf_bytes,
+                       const void* Xo, const void* Yo, int in_f64, hipStream_t st);
+hipError_t set_leaf_lds_limit(size_t bytes);
+hipError_t launch_init(const Work& w, hipStream_t st);
+hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t st);
+hipError_t launch_combine(const Work& w, int grid, hipStream_t st);
+hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* costs, int64_t* lens,
+                           int32_t* paths, int grid, hipStream_t st);
+hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
+                              hipStream_t st);
+hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st);
+hipError_t launch_diag(const Work& w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
+                       int32_t kstop, bool f32, int grid, double* out, hipStream_t st);
+int pick_dmax(int d);
+}  // namespace dtw
+
+using namespace dtw;
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+struct DevInfo {
+  int cus = 0;
+  int lds_max = 0;
+  int64_t wall_khz = 0;
+  bool attr_set = false;
+};
+
+DevInfo& dev_info() {
+  static DevInfo info[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  DevInfo& I = info[dev];
+  if (I.cus == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) I.cus = v;
+    else I.cus = 256;
+    v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      I.lds_max = std::min(v, 160 * 1024);
+    else
+      I.lds_max = 64 * 1024;
+    v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0) I.wall_khz = v;
+    else I.wall_khz = 100000;
+  }
+  return I;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* s = getenv(name);
+  if (!s || !*s) return dflt;
+  return atoi(s);
+}
+
+// Split levels that can occur: a block that is split has both sides >= m, so
+// K = Mb + Nb - 1 >= 2m - 1, and each child has K' <= min(K - 1, floor(K/2) + 3)
+// (the pivot lies on diagonals kf-2..kf with kf = ceil(K/2)).
+int level_bound(int64_t K0, int m) {
+  int L = 0;
+  int64_t K = K0;
+  while (K >= 2 * (int64_t)m - 1) {
+    ++L;
+    K = std::min(K - 1, K / 2 + 3);
+  }
+  return L;
+}
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+struct Layout {
+  Caps caps{};
+  int lmax = 0;
+  int n_pairs = 0;
+  bool conv = false;
+  int cbytes = 8;  // bytes of the compute type
+  int D = 0;       // padded frame stride of the compute copies
+  Region ctl, pairs, subs0, subs1, piv_key, piv_pos, smin, passes, tickets, hist, chunk_sub, bandF, bandC,
+      bandB, ring, flags, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, nonfinite;
+  size_t total = 0;
+};
+
+void put(Layout& L, Region& r, size_t bytes) {
+  r.off = (L.total + 255) & ~(size_t)255;
+  r.bytes = bytes;
+  L.total = r.off + bytes;
+}
+
+bool valid_precision(int p) { return p == DTW_PREC_FP64 || p == DTW_PREC_FP32; }
+
+// Xrows / Yrows: frames of X / Y that the compute copies must cover.
+Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vector<int64_t>& Ns, int d,
+                   int in_dtype, int precision, int m, int64_t Xrows, int64_t Yrows) {
+  Layout L;
+  L.n_pairs = n_pairs;
+  int64_t K0sum = 0, Msum = 0, Nsum = 0, Mmax = 0, sub = 0, leaf = 0;
+  for (int b = 0; b < n_pairs; ++b) {
+    const int64_t K0 = Ms[b] + Ns[b] - 1;
+    K0sum += K0;
+    Msum += Ms[b];
+    Nsum += Ns[b];
+    Mmax = std::max(Mmax, std::max(Ms[b], Ns[b]));
+    sub += K0 / (2 * (int64_t)m - 2) + 1;
+    leaf += K0 / ((int64_t)m - 2) + 2;
+    L.lmax = std::max(L.lmax, level_bound(K0, m));
+  }
+  Caps& c = L.caps;
+  c.sub = sub + 1;
+  c.cand = std::max<int64_t>(2 * c.sub, n_pairs);
+  c.leaf = leaf + 1;
+  c.band = (3 * K0sum) / 2 + (3 + kBandChunk) * c.sub + 3 * Mmax + kBandChunk;
+  c.chunk = c.band / kBandChunk + c.sub + 1;
+  c.ring = 2 * kRing * (Nsum + c.sub) + kRing * Mmax;
+  c.flag = 2 * kRing * ((Nsum + kChunkCols - 1) / kChunkCols + 2 * c.sub) + kRing * (Mmax / kChunkCols + 2);
+  c.ticket = 2 * ((Msum + kWave - 1) / kWave + 2 * c.sub) + Mmax / kWave + 2;
+  c.hist = Mmax / kWave + 3;
+  c.leaf_words = ((int64_t)m * (K0sum + c.leaf)) / 16 + ((int64_t)m + 4) * c.leaf + 2 * (K0sum + c.leaf) + 16;
+  c.pslots = K0sum;
+  const bool f32 = precision == DTW_PREC_FP32;
+  L.cbytes = f32 ? 4 : 8;
+  L.D = pick_dmax(d);
+  L.conv = (f32 && in_dtype == DTW_F64) || (!f32 && in_dtype == DTW_F32) || (L.D != d);
+  put(L, L.ctl, sizeof(Ctl));
+  put(L, L.pairs, sizeof(PairDesc) * n_pairs);
+  put(L, L.subs0, sizeof(Block) * c.sub);
+  put(L, L.subs1, sizeof(Block) * c.sub);
+  put(L, L.piv_key, 8 * c.sub);
+  put(L, L.piv_pos, 8 * c.sub);
+  put(L, L.smin, 8 * (size_t)n_pairs);
+  put(L, L.passes, sizeof(PassDesc) * 2 * c.sub);
+  put(L, L.tickets, sizeof(int2) * c.ticket);
+  put(L, L.hist, 4 * 4 * c.hist);
+  put(L, L.chunk_sub, 4 * c.chunk);
+  put(L, L.bandF, 8 * c.band);
+  put(L, L.bandC, 8 * c.band);
+  put(L, L.bandB, 8 * c.band);
+  put(L, L.ring, 8 * c.ring);
+  put(L, L.flags, 4 * c.flag);
+  put(L, L.leaves, sizeof(LeafDesc) * c.leaf);
+  put(L, L.leaf_scratch, 4 * c.leaf_words);
+  put(L, L.tpath, 8 * c.pslots);
+  put(L, L.cnt, 4 * c.pslots);
+  put(L, L.poff, 4 * c.pslots);
+  put(L, L.lidx, 4 * c.pslots);
+  put(L, L.leaf_cost, 16 * c.leaf);
+  if (L.conv) {
+    put(L, L.xconv, (size_t)L.cbytes * Xrows * L.D);
+    put(L, L.yconv, (size_t)L.cbytes * Yrows * L.D);
+  }
+  put(L, L.nonfinite, 4);
+  return L;
+}
+
+template <typename T>
+T* at(void* base, const Region& r) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + r.off);
+}
+
+Work make_work(const Layout& L, void* ws, int d, int m, int precision) {
+  Work w{};
+  w.ctl = at<Ctl>(ws, L.ctl);
+  w.pairs = at<PairDesc>(ws, L.pairs);
+  w.n_pairs = L.n_pairs;
+  w.min_block = m;
+  w.d = d;
+  w.precision = precision;
+  w.subs[0] = at<Block>(ws, L.subs0);
+  w.subs[1] = at<Block>(ws, L.subs1);
+  w.piv_key = at<uint64_t>(ws, L.piv_key);
+  w.piv_pos = at<uint64_t>(ws, L.piv_pos);
+  w.smin = at<double>(ws, L.smin);
+  w.passes = at<PassDesc>(ws, L.passes);
+  w.tickets = at<int2>(ws, L.tickets);
+  w.hist = at<int32_t>(ws, L.hist);
+  w.chunk_sub = at<int32_t>(ws, L.chunk_sub);
+  w.bandF = at<double>(ws, L.bandF);
+  w.bandC = at<double>(ws, L.bandC);
+  w.bandB = at<double>(ws, L.bandB);
+  w.ring = at<void>(ws, L.ring);
+  w.flags = at<uint32_t>(ws, L.flags);
+  w.leaves = at<LeafDesc>(ws, L.leaves);
+  w.leaf_scratch = at<uint32_t>(ws, L.leaf_scratch);
+  w.tpath = at<int2>(ws, L.tpath);
+  w.cnt = at<int32_t>(ws, L.cnt);
+  w.leaf_cost = at<double2>(ws, L.leaf_cost);
+  w.caps = L.caps;
+  return w;
+}
+
+#define HIP_TRY(expr)                          \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) {                    \
+      g_last_hip = (int32_t)e_;                \
+      return DTW_ERR_HIP;                      \
+    }                                          \
+  } while (0)
+
+dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
+  dtw_default_opts(out);
+  if (o) *out = *o;
+  if (!valid_precision(out->precision)) return out->precision == DTW_PREC_BF16_COST ? DTW_ERR_UNSUPPORTED : DTW_ERR_INVALID_ARG;
+  if (out->min_block < 3 || out->min_block > kMaxMinBlock) return DTW_ERR_INVALID_ARG;
+  for (int i = 0; i < 5; ++i)
+    if (out->reserved[i] != 0) return DTW_ERR_INVALID_ARG;
+  return DTW_OK;
+}
+
+// Core of dtw_align and dtw_align_batched.
+dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, const int64_t* yo, int d,
+               int in_dtype, const dtw_opts* opts_in, void* ws, size_t ws_bytes, double* costs,
+               int32_t* paths, const int64_t* path_offsets, int64_t path_cap_single, int64_t* lens,
+               dtw_stats* stats, hipStream_t st) {
+  dtw_opts opts;
+  dtw_status rc = read_opts(opts_in, &opts);
+  if (rc != DTW_OK) return rc;
+  if (n_pairs < 1 || !X || !Y || !xo || !yo || !ws || !costs || !paths || !lens) return DTW_ERR_INVALID_ARG;
+  if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
+  if (d < 1) return DTW_ERR_INVALID_ARG;
+  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  std::vector<int64_t> Ms(n_pairs), Ns(n_pairs);
+  std::vector<PairDesc> pd(n_pairs);
+  int64_t pbase = 0, Mtot = 0, Ntot = 0;
+  for (int b = 0; b < n_pairs; ++b) {
+    Ms[b] = xo[b + 1] - xo[b];
+    Ns[b] = yo[b + 1] - yo[b];
+    if (Ms[b] < 1 || Ns[b] < 1 || xo[b] < 0 || yo[b] < 0) return DTW_ERR_INVALID_ARG;
+    if (xo[b + 1] > INT32_MAX || yo[b + 1] > INT32_MAX) return DTW_ERR_INVALID_ARG;
+    const int64_t need = Ms[b] + Ns[b] - 1;
+    int64_t out_off = 0;
+    if (path_offsets) {
+      if (path_offsets[b + 1] - path_offsets[b] < need || path_offsets[b] < 0) return DTW_ERR_CAPACITY;
+      out_off = path_offsets[b];
+    } else if (path_cap_single < need) {
+      return DTW_ERR_CAPACITY;
+    }
+    pd[b] = PairDesc{xo[b], yo[b], Ms[b], Ns[b], pbase, out_off};
+    pbase += need;
+    Mtot = std::max(Mtot, xo[b + 1]);
+    Ntot = std::max(Ntot, yo[b + 1]);
+  }
+  const int m = opts.min_block;
+  Layout L = plan_layout(n_pairs, Ms, Ns, d, in_dtype, opts.precision, m, Mtot, Ntot);
+  if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
+  const bool f32 = opts.precision == DTW_PREC_FP32;
+  const int in_f64 = in_dtype == DTW_F64;
+  DevInfo& I = dev_info();
+  if (!I.attr_set) {
+    HIP_TRY(set_leaf_lds_limit((size_t)I.lds_max));
+    I.attr_set = true;
+  }
+
+  if (opts.validate_finite) {
+    int32_t* flag = at<int32_t>(ws, L.nonfinite);
+    HIP_TRY(hipMemsetAsync(flag, 0, 4, st));
+    HIP_TRY(launch_nonfinite(X, in_f64, Mtot * d, flag, st));
+    HIP_TRY(launch_nonfinite(Y, in_f64, Ntot * d, flag, st));
+    int32_t h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h) return DTW_ERR_NONFINITE;
+  }
+
+  Work w = make_work(L, ws, d, m, opts.precision);
+  w.X = X;
+  w.Y = Y;
+  // one flag wait may last at most DTW_SPIN_LIMIT_MS (default 20 s)
+  w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
+  if (L.conv) {
+    void* xc = at<void>(ws, L.xconv);
+    void* yc = at<void>(ws, L.yconv);
+    HIP_TRY(launch_pad_convert(X, in_f64, xc, !f32, Mtot, d, L.D, st));
+    HIP_TRY(launch_pad_convert(Y, in_f64, yc, !f32, Ntot, d, L.D, st));
+    w.X = xc;
+    w.Y = yc;
+  }
+  HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_init(w, st));
+
+  const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WAVES_PER_CU", 4));
+  const int comb_grid = I.cus * 4;
+  const size_t cring_bytes = (size_t)L.cbytes * (kWave * kWave + kWave);
+  const size_t lds_bytes = (size_t)I.lds_max;
+  const int64_t lds_leaf_bytes = (int64_t)lds_bytes - (int64_t)cring_bytes;
+  for (int lvl = 0; lvl <= L.lmax; ++lvl) {
+    const int final_level = (lvl == L.lmax) ? 1 : 0;
+    HIP_TRY(launch_plan(w, lvl, final_level, lds_leaf_bytes, st));
+    if (final_level) break;
+    HIP_TRY(launch_pass(w, lvl, f32, pass_grid, st));
+    HIP_TRY(launch_combine(w, comb_grid, st));
+  }
+  HIP_TRY(launch_leaf(w, f32, I.cus, lds_bytes, lds_leaf_bytes, X, Y, in_f64, st));
+  HIP_TRY(launch_assemble(w, at<int32_t>(ws, L.poff), at<int32_t>(ws, L.lidx), costs, lens, paths, I.cus * 2, st));
+
+  if (stats) {
+    Ctl c{};
+    double smin = 0.0;
+    int64_t len = 0;
+    HIP_TRY(hipMemcpyAsync(&c, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&smin, w.smin, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&len, lens, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    memset(stats, 0, sizeof(*stats));
+    stats->s_min = smin;
+    stats->cells_processed = c.cells;
+    stats->path_len = len;
+    stats->workspace_bytes = (int64_t)L.total;
+    stats->levels = c.levels_run;
+    stats->leaves = c.n_leaf;
+    stats->device_error = c.error;
+    if (c.error) return DTW_ERR_INTERNAL;
+  }
+  return DTW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dtw_default_opts(dtw_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->precision = DTW_PREC_FP64;
+  o->min_block = 500;
+  o->validate_finite = 0;
+}
+
+const char* dtw_status_string(int32_t s) {
+  switch (s) {
+    case DTW_OK: return "ok";
+    case DTW_ERR_INVALID_ARG: return "invalid argument";
+    case DTW_ERR_CAPACITY: return "path capacity too small";
+    case DTW_ERR_WORKSPACE: return "workspace too small";
+    case DTW_ERR_NONFINITE: return "non-finite input";
+    case DTW_ERR_HIP: return "HIP runtime error";
+    case DTW_ERR_BUSY: return "not ready";
+    case DTW_ERR_NOT_FOUND: return "unknown ticket";
+    case DTW_ERR_UNSUPPORTED: return "unsupported dimension or mode";
+    case DTW_ERR_INTERNAL: return "device-side consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+int32_t dtw_last_hip_error(void) { return g_last_hip; }
+
+dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype, const dtw_opts* opts_in,
+                              size_t* bytes) {
+  dtw_opts opts;
+  dtw_status rc = read_opts(opts_in, &opts);
+  if (rc != DTW_OK) return rc;
+  if (!bytes || M < 1 || N < 1 || d < 1 || M > INT32_MAX || N > INT32_MAX) return DTW_ERR_INVALID_ARG;
+  if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
+  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  std::vector<int64_t> Ms{M}, Ns{N};
+  *bytes = plan_layout(1, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, M, N).total;
+  return DTW_OK;
+}
+
+dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t d, int32_t in_dtype,
+                     const dtw_opts* opts, void* workspace, size_t ws_bytes, double* cost_out,
+                     int32_t* path_out, int64_t path_cap, int64_t* path_len_out, dtw_stats* stats,
+                     void* stream) {
+  if (M < 1 || N < 1) return DTW_ERR_INVALID_ARG;
+  const int64_t xo[2] = {0, M}, yo[2] = {0, N};
+  return run(1, X, Y, xo, yo, d, in_dtype, opts, workspace, ws_bytes, cost_out, path_out, nullptr, path_cap,
+             path_len_out, stats, (hipStream_t)stream);
+}
+
+dtw_status dtw_workspace_size_batched(int32_t B, const int64_t* x_offsets, const int64_t* y_offsets, int32_t d,
+                                      int32_t in_dtype, const dtw_opts* opts_in, size_t* bytes) {
+  dtw_opts opts;
+  dtw_status rc = read_opts(opts_in, &opts);
+  if (rc != DTW_OK) return rc;
+  if (!bytes || B < 1 || !x_offsets || !y_offsets || d < 1) return DTW_ERR_INVALID_ARG;
+  if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
+  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  std::vector<int64_t> Ms(B), Ns(B);
+  int64_t Xrows = 0, Yrows = 0;
+  for (int b = 0; b < B; ++b) {
+    Ms[b] = x_offsets[b + 1] - x_offsets[b];
+    Ns[b] = y_offsets[b + 1] - y_offsets[b];
+    if (Ms[b] < 1 || Ns[b] < 1 || x_offsets[b] < 0 || y_offsets[b] < 0) return DTW_ERR_INVALID_ARG;
+    Xrows = std::max(Xrows, x_offsets[b + 1]);
+    Yrows = std::max(Yrows, y_offsets[b + 1]);
+  }
+  *bytes = plan_layout(B, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, Xrows, Yrows).total;
+  return DTW_OK;
+}
+
+dtw_status dtw_align_batched(int32_t B, const void* X_packed, const int64_t* x_offsets, const void* Y_packed,
+                             const int64_t* y_offsets, int32_t d, int32_t in_dtype, const dtw_opts* opts,
+                             void* workspace, size_t ws_bytes, double* costs_out, int32_t* paths_out,
+                             const int64_t* path_offsets, int64_t* path_lens_out, dtw_stats* stats,
+                             void* stream) {
+  if (B < 1 || !x_offsets || !y_offsets || !path_offsets) return DTW_ERR_INVALID_ARG;
+  return run(B, X_packed, Y_packed, x_offsets, y_offsets, d, in_dtype, opts, workspace, ws_bytes, costs_out,
+             paths_out, path_offsets, 0, path_lens_out, stats, (hipStream_t)stream);
+}
+
+dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype, int64_t i0, int64_t j0, int64_t i1,
+                    int64_t j1, int32_t reverse, int64_t kstop, int32_t precision, void* workspace,
+                    size_t ws_bytes, double* out, void* stream) {
+  if (!X || !Y || !workspace || !out || d < 1 || i0 < 0 || j0 < 0 || i1 < i0 || j1 < j0) return DTW_ERR_INVALID_ARG;
+  if (i1 > INT32_MAX || j1 > INT32_MAX) return DTW_ERR_INVALID_ARG;
+  if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
+  if (!valid_precision(precision)) return DTW_ERR_UNSUPPORTED;
+  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  const int64_t Mb = i1 - i0 + 1, Nb = j1 - j0 + 1;
+  if (kstop < 2 || kstop > Mb + Nb - 2) return DTW_ERR_INVALID_ARG;
+  const bool f32 = precision == DTW_PREC_FP32;
+  const int in_f64 = in_dtype == DTW_F64;
+  std::vector<int64_t> Ms{Mb}, Ns{Nb};
+  // same layout as dtw_workspace_size(i1+1, j1+1, d, in_dtype, opts with this precision)
+  Layout L = plan_layout(1, Ms, Ns, d, in_dtype, precision, 500, i1 + 1, j1 + 1);
+  {
+    std::vector<int64_t> Mf{i1 + 1}, Nf{j1 + 1};
+    Layout Lf = plan_layout(1, Mf, Nf, d, in_dtype, precision, 500, i1 + 1, j1 + 1);
+    if (Lf.total > L.total) L = Lf;
+  }
+  if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  Work w = make_work(L, workspace, d, 500, precision);
+  w.X = X;
+  w.Y = Y;
+  if (L.conv) {
+    void* xc = at<void>(workspace, L.xconv);
+    void* yc = at<void>(workspace, L.yconv);
+    HIP_TRY(launch_pad_convert(X, in_f64, xc, !f32, i1 + 1, d, L.D, st));
+    HIP_TRY(launch_pad_convert(Y, in_f64, yc, !f32, j1 + 1, d, L.D, st));
+    w.X = xc;
+    w.Y = yc;
+  }
+  w.bandC = nullptr;
+  DevInfo& I = dev_info();
+  w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
+  HIP_TRY(launch_diag(w, (int32_t)i0, (int32_t)j0, (int32_t)i1, (int32_t)j1, reverse ? 1 : 0, (int32_t)kstop, f32,
+                      I.cus * 4, out, st));
+  return DTW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Device helpers shared by the wave kernels (dtw_wave.hip) and the
+// orchestration kernels (dtw_plan.hip).
+#pragma once
+
+#include "dtw_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace dtw {
+
+// Number of cells (a,b) of an Mb x Nb block with a + b <= k.
+__device__ __forceinline__ int64_t cells_upto(int64_t Mb, int64_t Nb, int64_t k) {
+  const int64_t A = min(Mb - 1, k);
+  if (A < 0) return 0;
+  const int64_t t = k - (Nb - 1);
+  const int64_t nfull = max((int64_t)0, min(A, t) + 1);
+  int64_t cells = nfull * Nb;
+  const int64_t lo = nfull, hi = A;
+  if (hi >= lo) cells += (hi - lo + 1) * (2 * k - lo - hi + 2) / 2;
+  return cells;
+}
+
+__device__ __forceinline__ void set_error(Ctl* ctl, int32_t code) { atomicCAS(&ctl->error, 0, code); }
+
+// Error-free transformation a + b = s + e (Knuth's TwoSum).
+__device__ __forceinline__ double2 two_sum_acc(double2 acc, double v) {
+  const double s = acc.x + v;
+  const double bp = s - acc.x;
+  const double e = (acc.x - (s - bp)) + (v - bp);
+  return make_double2(s, acc.y + e);
+}
+__device__ __forceinline__ double2 dd_add(double2 a, double2 b) {
+  double2 r = two_sum_acc(a, b.x);
+  r.y += b.y;
+  return r;
+}
+
+// ----------------------------------------------------------------- block scan
+
+__device__ int64_t block_excl_scan(int64_t v, int64_t* tmp, int64_t* total) {
+  const int t = threadIdx.x, n = blockDim.x;
+  tmp[t] = v;
+  __syncthreads();
+  for (int off = 1; off < n; off <<= 1) {
+    const int64_t u = (t >= off) ? tmp[t - off] : 0;
+    __syncthreads();
+    tmp[t] += u;
+    __syncthreads();
+  }
+  const int64_t incl = tmp[t];
+  *total = tmp[n - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+}  // namespace dtw

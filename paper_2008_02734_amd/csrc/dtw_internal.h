@@ -1,0 +1,137 @@
+// Internal layout shared by the HIP kernels (dtw_kernels.hip) and the host
+// runtime (dtw_api.hip).  Everything here lives in the caller's workspace.
+//
+// Coordinates: a block is a sub-rectangle of one pair's DP grid, stored with
+// GLOBAL frame indices into the packed X / Y arrays (i into X, j into Y), so
+// the sweep kernels never need to know which pair a block belongs to; only
+// path assembly subtracts the pair's frame offsets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dtw {
+
+constexpr int kWave = 64;        // gfx950 wavefront width; one lane per DP row
+constexpr int kChunkCols = 32;   // boundary-row columns published per flag
+constexpr int kRing = 2;         // boundary-row slots per sweep (see pass kernel)
+constexpr int kBandChunk = 256;  // band cells per split-cost work item
+constexpr int kMaxMinBlock = 1024;
+constexpr int kLeafThreads = 64;
+
+struct Block {
+  int32_t i0, j0, i1, j1;  // inclusive, global frame indices
+  int32_t pair;
+  int32_t pad;
+};
+
+struct PairDesc {
+  int64_t x_off, y_off;  // first frame of the pair in X / Y
+  int64_t M, N;
+  int64_t pbase;         // first slot of the pair in the diagonal-indexed path scratch
+  int64_t out_off;       // first pair of the pair's path in the caller's path buffer
+};
+
+// One half sweep (forward or backward) of one block.
+struct PassDesc {
+  int32_t i0, j0, i1, j1;
+  int32_t Mb, Nb;
+  int32_t dir;        // 0: from (i0,j0); 1: on the reversed series, from (i1,j1)
+  int32_t kstop;      // last local diagonal of this sweep
+  int32_t kf;         // forward stop of the block: band = forward diagonals kf-2..kf
+  int32_t n_rows;     // local rows touched: min(Mb-1, kstop) + 1
+  int32_t n_stripes;  // ceil(n_rows / 64)
+  int32_t L;          // band stride: min(Mb, Nb) >= longest band diagonal
+  int32_t raw;        // 1: band written in the sweep's own coordinates (dtw_diag)
+  int32_t pad;
+  int64_t band_off;   // element offset of the block's 3*L band slots
+  int64_t ring_off;   // element offset of the kRing boundary rows (kRing*Nb)
+  int64_t flag_off;   // offset of the chunk flags (kRing*ceil(Nb/kChunkCols))
+};
+
+struct LeafDesc {
+  int32_t i0, j0, i1, j1;  // global frame indices
+  int32_t pair;
+  int32_t first;           // 1 when the leaf starts at the pair's (0,0)
+  int64_t scratch_off;     // word offset in leaf scratch, or -1 when it fits in LDS
+};
+
+// Device control block.
+struct Ctl {
+  int32_t n_sub;        // non-leaf blocks at the current level
+  int32_t n_pass;       // 2 * n_sub
+  int32_t n_tickets;    // stripes of the current level
+  int32_t ticket;       // pass-kernel dequeue counter
+  int32_t n_chunks;     // band work items of the current level
+  int32_t n_leaf;       // leaves emitted so far
+  int32_t levels_run;   // levels that had at least one split
+  int32_t error;        // first device-side error code, 0 if none
+  int32_t leaf_ticket;  // leaf-kernel dequeue counter
+  int32_t max_stripes;  // largest n_stripes of the current level
+  int64_t leaf_words;   // leaf scratch words handed out
+  int64_t cells;        // cells evaluated (sweeps + leaf tables)
+};
+
+enum DeviceError : int32_t {
+  kErrSubCap = 1,
+  kErrLeafCap = 2,
+  kErrBandCap = 3,
+  kErrRingCap = 4,
+  kErrTicketCap = 5,
+  kErrLeafScratch = 6,
+  kErrNotLeafAtEnd = 7,
+  kErrNoPivot = 8,
+  kErrSpinTimeout = 9,
+  kErrBadPivot = 10,
+  kErrBadLeaf = 11,
+};
+
+// Capacities chosen by the host planner (see plan_workspace in dtw_api.hip).
+struct Caps {
+  int64_t sub;       // blocks per level
+  int64_t cand;      // candidates per level (2 * sub, at least n_pairs)
+  int64_t leaf;      // leaves over all levels
+  int64_t band;      // band slots per level
+  int64_t ring;      // boundary-row elements per level
+  int64_t flag;      // flags per level
+  int64_t ticket;    // stripes per level
+  int64_t chunk;     // band work items per level
+  int64_t hist;      // histogram bins (max stripes + 1)
+  int64_t leaf_words;// global leaf scratch words
+  int64_t pslots;    // diagonal-indexed path scratch slots (sum of M+N-1)
+};
+
+// Device pointers carved out of the caller's workspace; passed by value.
+struct Work {
+  Ctl* ctl;
+  const PairDesc* pairs;
+  int32_t n_pairs;
+  int32_t min_block;
+  int32_t d;
+  int32_t precision;
+  const void* X;        // compute-type copies (or the caller's arrays)
+  const void* Y;
+  Block* subs[2];
+  uint64_t* piv_key;    // per block of the current level: bits of min split cost
+  uint64_t* piv_pos;    // per block: (q << 32) | local row of the argmin
+  double* smin;         // per pair: split cost at the top level
+  PassDesc* passes;
+  int2* tickets;        // (pass, stripe)
+  int32_t* pass_rank;   // scratch for the ticket ordering
+  int32_t* hist;        // scratch histogram of stripe counts
+  int32_t* chunk_sub;   // band work item -> block
+  double* bandF;        // forward accumulated cost on the band (S after combine)
+  double* bandC;        // frame cost on the band
+  double* bandB;        // backward accumulated cost on the band
+  void* ring;           // boundary rows, compute type
+  uint32_t* flags;
+  LeafDesc* leaves;
+  uint32_t* leaf_scratch;
+  int2* tpath;          // diagonal-indexed path scratch
+  int32_t* cnt;         // cells written by the leaf that ends on this diagonal
+  double2* leaf_cost;   // per leaf (hi, lo) compensated sum
+  uint64_t spin_ticks;  // bound on one flag wait, device wall-clock ticks
+  Caps caps;
+};
+
+}  // namespace dtw

@@ -1,0 +1,511 @@
+// HIP orchestration kernels for gfx950 (arXiv 2008.02734, Algorithm 2):
+//
+//   plan_kernel      one level of the recursion: children of the previous
+//                    level's pivots, leaf cutoff, sweep descriptors and the
+//                    stripe queue;
+//   combine_*        split cost S = (F + B) - C on the three central diagonals
+//                    (Lemma 2) and the argmin pivot (smallest S, then smallest
+//                    diagonal, then smallest row);
+//   scan/copy        concatenation of the leaf paths (the pivot is not
+//                    repeated) and the FP64 path cost of Eq. 1;
+//   init, pad_convert, nonfinite, diag setup/out: bookkeeping.
+#include "dtw_common.h"
+
+namespace dtw {
+
+// dtw_diag: the pass kernel runs one sweep in raw mode (band written in the
+// sweep's own local coordinates, stride Mb, at q*Mb + (a - lo)); this kernel
+// moves the values to q*Mb + a and fills cells outside the block with NaN.
+__global__ void diag_out_kernel(Work w, double* out) {
+  const PassDesc P = w.passes[0];
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < 3 * (int64_t)P.Mb;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(u / P.Mb), a = (int)(u % P.Mb);
+    const int k = P.kstop - 2 + q;
+    const int b = k - a;
+    double v = __builtin_nan("");
+    if (b >= 0 && b < P.Nb) {
+      const int lo = max(0, k - (P.Nb - 1));
+      v = w.bandF[(int64_t)q * P.L + (a - lo)];
+    }
+    out[u] = v;
+  }
+}
+
+// ----------------------------------------------------------------- init
+
+__global__ void init_kernel(Work w) {
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  if (tid == 0) {
+    Ctl c = {};
+    *w.ctl = c;
+  }
+  for (int64_t u = tid; u < w.caps.flag; u += nt) w.flags[u] = 0u;
+  for (int64_t u = tid; u < w.caps.pslots; u += nt) w.cnt[u] = 0;
+  for (int64_t u = tid; u < w.n_pairs; u += nt) w.smin[u] = __builtin_nan("");
+}
+
+// ----------------------------------------------------------------- plan
+
+// One level of Algorithm 2, run by a single workgroup of 1024 threads.
+//  - candidates: the roots (level 0) or both children of every split of the
+//    previous level, read from its pivot (both children contain the pivot);
+//  - a candidate whose shorter side is below m becomes a leaf;
+//  - every other candidate gets a forward sweep to kf = ceil(K/2) and a
+//    backward sweep to kb = kf + [K even] (K = Mb + Nb - 1), band slots, a
+//    boundary-row ring and flags, and its stripes enter the level's queue in
+//    stripe-major order.
+__global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final_level,
+                                                    int64_t lds_leaf_bytes) {
+  __shared__ int64_t tmp[1024];
+  __shared__ int32_t s_max_stripes;
+  Ctl* ctl = w.ctl;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n_prev = (level == 0) ? 0 : ctl->n_sub;
+  const int64_t n_cand = (level == 0) ? (int64_t)w.n_pairs : 2 * (int64_t)n_prev;
+  const Block* prev = w.subs[(level + 1) & 1];
+  Block* cur = w.subs[level & 1];
+  const int m = w.min_block;
+
+  if (level == 1) {
+    for (int s = tid; s < n_prev; s += nt) w.smin[prev[s].pair] = __longlong_as_double((long long)w.piv_key[s]);
+  }
+  if (tid == 0) s_max_stripes = 0;
+  __syncthreads();
+
+  int64_t leaf_base = ctl->n_leaf, sub_base = 0, words_base = ctl->leaf_words;
+  for (int64_t tile = 0; tile < n_cand; tile += nt) {
+    const int64_t ci = tile + tid;
+    const bool valid = ci < n_cand;
+    Block c = {0, 0, 0, 0, 0, 0};
+    bool is_leaf = false;
+    int64_t words = 0;
+    if (valid) {
+      if (level == 0) {
+        const PairDesc pd = w.pairs[ci];
+        c = Block{(int32_t)pd.x_off, (int32_t)pd.y_off, (int32_t)(pd.x_off + pd.M - 1),
+                  (int32_t)(pd.y_off + pd.N - 1), (int32_t)ci, 0};
+      } else {
+        const int s = (int)(ci >> 1);
+        const Block pb = prev[s];
+        const uint64_t pos = w.piv_pos[s];
+        const int Mb = pb.i1 - pb.i0 + 1, Nb = pb.j1 - pb.j0 + 1;
+        const int K = Mb + Nb - 1, kf = (K + 1) / 2;
+        int q = 0, ar = 0;
+        if (pos == ~0ull) {
+          set_error(ctl, kErrNoPivot);
+          ar = max(0, kf - (Nb - 1));
+        } else {
+          q = (int)(pos >> 32);
+          ar = (int)(pos & 0xffffffffu);
+        }
+        const int k = kf - 2 + q;
+        int pi = pb.i0 + ar, pj = pb.j0 + (k - ar);
+        if (q < 0 || q > 2 || pi < pb.i0 || pi > pb.i1 || pj < pb.j0 || pj > pb.j1) {
+          // a pivot outside its block would make an empty child
+          set_error(ctl, kErrBadPivot);
+          pi = pb.i0 + (Mb - 1) / 2;
+          pj = pb.j0 + (Nb - 1) / 2;
+        }
+        c = ((ci & 1) == 0) ? Block{pb.i0, pb.j0, pi, pj, pb.pair, 0}
+                            : Block{pi, pj, pb.i1, pb.j1, pb.pair, 0};
+      }
+      const int64_t Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
+      is_leaf = (Mb < m) || (Nb < m);
+      if (is_leaf) {
+        const int64_t R = min(Mb, Nb), Cc = max(Mb, Nb);
+        const int64_t bpw = ((R * ((Cc + 15) / 16)) + 1) & ~(int64_t)1;
+        const int64_t need = bpw + 2 * Cc;
+        if (need * 4 > lds_leaf_bytes) words = need;
+      }
+    }
+    int64_t tot_leaf, tot_sub, tot_words;
+    const int64_t lrank = block_excl_scan(valid && is_leaf ? 1 : 0, tmp, &tot_leaf);
+    const int64_t srank = block_excl_scan(valid && !is_leaf ? 1 : 0, tmp, &tot_sub);
+    const int64_t wrank = block_excl_scan(words, tmp, &tot_words);
+    if (valid && is_leaf) {
+      const int64_t li = leaf_base + lrank;
+      if (li < w.caps.leaf) {
+        const PairDesc pd = w.pairs[c.pair];
+        LeafDesc L;
+        L.i0 = c.i0; L.j0 = c.j0; L.i1 = c.i1; L.j1 = c.j1; L.pair = c.pair;
+        L.first = (c.i0 == pd.x_off && c.j0 == pd.y_off) ? 1 : 0;
+        L.scratch_off = words ? words_base + wrank : -1;
+        w.leaves[li] = L;
+      } else {
+        set_error(ctl, kErrLeafCap);
+      }
+    }
+    if (valid && !is_leaf) {
+      const int64_t si = sub_base + srank;
+      if (si < w.caps.sub) cur[si] = c;
+      else set_error(ctl, kErrSubCap);
+    }
+    leaf_base += tot_leaf;
+    sub_base += tot_sub;
+    words_base += tot_words;
+  }
+  // cur[] was written by rank, i.e. by other threads than the ones that read
+  // it below: every write must be visible before the descriptor loop.
+  __syncthreads();
+  if (words_base > w.caps.leaf_words && tid == 0) set_error(ctl, kErrLeafScratch);
+  const int n_sub = (int)min(sub_base, w.caps.sub);
+  if (final_level && n_sub > 0 && tid == 0) set_error(ctl, kErrNotLeafAtEnd);
+  const int n_sub_run = final_level ? 0 : n_sub;
+
+  // sweep descriptors, band slots, rings, flags
+  int64_t chunk_base = 0, ring_base = 0, flag_base = 0;
+  for (int64_t tile = 0; tile < n_sub_run; tile += nt) {
+    const int64_t s = tile + tid;
+    const bool valid = s < n_sub_run;
+    int64_t nchunk = 0, ring_e = 0, flag_e = 0;
+    Block c = {0, 0, 0, 0, 0, 0};
+    if (valid) {
+      c = cur[s];
+      const int64_t Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
+      const int64_t L = min(Mb, Nb);
+      nchunk = (3 * L + kBandChunk - 1) / kBandChunk;
+      ring_e = 2 * kRing * Nb;  // forward sweep, then backward sweep
+      flag_e = 2 * kRing * ((Nb + kChunkCols - 1) / kChunkCols);
+    }
+    int64_t tc, tr, tf;
+    const int64_t cb = block_excl_scan(nchunk, tmp, &tc);
+    const int64_t rb = block_excl_scan(ring_e, tmp, &tr);
+    const int64_t fb = block_excl_scan(flag_e, tmp, &tf);
+    if (valid) {
+      const int Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
+      const int K = Mb + Nb - 1;
+      const int kf = (K + 1) / 2;
+      const int kb = kf + ((K % 2) == 0 ? 1 : 0);
+      PassDesc P;
+      P.raw = 0;
+      P.i0 = c.i0; P.j0 = c.j0; P.i1 = c.i1; P.j1 = c.j1;
+      P.Mb = Mb; P.Nb = Nb;
+      P.kf = kf;
+      P.L = min(Mb, Nb);
+      P.band_off = (chunk_base + cb) * kBandChunk;
+      P.ring_off = ring_base + rb;
+      P.flag_off = flag_base + fb;
+      const bool ok = (P.band_off + nchunk * kBandChunk <= w.caps.band) &&
+                      (P.ring_off + ring_e <= w.caps.ring) && (P.flag_off + flag_e <= w.caps.flag) &&
+                      (chunk_base + cb + nchunk <= w.caps.chunk);
+      if (!ok) set_error(ctl, kErrBandCap);
+      const int64_t ring0 = P.ring_off, flag0 = P.flag_off;
+      for (int dir = 0; dir < 2; ++dir) {
+        P.dir = dir;
+        P.ring_off = ring0 + dir * (int64_t)kRing * Nb;
+        P.flag_off = flag0 + dir * (int64_t)kRing * ((Nb + kChunkCols - 1) / kChunkCols);
+        P.kstop = dir ? kb : kf;
+        P.n_rows = min(Mb - 1, P.kstop) + 1;
+        P.n_stripes = ok ? (P.n_rows + kWave - 1) / kWave : 0;
+        w.passes[2 * s + dir] = P;
+        atomicMax(&s_max_stripes, P.n_stripes);
+      }
+      if (ok)
+        for (int64_t q = 0; q < nchunk; ++q) w.chunk_sub[chunk_base + cb + q] = (int32_t)s;
+      w.piv_key[s] = ~0ull;
+      w.piv_pos[s] = ~0ull;
+      atomicAdd((unsigned long long*)&ctl->cells,
+                (unsigned long long)(cells_upto(Mb, Nb, kf) + cells_upto(Mb, Nb, kb)));
+    }
+    chunk_base += tc;
+    ring_base += tr;
+    flag_base += tf;
+  }
+  __syncthreads();
+
+  // stripe queue in stripe-major order: passes sorted by stripe count
+  // (descending); stripe s of the pass at sorted position r gets ticket
+  // start(s) + r, start(s) = sum over s' < s of #{passes with > s' stripes}.
+  const int n_pass = 2 * n_sub_run;
+  const int max_s = s_max_stripes;
+  int32_t* hist = w.hist;                   // [0, max_s]: passes with exactly v stripes
+  int32_t* gt = w.hist + w.caps.hist;       // #passes with more than v stripes
+  int32_t* start = w.hist + 2 * w.caps.hist;
+  int32_t* eqc = w.hist + 3 * w.caps.hist;
+  const bool hist_ok = max_s < w.caps.hist;
+  if (!hist_ok && tid == 0) set_error(ctl, kErrTicketCap);
+  if (hist_ok) {
+    for (int v = tid; v <= max_s; v += nt) { hist[v] = 0; eqc[v] = 0; }
+    __syncthreads();
+    for (int p = tid; p < n_pass; p += nt) atomicAdd(&hist[w.passes[p].n_stripes], 1);
+    __syncthreads();
+    // gt[v] = sum_{u > v} hist[u];  start[s] = sum_{s' < s} gt[s']
+    int64_t carry = 0;
+    for (int64_t tile = 0; tile <= max_s; tile += nt) {
+      const int64_t v = max_s - (tile + tid);  // descending order
+      const int64_t hv = (v >= 0) ? hist[v] : 0;
+      int64_t tot;
+      const int64_t ex = block_excl_scan(hv, tmp, &tot);
+      if (v >= 0) gt[v] = (int32_t)(carry + ex);
+      carry += tot;
+    }
+    __syncthreads();
+    carry = 0;
+    for (int64_t tile = 0; tile <= max_s; tile += nt) {
+      const int64_t v = tile + tid;
+      const int64_t g = (v <= max_s) ? gt[v] : 0;
+      int64_t tot;
+      const int64_t ex = block_excl_scan(g, tmp, &tot);
+      if (v <= max_s) start[v] = (int32_t)(carry + ex);
+      carry += tot;
+    }
+    const int64_t n_tickets = carry;
+    __syncthreads();
+    if (n_tickets > w.caps.ticket) {
+      if (tid == 0) set_error(ctl, kErrTicketCap);
+    } else {
+      for (int p = tid; p < n_pass; p += nt) {
+        const int ns = w.passes[p].n_stripes;
+        const int r = gt[ns] + atomicAdd(&eqc[ns], 1);
+        for (int s = 0; s < ns; ++s) w.tickets[start[s] + r] = make_int2(p, s);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ctl->n_sub = n_sub;
+      ctl->n_pass = n_pass;
+      ctl->n_tickets = (n_tickets > w.caps.ticket) ? 0 : (int32_t)n_tickets;
+      ctl->ticket = 0;
+      ctl->n_chunks = (int32_t)chunk_base;
+      ctl->n_leaf = (int32_t)min(leaf_base, w.caps.leaf);
+      ctl->leaf_words = words_base;
+      if (n_sub_run > 0) ctl->levels_run += 1;
+    }
+  } else if (tid == 0) {
+    ctl->n_sub = 0;
+    ctl->n_pass = 0;
+    ctl->n_tickets = 0;
+    ctl->n_chunks = 0;
+    ctl->n_leaf = (int32_t)min(leaf_base, w.caps.leaf);
+    ctl->leaf_words = words_base;
+  }
+}
+
+// ----------------------------------------------------------------- split cost
+
+// S = (F + B) - C on every band slot (stored over F), and the smallest S of
+// each block as the bits of a non-negative double (monotone as uint64).
+__global__ __launch_bounds__(kBandChunk) void combine_min_kernel(Work w) {
+  __shared__ uint64_t red[kBandChunk];
+  const int n_chunks = w.ctl->n_chunks;
+  for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    const int s = w.chunk_sub[c];
+    const PassDesc P = w.passes[2 * s];
+    const int64_t slot = (int64_t)c * kBandChunk + threadIdx.x - P.band_off;
+    uint64_t key = ~0ull;
+    if (slot < 3 * (int64_t)P.L) {
+      const int q = (int)(slot / P.L), idx = (int)(slot % P.L);
+      const int k = P.kf - 2 + q;
+      const int lo = max(0, k - (P.Nb - 1)), hi = min(P.Mb - 1, k);
+      const int64_t g = P.band_off + slot;
+      if (idx <= hi - lo) {
+        const double S = (w.bandF[g] + w.bandB[g]) - w.bandC[g];
+        w.bandF[g] = S;
+        key = (uint64_t)__double_as_longlong(S);
+      }
+    }
+    red[threadIdx.x] = key;
+    __syncthreads();
+    for (int off = kBandChunk / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != ~0ull) atomicMin((unsigned long long*)&w.piv_key[s], (unsigned long long)red[0]);
+    __syncthreads();
+  }
+}
+
+// Among the slots that reach the block's minimum, the smallest (diagonal,
+// row), packed as (q << 32) | row with q = diagonal - (kf - 2).
+__global__ __launch_bounds__(kBandChunk) void combine_argmin_kernel(Work w) {
+  __shared__ uint64_t red[kBandChunk];
+  const int n_chunks = w.ctl->n_chunks;
+  for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    const int s = w.chunk_sub[c];
+    const PassDesc P = w.passes[2 * s];
+    const uint64_t target = w.piv_key[s];
+    const int64_t slot = (int64_t)c * kBandChunk + threadIdx.x - P.band_off;
+    uint64_t key = ~0ull;
+    if (slot < 3 * (int64_t)P.L) {
+      const int q = (int)(slot / P.L), idx = (int)(slot % P.L);
+      const int k = P.kf - 2 + q;
+      const int lo = max(0, k - (P.Nb - 1)), hi = min(P.Mb - 1, k);
+      const int64_t g = P.band_off + slot;
+      if (idx <= hi - lo && (uint64_t)__double_as_longlong(w.bandF[g]) == target)
+        key = ((uint64_t)q << 32) | (uint64_t)(lo + idx);
+    }
+    red[threadIdx.x] = key;
+    __syncthreads();
+    for (int off = kBandChunk / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != ~0ull) atomicMin((unsigned long long*)&w.piv_pos[s], (unsigned long long)red[0]);
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- assembly
+
+// Per pair: exclusive scan of the per-diagonal cell counts (segments are in
+// path order because their end diagonals increase along the path) and the
+// compensated sum of the leaf costs in path order.
+__global__ __launch_bounds__(1024) void scan_kernel(Work w, int32_t* poff, int32_t* lidx,
+                                                     double* costs_out, int64_t* lens_out) {
+  __shared__ int64_t tmp[1024];
+  __shared__ double2 red[1024];
+  const int p = blockIdx.x;
+  const PairDesc pd = w.pairs[p];
+  const int64_t n = pd.M + pd.N - 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t per = (n + nt - 1) / nt;
+  const int64_t lo = min(n, tid * per), hi = min(n, lo + per);
+  int64_t local = 0;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t e = lo; e < hi; ++e) {
+    const int c = w.cnt[pd.pbase + e];
+    local += c;
+    if (c > 0) acc = dd_add(acc, w.leaf_cost[lidx[pd.pbase + e]]);
+  }
+  int64_t total;
+  int64_t run = block_excl_scan(local, tmp, &total);
+  for (int64_t e = lo; e < hi; ++e) {
+    poff[pd.pbase + e] = (int32_t)run;
+    run += w.cnt[pd.pbase + e];
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int off = nt / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] = dd_add(red[tid], red[tid + off]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    costs_out[p] = red[0].x + red[0].y;
+    lens_out[p] = total;
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(Work w, const int32_t* poff, int32_t* paths_out) {
+  const int n_leaf = w.ctl->n_leaf;
+  for (int l = blockIdx.x; l < n_leaf; l += gridDim.x) {
+    const LeafDesc Lf = w.leaves[l];
+    const PairDesc pd = w.pairs[Lf.pair];
+    const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
+    const int64_t slot_end = pd.pbase + e;
+    const int c = w.cnt[slot_end];
+    const int64_t o = pd.out_off + poff[slot_end];
+    int2* out = reinterpret_cast<int2*>(paths_out);
+    for (int q = threadIdx.x; q < c; q += blockDim.x) out[o + q] = w.tpath[slot_end - c + 1 + q];
+  }
+}
+
+// leaf index by end diagonal, for the cost sum in path order
+__global__ void leaf_index_kernel(Work w, int32_t* lidx) {
+  const int n_leaf = w.ctl->n_leaf;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < n_leaf; l += gridDim.x * blockDim.x) {
+    const LeafDesc Lf = w.leaves[l];
+    const PairDesc pd = w.pairs[Lf.pair];
+    lidx[pd.pbase + (Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off)] = l;
+  }
+}
+
+// ----------------------------------------------------------------- misc
+
+// Compute-type copy with frames zero-padded from d to D dimensions.
+template <typename TO, typename TI>
+__global__ void pad_convert_kernel(const TI* in, TO* out, int64_t rows, int d, int D) {
+  const int64_t n = rows * D;
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = u / D;
+    const int k = (int)(u % D);
+    out[u] = (k < d) ? (TO)in[r * d + k] : (TO)0;
+  }
+}
+
+template <typename TI>
+__global__ void nonfinite_kernel(const TI* in, int64_t n, int32_t* flag) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+    if (!__builtin_isfinite((double)in[u])) atomicOr(flag, 1);
+}
+
+__global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
+                                  int32_t kstop) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Ctl c = {};
+  PassDesc P;
+  P.i0 = i0; P.j0 = j0; P.i1 = i1; P.j1 = j1;
+  P.Mb = i1 - i0 + 1; P.Nb = j1 - j0 + 1;
+  P.dir = dir;
+  P.kstop = kstop;
+  P.kf = kstop;
+  P.raw = 1;
+  P.n_rows = min(P.Mb - 1, kstop) + 1;
+  P.n_stripes = (P.n_rows + kWave - 1) / kWave;
+  P.L = P.Mb;
+  P.band_off = 0;
+  P.ring_off = 0;
+  P.flag_off = 0;
+  w.passes[0] = P;
+  for (int s = 0; s < P.n_stripes; ++s) w.tickets[s] = make_int2(0, s);
+  c.n_tickets = P.n_stripes;
+  c.n_pass = 1;
+  *w.ctl = c;
+}
+
+// ----------------------------------------------------------------- launchers
+
+hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t st);
+
+hipError_t launch_init(const Work& w, hipStream_t st) {
+  init_kernel<<<256, 256, 0, st>>>(w);
+  return hipGetLastError();
+}
+hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t st) {
+  plan_kernel<<<1, 1024, 0, st>>>(w, level, final_level, lds_leaf_bytes);
+  return hipGetLastError();
+}
+hipError_t launch_combine(const Work& w, int grid, hipStream_t st) {
+  combine_min_kernel<<<grid, kBandChunk, 0, st>>>(w);
+  combine_argmin_kernel<<<grid, kBandChunk, 0, st>>>(w);
+  return hipGetLastError();
+}
+hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* costs, int64_t* lens,
+                           int32_t* paths, int grid, hipStream_t st) {
+  leaf_index_kernel<<<64, 256, 0, st>>>(w, lidx);
+  scan_kernel<<<w.n_pairs, 1024, 0, st>>>(w, poff, lidx, costs, lens);
+  copy_kernel<<<grid, 256, 0, st>>>(w, poff, paths);
+  return hipGetLastError();
+}
+hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
+                              hipStream_t st) {
+  const int64_t n = rows * D;
+  const int grid = (int)min((int64_t)2048, (n + 255) / 256 + 1);
+  if (in_f64 && out_f64)
+    pad_convert_kernel<double, double><<<grid, 256, 0, st>>>((const double*)in, (double*)out, rows, d, D);
+  else if (in_f64 && !out_f64)
+    pad_convert_kernel<float, double><<<grid, 256, 0, st>>>((const double*)in, (float*)out, rows, d, D);
+  else if (!in_f64 && out_f64)
+    pad_convert_kernel<double, float><<<grid, 256, 0, st>>>((const float*)in, (double*)out, rows, d, D);
+  else
+    pad_convert_kernel<float, float><<<grid, 256, 0, st>>>((const float*)in, (float*)out, rows, d, D);
+  return hipGetLastError();
+}
+hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st) {
+  const int grid = (int)min((int64_t)1024, (n + 255) / 256 + 1);
+  if (in_f64) nonfinite_kernel<double><<<grid, 256, 0, st>>>((const double*)in, n, flag);
+  else nonfinite_kernel<float><<<grid, 256, 0, st>>>((const float*)in, n, flag);
+  return hipGetLastError();
+}
+hipError_t launch_diag(const Work& w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
+                       int32_t kstop, bool f32, int grid, double* out, hipStream_t st) {
+  init_kernel<<<256, 256, 0, st>>>(w);
+  diag_setup_kernel<<<1, 1, 0, st>>>(w, i0, j0, i1, j1, dir, kstop);
+  hipError_t e = launch_pass(w, 0, f32, grid, st);
+  if (e != hipSuccess) return e;
+  diag_out_kernel<<<64, 256, 0, st>>>(w, out);
+  return hipGetLastError();
+}
+
+}  // namespace dtw

@@ -1,0 +1,219 @@
+"""ctypes binding of libdtw_hip.so (C-ABI in include/dtw.h).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+library.  PyTorch supplies device memory (inputs, outputs, workspace) and the
+current stream.  There is no CPU fallback: loading fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdtw_hip.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "dtw.h")
+
+DTW_F64, DTW_F32 = 0, 1
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+STATUS = {0: "ok", -1: "invalid argument", -2: "path capacity too small", -3: "workspace too small",
+          -4: "non-finite input", -5: "HIP runtime error", -6: "not ready", -7: "unknown ticket",
+          -8: "unsupported dimension or mode", -9: "device-side consistency check failed"}
+
+
+class DtwError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({status})")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("min_block", ctypes.c_int32),
+                ("validate_finite", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("s_min", ctypes.c_double), ("cost_lowp", ctypes.c_double),
+                ("cells_processed", ctypes.c_int64), ("path_len", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("leaves", ctypes.c_int32), ("device_error", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions declared in include/dtw.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:dtw_status|void|const char\*|int32_t)\s+(dtw_\w+)\s*\(", txt, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.dtw_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.dtw_default_opts.restype = None
+        L.dtw_status_string.argtypes = [i32]
+        L.dtw_status_string.restype = ctypes.c_char_p
+        L.dtw_last_hip_error.restype = i32
+        L.dtw_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(sz)]
+        L.dtw_workspace_size.restype = i32
+        L.dtw_align.argtypes = [vp, i64, vp, i64, i32, i32, ctypes.POINTER(Opts), vp, sz, vp, vp, i64, vp,
+                                ctypes.POINTER(Stats), vp]
+        L.dtw_align.restype = i32
+        L.dtw_diag.argtypes = [vp, vp, i32, i32, i64, i64, i64, i64, i32, i64, i32, vp, sz, vp, vp]
+        L.dtw_diag.restype = i32
+        L.dtw_workspace_size_batched.argtypes = [i32, i64p, i64p, i32, i32, ctypes.POINTER(Opts),
+                                                 ctypes.POINTER(sz)]
+        L.dtw_workspace_size_batched.restype = i32
+        L.dtw_align_batched.argtypes = [i32, vp, i64p, vp, i64p, i32, i32, ctypes.POINTER(Opts), vp, sz, vp,
+                                        vp, i64p, vp, ctypes.POINTER(Stats), vp]
+        L.dtw_align_batched.restype = i32
+        _lib = L
+    return _lib
+
+
+def make_opts(precision="fp64", min_block=500, validate_finite=False):
+    o = Opts()
+    lib().dtw_default_opts(ctypes.byref(o))
+    o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    o.min_block = int(min_block)
+    o.validate_finite = 1 if validate_finite else 0
+    return o
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise DtwError(rc, what)
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return DTW_F64
+    if t.dtype == torch.float32:
+        return DTW_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("inputs must be contiguous device tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_size(M, N, d, dtype=torch.float64, precision="fp64", min_block=500):
+    o = make_opts(precision, min_block)
+    n = ctypes.c_size_t()
+    code = DTW_F64 if dtype == torch.float64 else DTW_F32
+    _check(lib().dtw_workspace_size(M, N, d, code, ctypes.byref(o), ctypes.byref(n)), "dtw_workspace_size")
+    return n.value
+
+
+class Aligner:
+    """Reusable buffers for repeated alignments of one problem shape."""
+
+    def __init__(self, M, N, d, dtype=torch.float64, precision="fp64", min_block=500, device="cuda"):
+        self.M, self.N, self.d, self.dtype = M, N, d, dtype
+        self.opts = make_opts(precision, min_block)
+        self.ws_bytes = workspace_size(M, N, d, dtype, precision, min_block)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.cost = torch.empty(1, dtype=torch.float64, device=device)
+        self.cap = M + N - 1
+        self.path = torch.empty((self.cap, 2), dtype=torch.int32, device=device)
+        self.plen = torch.empty(1, dtype=torch.int64, device=device)
+
+    def run(self, X, Y, stats=False, stream=None):
+        st = Stats()
+        rc = lib().dtw_align(_dev(X), self.M, _dev(Y), self.N, self.d, _dtype_code(X), ctypes.byref(self.opts),
+                             ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                             ctypes.c_void_p(self.cost.data_ptr()), ctypes.c_void_p(self.path.data_ptr()),
+                             self.cap, ctypes.c_void_p(self.plen.data_ptr()),
+                             ctypes.byref(st) if stats else None, _stream_ptr(stream))
+        _check(rc, "dtw_align")
+        return st.to_dict() if stats else None
+
+
+def align(X, Y, precision="fp64", min_block=500, validate_finite=False, stream=None):
+    """Optimal warping path of X (M x d) and Y (N x d), device tensors.
+
+    Returns (cost: float, path: int32 tensor [K, 2] on the device, stats: dict).
+    """
+    if X.dtype != Y.dtype or X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+        raise ValueError("X and Y must be 2-D with equal dtype and feature dimension")
+    M, d = X.shape
+    N = Y.shape[0]
+    al = Aligner(M, N, d, X.dtype, precision, min_block, device=X.device)
+    al.opts.validate_finite = 1 if validate_finite else 0
+    st = al.run(X, Y, stats=True, stream=stream)
+    n = int(st["path_len"])
+    return float(al.cost.item()), al.path[:n], st
+
+
+def align_batched(Xs, Ys, precision="fp64", min_block=500, stream=None):
+    """Align B independent pairs in one call.  Returns (costs [B] float64 tensor,
+    list of path tensors, stats dict)."""
+    B = len(Xs)
+    dev = Xs[0].device
+    d = Xs[0].shape[1]
+    xo = [0]
+    yo = [0]
+    po = [0]
+    for X, Y in zip(Xs, Ys):
+        xo.append(xo[-1] + X.shape[0])
+        yo.append(yo[-1] + Y.shape[0])
+        po.append(po[-1] + X.shape[0] + Y.shape[0] - 1)
+    Xp = torch.cat(list(Xs)).contiguous()
+    Yp = torch.cat(list(Ys)).contiguous()
+    arr = lambda v: (ctypes.c_int64 * len(v))(*v)
+    xo_a, yo_a, po_a = arr(xo), arr(yo), arr(po)
+    o = make_opts(precision, min_block)
+    n = ctypes.c_size_t()
+    _check(lib().dtw_workspace_size_batched(B, xo_a, yo_a, d, _dtype_code(Xp), ctypes.byref(o), ctypes.byref(n)),
+           "dtw_workspace_size_batched")
+    ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    costs = torch.empty(B, dtype=torch.float64, device=dev)
+    paths = torch.empty((po[-1], 2), dtype=torch.int32, device=dev)
+    lens = torch.empty(B, dtype=torch.int64, device=dev)
+    st = Stats()
+    rc = lib().dtw_align_batched(B, _dev(Xp), xo_a, _dev(Yp), yo_a, d, _dtype_code(Xp), ctypes.byref(o),
+                                 ctypes.c_void_p(ws.data_ptr()), n.value, ctypes.c_void_p(costs.data_ptr()),
+                                 ctypes.c_void_p(paths.data_ptr()), po_a, ctypes.c_void_p(lens.data_ptr()),
+                                 ctypes.byref(st), _stream_ptr(stream))
+    _check(rc, "dtw_align_batched")
+    lens_h = lens.tolist()
+    return costs, [paths[po[b]:po[b] + lens_h[b]] for b in range(B)], st.to_dict()
+
+
+def diag(X, Y, i0, j0, i1, j1, reverse, kstop, precision="fp64", stream=None):
+    """DiagDTW sweep (Algorithm 1) on a block: (3, Mb) float64 device tensor of
+    diagonals kstop-2..kstop by local row, NaN outside the block."""
+    d = X.shape[1]
+    o = make_opts(precision)
+    n = ctypes.c_size_t()
+    _check(lib().dtw_workspace_size(i1 + 1, j1 + 1, d, _dtype_code(X), ctypes.byref(o), ctypes.byref(n)),
+           "dtw_workspace_size")
+    ws = torch.empty(n.value, dtype=torch.uint8, device=X.device)
+    Mb = i1 - i0 + 1
+    out = torch.empty((3, Mb), dtype=torch.float64, device=X.device)
+    rc = lib().dtw_diag(_dev(X), _dev(Y), d, _dtype_code(X), i0, j0, i1, j1, int(bool(reverse)), kstop,
+                        o.precision, ctypes.c_void_p(ws.data_ptr()), n.value, ctypes.c_void_p(out.data_ptr()),
+                        _stream_ptr(stream))
+    _check(rc, "dtw_diag")
+    return out

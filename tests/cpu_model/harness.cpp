@@ -1,0 +1,252 @@
+// CPU model of libdtw_hip.so for host-side tests.
+//
+// Compiled for x86 together with the orchestration kernels of
+// paper_2008_02734_amd/csrc/dtw_plan.hip (included below by the test as
+// "dtw_plan_kernels.inc", the file minus its launcher section) and the real
+// host runtime dtw_api.hip.  The two wave kernels (sweep and leaf) are
+// replaced by plain loops that write exactly the outputs the GPU kernels
+// write; they also check the stripe queue and every buffer index they use.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "hip/hip_runtime.h"
+
+thread_local dim3_cpu threadIdx, blockIdx, blockDim, gridDim;
+thread_local std::barrier<>* cpu_block_barrier = nullptr;
+
+#include "dtw_plan_kernels.inc"
+
+#define MODEL_CHECK(cond)                                                      \
+  do {                                                                         \
+    if (!(cond)) {                                                             \
+      std::fprintf(stderr, "model check failed: %s (%s:%d)\n", #cond, __FILE__, __LINE__); \
+      std::abort();                                                            \
+    }                                                                          \
+  } while (0)
+
+namespace dtw {
+
+int pick_dmax(int d) {
+  if (d <= 4) return 4;
+  if (d <= 8) return 8;
+  if (d <= 12) return 12;
+  if (d <= 16) return 16;
+  if (d <= 24) return 24;
+  if (d <= 32) return 32;
+  return 0;
+}
+
+template <typename T>
+static T model_cost(const T* x, const T* y, int D) {
+  T s = T(0);
+  for (int k = 0; k < D; ++k) {
+    const T e = x[k] - y[k];
+    s = std::fma(e, e, s);
+  }
+  return std::sqrt(s);
+}
+
+template <typename T>
+static void model_pass(const Work& w) {
+  Ctl* ctl = w.ctl;
+  const int n_t = ctl->n_tickets, n_pass = ctl->n_pass;
+  MODEL_CHECK(n_pass >= 0 && n_pass <= 2 * w.caps.sub);
+  MODEL_CHECK(n_t >= 0 && n_t <= w.caps.ticket);
+  std::vector<std::vector<int>> seen(n_pass);
+  for (int p = 0; p < n_pass; ++p) seen[p].assign(w.passes[p].n_stripes, 0);
+  int last_s = 0;
+  for (int t = 0; t < n_t; ++t) {
+    const int2 tv = w.tickets[t];
+    MODEL_CHECK(tv.x >= 0 && tv.x < n_pass);
+    MODEL_CHECK(tv.y >= 0 && tv.y < w.passes[tv.x].n_stripes);
+    MODEL_CHECK(tv.y >= last_s);  // stripe-major order: no stripe waits on a later ticket
+    last_s = tv.y;
+    seen[tv.x][tv.y] += 1;
+  }
+  for (int p = 0; p < n_pass; ++p)
+    for (int c : seen[p]) MODEL_CHECK(c == 1);
+  const int D = pick_dmax(w.d);
+  const T* X = static_cast<const T*>(w.X);
+  const T* Y = static_cast<const T*>(w.Y);
+  const T INF = std::numeric_limits<T>::infinity();
+  for (int p = 0; p < n_pass; ++p) {
+    const PassDesc P = w.passes[p];
+    MODEL_CHECK(P.n_rows == std::min(P.Mb - 1, P.kstop) + 1);
+    MODEL_CHECK(P.band_off >= 0 && P.band_off + 3 * (int64_t)P.L <= w.caps.band);
+    MODEL_CHECK(P.ring_off >= 0 && P.ring_off + kRing * (int64_t)P.Nb <= w.caps.ring);
+    const int K = P.Mb + P.Nb - 1;
+    std::vector<T> F((size_t)P.n_rows * P.Nb, INF);
+    for (int a = 0; a < P.n_rows; ++a) {
+      const int bmax = std::min(P.Nb - 1, P.kstop - a);
+      for (int b = 0; b <= bmax; ++b) {
+        const int64_t gi = P.dir ? P.i1 - a : P.i0 + a;
+        const int64_t gj = P.dir ? P.j1 - b : P.j0 + b;
+        const T c = model_cost(X + gi * D, Y + gj * D, D);
+        T f;
+        if (a == 0 && b == 0) f = c;
+        else {
+          const T dg = (a > 0 && b > 0) ? F[(size_t)(a - 1) * P.Nb + b - 1] : INF;
+          const T up = (a > 0) ? F[(size_t)(a - 1) * P.Nb + b] : INF;
+          const T lf = (b > 0) ? F[(size_t)a * P.Nb + b - 1] : INF;
+          f = std::min(std::min(dg, up), lf) + c;
+        }
+        F[(size_t)a * P.Nb + b] = f;
+        const int k = a + b;
+        if (k >= P.kstop - 2) {
+          if (P.dir == 0 || P.raw) {
+            const int q = k - (P.kstop - 2);
+            const int lo = std::max(0, k - (P.Nb - 1));
+            MODEL_CHECK(a - lo >= 0 && a - lo < P.L && q >= 0 && q < 3);
+            const int64_t idx = P.band_off + (int64_t)q * P.L + (a - lo);
+            w.bandF[idx] = (double)f;
+            if (w.bandC) w.bandC[idx] = (double)c;
+          } else {
+            const int kfw = K - 1 - k;
+            const int q = kfw - (P.kf - 2);
+            const int af = P.Mb - 1 - a;
+            const int lo = std::max(0, kfw - (P.Nb - 1));
+            MODEL_CHECK(af - lo >= 0 && af - lo < P.L && q >= 0 && q < 3);
+            w.bandB[P.band_off + (int64_t)q * P.L + (af - lo)] = (double)f;
+          }
+        }
+      }
+    }
+  }
+  ctl->ticket = n_t;
+}
+
+template <typename T>
+static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64) {
+  Ctl* ctl = w.ctl;
+  const int n_leaf = ctl->n_leaf;
+  MODEL_CHECK(n_leaf >= 0 && n_leaf <= w.caps.leaf);
+  const int D = pick_dmax(w.d);
+  const int d = w.d;
+  const T* X = static_cast<const T*>(w.X);
+  const T* Y = static_cast<const T*>(w.Y);
+  const T INF = std::numeric_limits<T>::infinity();
+  for (int l = 0; l < n_leaf; ++l) {
+    const LeafDesc Lf = w.leaves[l];
+    MODEL_CHECK(Lf.pair >= 0 && Lf.pair < w.n_pairs);
+    const PairDesc pd = w.pairs[Lf.pair];
+    const int Mb = Lf.i1 - Lf.i0 + 1, Nb = Lf.j1 - Lf.j0 + 1;
+    MODEL_CHECK(Mb >= 1 && Nb >= 1);
+    MODEL_CHECK(Lf.i0 >= pd.x_off && Lf.i1 < pd.x_off + pd.M && Lf.j0 >= pd.y_off && Lf.j1 < pd.y_off + pd.N);
+    MODEL_CHECK(std::min(Mb, Nb) < w.min_block);
+    if (Lf.scratch_off >= 0) {
+      const int64_t R = std::min(Mb, Nb), Cc = std::max(Mb, Nb);
+      const int64_t need = (((R * ((Cc + 15) / 16)) + 1) & ~(int64_t)1) + 2 * Cc;
+      MODEL_CHECK(Lf.scratch_off + need <= w.caps.leaf_words);
+    }
+    std::vector<T> F((size_t)Mb * Nb);
+    std::vector<unsigned char> P((size_t)Mb * Nb);
+    for (int i = 0; i < Mb; ++i)
+      for (int j = 0; j < Nb; ++j) {
+        const T c = model_cost(X + (int64_t)(Lf.i0 + i) * D, Y + (int64_t)(Lf.j0 + j) * D, D);
+        T f;
+        unsigned char mv = 0;
+        if (i == 0 && j == 0) f = c;
+        else {
+          const T dg = (i > 0 && j > 0) ? F[(size_t)(i - 1) * Nb + j - 1] : INF;
+          const T up = (i > 0) ? F[(size_t)(i - 1) * Nb + j] : INF;
+          const T lf = (j > 0) ? F[(size_t)i * Nb + j - 1] : INF;
+          if (dg <= up && dg <= lf) mv = 0;
+          else if (up <= lf) mv = 1;
+          else mv = 2;
+          f = std::min(std::min(dg, up), lf) + c;
+        }
+        F[(size_t)i * Nb + j] = f;
+        P[(size_t)i * Nb + j] = mv;
+      }
+    const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
+    const int64_t slot_end = pd.pbase + e;
+    MODEL_CHECK(e >= 0 && e < pd.M + pd.N - 1);
+    int cnt = 0, i = Mb - 1, j = Nb - 1;
+    double cost = 0.0;
+    for (;;) {
+      const bool at_start = (i == 0 && j == 0);
+      if (!at_start || Lf.first) {
+        MODEL_CHECK(slot_end - cnt >= pd.pbase);
+        w.tpath[slot_end - cnt] = make_int2((int)(Lf.i0 + i - pd.x_off), (int)(Lf.j0 + j - pd.y_off));
+        ++cnt;
+        const int64_t gi = Lf.i0 + i, gj = Lf.j0 + j;
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double ee = in_f64 ? static_cast<const double*>(Xo)[gi * d + k] - static_cast<const double*>(Yo)[gj * d + k]
+                                   : (double)static_cast<const float*>(Xo)[gi * d + k] - (double)static_cast<const float*>(Yo)[gj * d + k];
+          s = std::fma(ee, ee, s);
+        }
+        cost += std::sqrt(s);
+      }
+      if (at_start) break;
+      const unsigned char mv = (i == 0) ? 2 : (j == 0) ? 1 : P[(size_t)i * Nb + j];
+      if (mv == 0) { --i; --j; }
+      else if (mv == 1) --i;
+      else --j;
+    }
+    w.cnt[slot_end] = cnt;
+    w.leaf_cost[l] = make_double2(cost, 0.0);
+    ctl->cells += (int64_t)Mb * Nb;
+    if (Lf.first && Lf.i1 == pd.x_off + pd.M - 1 && Lf.j1 == pd.y_off + pd.N - 1)
+      w.smin[Lf.pair] = (double)F[(size_t)Mb * Nb - 1];
+  }
+  ctl->leaf_ticket = n_leaf;
+}
+
+hipError_t launch_pass(const Work& w, int, bool f32, int, hipStream_t) {
+  if (f32) model_pass<float>(w);
+  else model_pass<double>(w);
+  return hipSuccess;
+}
+hipError_t launch_leaf(const Work& w, bool f32, int, size_t, int64_t, const void* Xo, const void* Yo, int in_f64,
+                       hipStream_t) {
+  if (f32) model_leaf<float>(w, Xo, Yo, in_f64);
+  else model_leaf<double>(w, Xo, Yo, in_f64);
+  return hipSuccess;
+}
+hipError_t set_leaf_lds_limit(size_t) { return hipSuccess; }
+
+hipError_t launch_init(const Work& w, hipStream_t) {
+  cpu_launch(2, 64, [&] { init_kernel(w); });
+  return hipSuccess;
+}
+hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t) {
+  cpu_launch(1, 128, [&] { plan_kernel(w, level, final_level, lds_leaf_bytes); });
+  return hipSuccess;
+}
+hipError_t launch_combine(const Work& w, int, hipStream_t) {
+  cpu_launch(3, kBandChunk, [&] { combine_min_kernel(w); });
+  cpu_launch(3, kBandChunk, [&] { combine_argmin_kernel(w); });
+  return hipSuccess;
+}
+hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* costs, int64_t* lens,
+                           int32_t* paths, int, hipStream_t) {
+  cpu_launch(2, 64, [&] { leaf_index_kernel(w, lidx); });
+  cpu_launch(w.n_pairs, 128, [&] { scan_kernel(w, poff, lidx, costs, lens); });
+  cpu_launch(2, 64, [&] { copy_kernel(w, poff, paths); });
+  return hipSuccess;
+}
+hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
+                              hipStream_t) {
+  if (in_f64 && out_f64)
+    cpu_launch(2, 64, [&] { pad_convert_kernel<double, double>((const double*)in, (double*)out, rows, d, D); });
+  else if (in_f64)
+    cpu_launch(2, 64, [&] { pad_convert_kernel<float, double>((const double*)in, (float*)out, rows, d, D); });
+  else if (out_f64)
+    cpu_launch(2, 64, [&] { pad_convert_kernel<double, float>((const float*)in, (double*)out, rows, d, D); });
+  else
+    cpu_launch(2, 64, [&] { pad_convert_kernel<float, float>((const float*)in, (float*)out, rows, d, D); });
+  return hipSuccess;
+}
+hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t) {
+  if (in_f64) cpu_launch(2, 64, [&] { nonfinite_kernel<double>((const double*)in, n, flag); });
+  else cpu_launch(2, 64, [&] { nonfinite_kernel<float>((const float*)in, n, flag); });
+  return hipSuccess;
+}
+hipError_t launch_diag(const Work&, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, bool, int, double*,
+                       hipStream_t) {
+  return hipErrorInvalidValue;  // the sweep itself is a wave kernel: GPU tests cover it
+}
+
+}  // namespace dtw

@@ -1,0 +1,100 @@
+// Host stand-in for <hip/hip_runtime.h> used by the CPU model of the
+// orchestration kernels (tests only).  A "block" runs as blockDim.x OS
+// threads sharing one std::barrier; __shared__ becomes a function-static
+// object, so blocks of a launch run one after another.
+#pragma once
+#include <algorithm>
+#include <atomic>
+#include <barrier>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <thread>
+#include <vector>
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+typedef void* hipStream_t;
+enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
+enum hipDeviceAttribute_t {
+  hipDeviceAttributeMultiprocessorCount,
+  hipDeviceAttributeMaxSharedMemoryPerBlock,
+  hipDeviceAttributeWallClockRate
+};
+enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize };
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define __align__(x) alignas(x)
+
+struct dim3_cpu { unsigned int x = 0, y = 1, z = 1; };
+extern thread_local dim3_cpu threadIdx, blockIdx, blockDim, gridDim;
+extern thread_local std::barrier<>* cpu_block_barrier;
+inline void __syncthreads() { cpu_block_barrier->arrive_and_wait(); }
+
+struct int2 { int x, y; };
+struct double2 { double x, y; };
+inline int2 make_int2(int a, int b) { return int2{a, b}; }
+inline double2 make_double2(double a, double b) { return double2{a, b}; }
+inline long long __double_as_longlong(double v) { long long r; std::memcpy(&r, &v, 8); return r; }
+inline double __longlong_as_double(long long v) { double r; std::memcpy(&r, &v, 8); return r; }
+
+template <class T> inline T min(T a, T b) { return b < a ? b : a; }
+template <class T> inline T max(T a, T b) { return a < b ? b : a; }
+
+template <class T> inline T atomicAdd(T* p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+template <class T> inline T atomicOr(T* p, T v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+template <class T> inline T atomicCAS(T* p, T cmp, T v) {
+  __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+  return cmp;
+}
+template <class T> inline T atomicMin(T* p, T v) {
+  T cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {}
+  return cur;
+}
+template <class T> inline T atomicMax(T* p, T v) {
+  T cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (cur < v && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {}
+  return cur;
+}
+
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
+  switch (a) {
+    case hipDeviceAttributeMultiprocessorCount: *v = 4; break;
+    case hipDeviceAttributeMaxSharedMemoryPerBlock: *v = 163840; break;
+    case hipDeviceAttributeWallClockRate: *v = 100000; break;
+  }
+  return hipSuccess;
+}
+inline hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind, hipStream_t) {
+  std::memcpy(dst, src, n);
+  return hipSuccess;
+}
+inline hipError_t hipMemsetAsync(void* p, int v, size_t n, hipStream_t) { std::memset(p, v, n); return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipGetLastError() { return hipSuccess; }
+
+// The model launches the 1024-thread kernels with fewer threads; they tile
+// over blockDim.x, so smaller blocks exercise more tiles.
+// Run `body` as a grid of `grid` blocks of `block` threads.
+inline void cpu_launch(int grid, int block, const std::function<void()>& body) {
+  for (int b = 0; b < grid; ++b) {
+    std::barrier<> bar(block);
+    std::vector<std::thread> th;
+    th.reserve(block);
+    for (int t = 0; t < block; ++t)
+      th.emplace_back([&, t, b] {
+        threadIdx.x = t; blockIdx.x = b; blockDim.x = block; gridDim.x = grid;
+        cpu_block_barrier = &bar;
+        body();
+      });
+    for (auto& x : th) x.join();
+  }
+}

@@ -1,0 +1,88 @@
+"""Host-side checks of the C-ABI library (no GPU needed): the shared library
+loads, exports every function that include/dtw.h declares, and rejects bad
+arguments with the documented status codes before touching the device."""
+import ctypes
+
+import pytest
+
+from paper_2008_02734_amd import dtw
+
+
+def test_library_exports_every_header_symbol():
+    L = dtw.lib()
+    names = dtw.header_functions()
+    assert {"dtw_align", "dtw_align_batched", "dtw_workspace_size", "dtw_diag"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = dtw.lib()
+    for code, txt in dtw.STATUS.items():
+        assert L.dtw_status_string(code).decode() == txt
+
+
+def test_workspace_is_linear_in_length():
+    # O(M+N) working memory (Sec. 3.2 memory discussion): doubling both sides
+    # must not quadruple the workspace.
+    a = dtw.workspace_size(20000, 16000, 12)
+    b = dtw.workspace_size(40000, 32000, 12)
+    assert b < 2.3 * a
+    assert dtw.workspace_size(200000, 160000, 12) < 200e6
+
+
+def _align(L, X=1, M=10, Y=1, N=10, d=12, dt=0, opts=None, ws=1, wsb=1 << 40, cost=1, path=1, cap=None, plen=1):
+    o = opts if opts is not None else dtw.make_opts()
+    cap = (M + N - 1) if cap is None else cap
+    vp = ctypes.c_void_p
+    return L.dtw_align(vp(X) if X else None, M, vp(Y) if Y else None, N, d, dt, ctypes.byref(o),
+                       vp(ws) if ws else None, wsb, vp(cost) if cost else None, vp(path) if path else None,
+                       cap, vp(plen) if plen else None, None, None)
+
+
+def test_argument_errors_before_any_device_work():
+    L = dtw.lib()
+    assert _align(L, X=0) == -1
+    assert _align(L, Y=0) == -1
+    assert _align(L, M=0) == -1
+    assert _align(L, N=-3) == -1
+    assert _align(L, d=0) == -1
+    assert _align(L, dt=7) == -1
+    assert _align(L, ws=0) == -1
+    assert _align(L, cost=0) == -1
+    assert _align(L, cap=18) == -2        # M + N - 1 = 19 needed
+    assert _align(L, wsb=16) == -3
+    assert _align(L, d=33) == -8          # feature dimension not built
+    bad = dtw.make_opts(min_block=2)
+    assert _align(L, opts=bad) == -1      # recursion would not terminate
+    bad = dtw.make_opts(min_block=2000)
+    assert _align(L, opts=bad) == -1
+    bad = dtw.make_opts()
+    bad.reserved[0] = 1
+    assert _align(L, opts=bad) == -1
+    bad = dtw.make_opts(precision=9)
+    assert _align(L, opts=bad) == -1
+
+
+def test_workspace_size_errors():
+    L = dtw.lib()
+    n = ctypes.c_size_t()
+    o = dtw.make_opts()
+    assert L.dtw_workspace_size(0, 5, 12, 0, ctypes.byref(o), ctypes.byref(n)) == -1
+    assert L.dtw_workspace_size(5, 5, 12, 0, ctypes.byref(o), None) == -1
+    assert L.dtw_workspace_size(5, 5, 12, 0, None, ctypes.byref(n)) == 0 and n.value > 0
+
+
+def test_batched_argument_errors():
+    L = dtw.lib()
+    o = dtw.make_opts()
+    arr = lambda v: (ctypes.c_int64 * len(v))(*v)
+    vp = ctypes.c_void_p
+    # capacity of pair 1 too small (needs 5 + 4 - 1 = 8)
+    rc = L.dtw_align_batched(2, vp(1), arr([0, 3, 8]), vp(1), arr([0, 3, 7]), 4, 0, ctypes.byref(o), vp(1),
+                             1 << 40, vp(1), vp(1), arr([0, 5, 12]), vp(1), None, None)
+    assert rc == -2
+    # empty pair
+    rc = L.dtw_align_batched(2, vp(1), arr([0, 3, 3]), vp(1), arr([0, 3, 7]), 4, 0, ctypes.byref(o), vp(1),
+                             1 << 40, vp(1), vp(1), arr([0, 5, 12]), vp(1), None, None)
+    assert rc == -1

@@ -1,0 +1,108 @@
+"""CPU model of the device orchestration, built from the real sources.
+
+The orchestration kernels (paper_2008_02734_amd/csrc/dtw_plan.hip, without
+its launcher section) and the real host runtime (dtw_api.hip) are compiled
+for the host with g++ and AddressSanitizer against a thread-based stand-in
+for the HIP runtime (tests/cpu_model/hip/hip_runtime.h).  The two wave
+kernels are replaced by plain loops that write the same outputs and check
+the stripe queue and every buffer index (tests/cpu_model/harness.cpp).
+Every result is compared with the CPU oracle.
+"""
+import os
+import struct
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_02734_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2008_02734_amd", "csrc")
+MODEL = os.path.join(ROOT, "tests", "cpu_model")
+MARK = "// ----------------------------------------------------------------- launchers"
+
+
+@pytest.fixture(scope="module")
+def model_exe(tmp_path_factory):
+    d = tmp_path_factory.mktemp("cpu_model")
+    src = open(os.path.join(CSRC, "dtw_plan.hip")).read()
+    assert MARK in src
+    with open(d / "dtw_plan_kernels.inc", "w") as f:
+        f.write(src[: src.index(MARK)] + "}  // namespace dtw\n")
+    exe = d / "cpu_model"
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-Wno-unknown-pragmas", "-pthread",
+           "-I", MODEL, "-I", str(d), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(MODEL, "harness.cpp"), os.path.join(MODEL, "driver.cpp"),
+           "-x", "c++", os.path.join(CSRC, "dtw_api.hip"), "-o", str(exe)]
+    subprocess.run(cmd, check=True)
+    return str(exe)
+
+
+def run_model(exe, pairs, m, precision=0):
+    d = pairs[0][0].shape[1]
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
+        with open(fin, "wb") as f:
+            f.write(struct.pack("4i", len(pairs), d, m, precision))
+            for X, Y in pairs:
+                f.write(struct.pack("2q", X.shape[0], Y.shape[0]))
+            for X, _ in pairs:
+                f.write(np.ascontiguousarray(X, dtype=np.float64).tobytes())
+            for _, Y in pairs:
+                f.write(np.ascontiguousarray(Y, dtype=np.float64).tobytes())
+        r = subprocess.run([exe, fin, fout], capture_output=True, timeout=300,
+                           env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+        assert r.returncode == 0, r.stderr.decode()[-3000:]
+        buf = open(fout, "rb").read()
+    rc, derr, levels, leaves = struct.unpack_from("4i", buf, 0)
+    (cells,) = struct.unpack_from("q", buf, 16)
+    off = 24
+    out = []
+    for _ in pairs:
+        cost, n = struct.unpack_from("dq", buf, off)
+        off += 16
+        path = np.frombuffer(buf, dtype=np.int32, count=2 * n, offset=off).reshape(-1, 2) if rc == 0 else None
+        off += 8 * n if rc == 0 else 0
+        out.append((cost, path))
+    return dict(rc=rc, device_error=derr, levels=levels, leaves=leaves, cells=cells, results=out)
+
+
+CASES = [(37, 29, 3, 3), (100, 80, 12, 3), (129, 257, 5, 16), (300, 240, 12, 16), (70, 70, 4, 64),
+         (2, 300, 4, 3), (300, 1, 4, 3), (1, 1, 2, 3), (200, 130, 1, 5), (64, 65, 32, 3)]
+
+
+@pytest.mark.parametrize("M,N,d,m", CASES)
+def test_model_matches_oracle(model_exe, M, N, d, m):
+    X, Y = synth.random_pair(8000 + M + N, M, N, d, "normal")
+    r = run_model(model_exe, [(X, Y)], m)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    cost, path = r["results"][0]
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
+    assert r["cells"] == oracle.linmdtw(X, Y, min_block=m)["cells"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_model_ties_equal_linmdtw(model_exe, seed):
+    rng = np.random.default_rng(seed)
+    M, N = int(rng.integers(3, 90)), int(rng.integers(3, 90))
+    X, Y = synth.random_pair(9000 + seed, M, N, 1, "int3")
+    r = run_model(model_exe, [(X, Y)], 3)
+    assert r["rc"] == 0 and r["device_error"] == 0
+    assert r["results"][0][1].tolist() == oracle.linmdtw(X, Y, min_block=3)["path"].tolist()
+
+
+def test_model_batched(model_exe):
+    shapes = [(40, 33), (7, 90), (120, 100), (1, 1), (64, 64)]
+    pairs = [synth.random_pair(500 + i, M, N, 6, "normal") for i, (M, N) in enumerate(shapes)]
+    r = run_model(model_exe, pairs, 5)
+    assert r["rc"] == 0 and r["device_error"] == 0
+    for (X, Y), (cost, path) in zip(pairs, r["results"]):
+        c_ref, p_ref = oracle.full(X, Y)
+        assert path.tolist() == p_ref.tolist()
+        assert abs(cost - c_ref) <= 1e-12 * c_ref

@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C-ABI.
+
+FP64 bar (exact method): every accumulated cost of a sweep equals the
+oracle's bit for bit (min is exact and each cell is one rounded addition of
+the same frame cost); the alignment path equals the oracle's textbook path on
+tie-free inputs and the oracle's linmdtw path on every input; the cost agrees
+within 1e-12 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2008_02734_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dtw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_02734_amd import dtw as mod
+    mod.lib()
+    return mod
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def bitwise_equal(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(
+        a[~np.isnan(a)].view(np.int64), b[~np.isnan(b)].view(np.int64))
+
+
+# ------------------------------------------------------------------ one sweep
+
+SWEEP_CASES = [
+    # (M, N, d, block (i0, j0, i1, j1) or None, kstop selector)
+    (7, 5, 3, None, "all"),
+    (70, 50, 12, None, "mid"),        # two stripes, ragged tail
+    (130, 200, 12, None, "mid"),      # three stripes, N > M
+    (300, 90, 5, None, "mid"),        # stripes beyond the triangle
+    (150, 140, 24, None, "max"),      # kstop at the last diagonal but one
+    (200, 180, 12, (17, 9, 180, 170), "mid"),  # sub-block
+    (65, 64, 1, None, "mid"),         # one row past a full stripe
+    (40, 400, 32, None, "mid"),       # single stripe, long row
+]
+
+
+@pytest.mark.parametrize("case", range(len(SWEEP_CASES)))
+@pytest.mark.parametrize("reverse", [0, 1])
+def test_diag_sweep_bitwise(dtw, case, reverse):
+    M, N, d, blk, sel = SWEEP_CASES[case]
+    X, Y = synth.random_pair(7000 + case, M, N, d, "normal")
+    i0, j0, i1, j1 = blk if blk else (0, 0, M - 1, N - 1)
+    K = (i1 - i0 + 1) + (j1 - j0 + 1) - 1
+    if sel == "all":
+        ks = list(range(2, K - 1))
+    elif sel == "mid":
+        ks = [2, (K + 1) // 2, (K + 1) // 2 + 1, K - 2]
+    else:
+        ks = [K - 2]
+    Xd, Yd = dev(X), dev(Y)
+    for kstop in ks:
+        got = dtw.diag(Xd, Yd, i0, j0, i1, j1, reverse, kstop).cpu().numpy()
+        want = oracle.diag(X, Y, i0, j0, i1, j1, reverse, kstop)
+        assert bitwise_equal(got, want), (case, reverse, kstop)
+
+
+# ------------------------------------------------------------------ full alignment
+
+def check_path(path, M, N):
+    p = np.asarray(path)
+    assert tuple(p[0]) == (0, 0) and tuple(p[-1]) == (M - 1, N - 1)
+    steps = {tuple(s) for s in np.diff(p, axis=0).tolist()}
+    assert steps <= {(0, 1), (1, 0), (1, 1)}
+
+
+ALIGN_CASES = [(s, M, N, d, m) for s, (M, N, d) in enumerate(
+    [(37, 29, 3), (100, 80, 12), (129, 257, 5), (300, 240, 12), (513, 470, 24), (1000, 700, 12),
+     (64, 64, 1), (2, 300, 4), (300, 1, 4), (1, 1, 2)]) for m in (3, 16, 500)]
+
+
+@pytest.mark.parametrize("s,M,N,d,m", ALIGN_CASES)
+def test_align_matches_textbook_tie_free(dtw, s, M, N, d, m):
+    X, Y = synth.random_pair(8000 + s, M, N, d, "normal")
+    cost, path, st = dtw.align(dev(X), dev(Y), min_block=m)
+    assert st["device_error"] == 0
+    path = path.cpu().numpy()
+    check_path(path, M, N)
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
+    r = oracle.linmdtw(X, Y, min_block=m)
+    assert st["cells_processed"] == r["cells"]
+    assert abs(st["s_min"] - c_ref) <= 1e-12 * c_ref
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("m", [3, 7])
+def test_align_equals_linmdtw_port_on_ties(dtw, seed, m):
+    # Integer frames make exact ties common: the GPU must take the same pivots
+    # as the CPU port of Algorithm 2 (same band, same tie rule), hence the same
+    # path, and its cost must be the exact optimum.
+    rng = np.random.default_rng(seed)
+    M, N = int(rng.integers(3, 150)), int(rng.integers(3, 150))
+    X, Y = synth.random_pair(9000 + seed, M, N, 1, "int3")
+    cost, path, st = dtw.align(dev(X), dev(Y), min_block=m)
+    r = oracle.linmdtw(X, Y, min_block=m)
+    assert path.cpu().numpy().tolist() == r["path"].tolist()
+    c_ref, _ = oracle.full(X, Y)
+    assert cost == c_ref
+
+
+def test_config1_exact(dtw):
+    # 500 x 400, d = 12 FP64 Gaussian walk: a single leaf at m = 500, and the
+    # divide-and-conquer path at smaller m.
+    X, Y = synth.config_pair(1)
+    c_ref, p_ref = oracle.full(X, Y)
+    for m in (500, 64, 16, 3):
+        cost, path, st = dtw.align(dev(X), dev(Y), min_block=m)
+        assert path.cpu().numpy().tolist() == p_ref.tolist(), m
+        assert abs(cost - c_ref) <= 1e-12 * c_ref
+
+
+def test_float32_input_promoted_exactly(dtw):
+    # FP32 inputs in FP64 mode are widened exactly; the oracle sees the same values.
+    X, Y = synth.random_pair(31, 200, 170, 12, "normal")
+    X32, Y32 = X.astype(np.float32), Y.astype(np.float32)
+    cost, path, _ = dtw.align(dev(X32, torch.float32), dev(Y32, torch.float32), min_block=16)
+    c_ref, p_ref = oracle.full(X32.astype(np.float64), Y32.astype(np.float64))
+    assert path.cpu().numpy().tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
+
+
+def test_deterministic_repeats(dtw):
+    X, Y = synth.make_pair(2, 5, 3000, 2500, 12, "chroma")
+    a = dtw.align(dev(X), dev(Y), min_block=64)
+    b = dtw.align(dev(X), dev(Y), min_block=64)
+    assert a[0] == b[0]
+    assert torch.equal(a[1], b[1])
+
+
+def test_batched_equals_single(dtw):
+    shapes = [(300, 250), (64, 700), (1000, 900), (5, 5), (777, 600)]
+    Xs, Ys = [], []
+    for p, (M, N) in enumerate(shapes):
+        X, Y = synth.make_pair(4, p, M, N, 12, "chroma") if 0.5 <= (M - 1) / (N - 1) <= 2 else \
+            synth.random_pair(40 + p, M, N, 12)
+        Xs.append(dev(X))
+        Ys.append(dev(Y))
+    costs, paths, st = dtw.align_batched(Xs, Ys, min_block=64)
+    assert st["device_error"] == 0
+    for b in range(len(shapes)):
+        c1, p1, _ = dtw.align(Xs[b], Ys[b], min_block=64)
+        assert costs[b].item() == c1
+        assert torch.equal(paths[b], p1)
+
+
+def test_validate_finite(dtw):
+    X, Y = synth.random_pair(1, 50, 40, 3)
+    X[7, 1] = np.nan
+    with pytest.raises(dtw.DtwError) as e:
+        dtw.align(dev(X), dev(Y), validate_finite=True)
+    assert e.value.status == -4
+
+
+def test_config2_full_size(dtw):
+    # 20000 x 16000, d = 12 FP64 chroma-like: the workload of the benchmark.
+    X, Y = synth.config_pair(2)
+    cost, path, st = dtw.align(dev(X), dev(Y))
+    assert st["device_error"] == 0
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.cpu().numpy().tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
+    M, N = X.shape[0], Y.shape[0]
+    assert st["cells_processed"] <= 2 * M * N + (M + N) * math.log2(M + N) + 3 * (M + N) * st["levels"]
