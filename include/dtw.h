@@ -76,7 +76,9 @@ typedef struct dtw_opts {
                               valid range [3, 1024]: below 3 the recursion would not
                               terminate, above 1024 a leaf no longer fits one workgroup */
   int32_t validate_finite; /* nonzero: scan X and Y for NaN/Inf first (synchronises)    */
-  int32_t reserved[5];     /* must be zero                                                */
+  int32_t profile;         /* nonzero (with stats): time each kernel class with HIP events
+                              recorded on `stream` and report the sums in dtw_stats       */
+  int32_t reserved[4];     /* must be zero                                                */
 } dtw_opts;
 
 typedef struct dtw_stats {
@@ -88,10 +90,17 @@ typedef struct dtw_stats {
                               cells of every leaf table (progress measure of Sec. 3.2)     */
   int64_t path_len;        /* number of (i,j) pairs written                               */
   int64_t workspace_bytes; /* bytes of the workspace this problem needs                  */
+  int64_t sweep_cells;     /* cells evaluated by the wavefront sweeps                     */
+  int64_t leaf_cells;      /* cells of the leaf tables                                    */
   int32_t levels;          /* split levels executed                                       */
   int32_t leaves;          /* leaf blocks solved with the full table                      */
   int32_t device_error;    /* 0, or a device-side consistency code                        */
-  int32_t reserved[5];
+  int32_t reserved[3];
+  double ms_sweep;         /* with opts->profile: summed GPU time of the sweep launches   */
+  double ms_split;         /* split cost + argmin launches                                */
+  double ms_plan;          /* recursion planning launches                                 */
+  double ms_leaf;          /* leaf solve launches                                         */
+  double ms_other;         /* input staging, initialisation and path assembly             */
 } dtw_stats;
 
 /* Fill *opts with the defaults (FP64, m = 500, no validation). */

@@ -218,10 +218,70 @@ dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
   if (o) *out = *o;
   if (!valid_precision(out->precision)) return out->precision == DTW_PREC_BF16_COST ? DTW_ERR_UNSUPPORTED : DTW_ERR_INVALID_ARG;
   if (out->min_block < 3 || out->min_block > kMaxMinBlock) return DTW_ERR_INVALID_ARG;
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 4; ++i)
     if (out->reserved[i] != 0) return DTW_ERR_INVALID_ARG;
   return DTW_OK;
 }
+
+// Kernel-class timing with HIP events recorded on the caller's stream.
+enum ProfClass { kProfSweep = 0, kProfSplit, kProfPlan, kProfLeaf, kProfOther, kProfClasses };
+constexpr int kProfEvents = 1024;
+
+struct Profiler {
+  bool on = false;
+  hipStream_t st = nullptr;
+  hipEvent_t* ev = nullptr;
+  int used = 0;
+  int cls[kProfEvents / 2];
+
+  hipError_t init(bool enable, hipStream_t s) {
+    on = enable;
+    st = s;
+    if (!on) return hipSuccess;
+    static hipEvent_t pools[64][kProfEvents];
+    static bool made[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (!made[dev]) {
+      for (int i = 0; i < kProfEvents; ++i) {
+        hipError_t e = hipEventCreate(&pools[dev][i]);
+        if (e != hipSuccess) return e;
+      }
+      made[dev] = true;
+    }
+    ev = pools[dev];
+    return hipSuccess;
+  }
+  hipError_t begin(int c) {
+    if (!on || used + 2 > kProfEvents) return hipSuccess;
+    cls[used / 2] = c;
+    return hipEventRecord(ev[used], st);
+  }
+  hipError_t end() {
+    if (!on || used + 2 > kProfEvents) return hipSuccess;
+    hipError_t e = hipEventRecord(ev[used + 1], st);
+    used += 2;
+    return e;
+  }
+  // after the stream has completed
+  hipError_t sums(double* ms) {
+    for (int c = 0; c < kProfClasses; ++c) ms[c] = 0.0;
+    for (int i = 0; i < used; i += 2) {
+      float t = 0.f;
+      hipError_t e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      if (e != hipSuccess) return e;
+      ms[cls[i / 2]] += t;
+    }
+    return hipSuccess;
+  }
+};
+
+#define PROF_TRY(P, CLS, expr)     \
+  do {                             \
+    HIP_TRY((P).begin(CLS));       \
+    HIP_TRY(expr);                 \
+    HIP_TRY((P).end());            \
+  } while (0)
 
 // Core of dtw_align and dtw_align_batched.
 dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, const int64_t* yo, int d,
@@ -278,6 +338,8 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
     if (h) return DTW_ERR_NONFINITE;
   }
 
+  Profiler prof;
+  HIP_TRY(prof.init(opts.profile != 0 && stats != nullptr, st));
   Work w = make_work(L, ws, d, m, opts.precision);
   w.X = X;
   w.Y = Y;
@@ -286,13 +348,13 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   if (L.conv) {
     void* xc = at<void>(ws, L.xconv);
     void* yc = at<void>(ws, L.yconv);
-    HIP_TRY(launch_pad_convert(X, in_f64, xc, !f32, Mtot, d, L.D, st));
-    HIP_TRY(launch_pad_convert(Y, in_f64, yc, !f32, Ntot, d, L.D, st));
+    PROF_TRY(prof, kProfOther, launch_pad_convert(X, in_f64, xc, !f32, Mtot, d, L.D, st));
+    PROF_TRY(prof, kProfOther, launch_pad_convert(Y, in_f64, yc, !f32, Ntot, d, L.D, st));
     w.X = xc;
     w.Y = yc;
   }
   HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_init(w, st));
+  PROF_TRY(prof, kProfOther, launch_init(w, st));
 
   const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WAVES_PER_CU", 4));
   const int comb_grid = I.cus * 4;
@@ -301,13 +363,14 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   const int64_t lds_leaf_bytes = (int64_t)lds_bytes - (int64_t)cring_bytes;
   for (int lvl = 0; lvl <= L.lmax; ++lvl) {
     const int final_level = (lvl == L.lmax) ? 1 : 0;
-    HIP_TRY(launch_plan(w, lvl, final_level, lds_leaf_bytes, st));
+    PROF_TRY(prof, kProfPlan, launch_plan(w, lvl, final_level, lds_leaf_bytes, st));
     if (final_level) break;
-    HIP_TRY(launch_pass(w, lvl, f32, pass_grid, st));
-    HIP_TRY(launch_combine(w, comb_grid, st));
+    PROF_TRY(prof, kProfSweep, launch_pass(w, lvl, f32, pass_grid, st));
+    PROF_TRY(prof, kProfSplit, launch_combine(w, comb_grid, st));
   }
-  HIP_TRY(launch_leaf(w, f32, I.cus, lds_bytes, lds_leaf_bytes, X, Y, in_f64, st));
-  HIP_TRY(launch_assemble(w, at<int32_t>(ws, L.poff), at<int32_t>(ws, L.lidx), costs, lens, paths, I.cus * 2, st));
+  PROF_TRY(prof, kProfLeaf, launch_leaf(w, f32, I.cus, lds_bytes, lds_leaf_bytes, X, Y, in_f64, st));
+  PROF_TRY(prof, kProfOther,
+           launch_assemble(w, at<int32_t>(ws, L.poff), at<int32_t>(ws, L.lidx), costs, lens, paths, I.cus * 2, st));
 
   if (stats) {
     Ctl c{};
@@ -318,8 +381,19 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
     HIP_TRY(hipMemcpyAsync(&len, lens, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     memset(stats, 0, sizeof(*stats));
+    if (prof.on) {
+      double ms[kProfClasses];
+      HIP_TRY(prof.sums(ms));
+      stats->ms_sweep = ms[kProfSweep];
+      stats->ms_split = ms[kProfSplit];
+      stats->ms_plan = ms[kProfPlan];
+      stats->ms_leaf = ms[kProfLeaf];
+      stats->ms_other = ms[kProfOther];
+    }
     stats->s_min = smin;
-    stats->cells_processed = c.cells;
+    stats->cells_processed = c.cells + c.leaf_cells;
+    stats->sweep_cells = c.cells;
+    stats->leaf_cells = c.leaf_cells;
     stats->path_len = len;
     stats->workspace_bytes = (int64_t)L.total;
     stats->levels = c.levels_run;
@@ -340,6 +414,7 @@ void dtw_default_opts(dtw_opts* o) {
   o->precision = DTW_PREC_FP64;
   o->min_block = 500;
   o->validate_finite = 0;
+  o->profile = 0;
 }
 
 const char* dtw_status_string(int32_t s) {

@@ -22,6 +22,17 @@ __device__ __forceinline__ int64_t cells_upto(int64_t Mb, int64_t Nb, int64_t k)
 
 __device__ __forceinline__ void set_error(Ctl* ctl, int32_t code) { atomicCAS(&ctl->error, 0, code); }
 
+// A work count read from the control block, clamped to the capacity the host
+// planned for it: every device loop takes its trip count from such a value,
+// so no corrupted count can make a kernel run away.
+__device__ __forceinline__ int clamp_count(Ctl* ctl, int32_t v, int64_t cap) {
+  if (v < 0 || v > cap) {
+    set_error(ctl, kErrBadCount);
+    return v < 0 ? 0 : (int)cap;
+  }
+  return v;
+}
+
 // Error-free transformation a + b = s + e (Knuth's TwoSum).
 __device__ __forceinline__ double2 two_sum_acc(double2 acc, double v) {
   const double s = acc.x + v;

@@ -18,6 +18,7 @@ constexpr int kRing = 2;         // boundary-row slots per sweep (see pass kerne
 constexpr int kBandChunk = 256;  // band cells per split-cost work item
 constexpr int kMaxMinBlock = 1024;
 constexpr int kLeafThreads = 64;
+constexpr uint32_t kSpinIterCap = 1u << 26;  // flag polls before a wait gives up
 
 struct Block {
   int32_t i0, j0, i1, j1;  // inclusive, global frame indices
@@ -69,7 +70,8 @@ struct Ctl {
   int32_t leaf_ticket;  // leaf-kernel dequeue counter
   int32_t max_stripes;  // largest n_stripes of the current level
   int64_t leaf_words;   // leaf scratch words handed out
-  int64_t cells;        // cells evaluated (sweeps + leaf tables)
+  int64_t cells;        // cells evaluated by the sweeps
+  int64_t leaf_cells;   // cells of the leaf tables
 };
 
 enum DeviceError : int32_t {
@@ -84,6 +86,8 @@ enum DeviceError : int32_t {
   kErrSpinTimeout = 9,
   kErrBadPivot = 10,
   kErrBadLeaf = 11,
+  kErrBadPass = 12,
+  kErrBadCount = 13,
 };
 
 // Capacities chosen by the host planner (see plan_workspace in dtw_api.hip).

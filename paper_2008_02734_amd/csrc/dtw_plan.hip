@@ -62,7 +62,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
   __shared__ int32_t s_max_stripes;
   Ctl* ctl = w.ctl;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int n_prev = (level == 0) ? 0 : ctl->n_sub;
+  const int n_prev = (level == 0) ? 0 : clamp_count(ctl, ctl->n_sub, w.caps.sub);
   const int64_t n_cand = (level == 0) ? (int64_t)w.n_pairs : 2 * (int64_t)n_prev;
   const Block* prev = w.subs[(level + 1) & 1];
   Block* cur = w.subs[level & 1];
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
   if (tid == 0) s_max_stripes = 0;
   __syncthreads();
 
-  int64_t leaf_base = ctl->n_leaf, sub_base = 0, words_base = ctl->leaf_words;
+  int64_t leaf_base = clamp_count(ctl, ctl->n_leaf, w.caps.leaf), sub_base = 0, words_base = ctl->leaf_words;
   for (int64_t tile = 0; tile < n_cand; tile += nt) {
     const int64_t ci = tile + tid;
     const bool valid = ci < n_cand;
@@ -289,9 +289,14 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
 // each block as the bits of a non-negative double (monotone as uint64).
 __global__ __launch_bounds__(kBandChunk) void combine_min_kernel(Work w) {
   __shared__ uint64_t red[kBandChunk];
-  const int n_chunks = w.ctl->n_chunks;
+  const int n_chunks = clamp_count(w.ctl, w.ctl->n_chunks, w.caps.chunk);
+  const int n_sub = clamp_count(w.ctl, w.ctl->n_sub, w.caps.sub);
   for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-    const int s = w.chunk_sub[c];
+    int s = w.chunk_sub[c];
+    if (s < 0 || s >= n_sub) {
+      if (threadIdx.x == 0) set_error(w.ctl, kErrBadCount);
+      s = 0;
+    }
     const PassDesc P = w.passes[2 * s];
     const int64_t slot = (int64_t)c * kBandChunk + threadIdx.x - P.band_off;
     uint64_t key = ~0ull;
@@ -321,9 +326,14 @@ __global__ __launch_bounds__(kBandChunk) void combine_min_kernel(Work w) {
 // row), packed as (q << 32) | row with q = diagonal - (kf - 2).
 __global__ __launch_bounds__(kBandChunk) void combine_argmin_kernel(Work w) {
   __shared__ uint64_t red[kBandChunk];
-  const int n_chunks = w.ctl->n_chunks;
+  const int n_chunks = clamp_count(w.ctl, w.ctl->n_chunks, w.caps.chunk);
+  const int n_sub = clamp_count(w.ctl, w.ctl->n_sub, w.caps.sub);
   for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-    const int s = w.chunk_sub[c];
+    int s = w.chunk_sub[c];
+    if (s < 0 || s >= n_sub) {
+      if (threadIdx.x == 0) set_error(w.ctl, kErrBadCount);
+      s = 0;
+    }
     const PassDesc P = w.passes[2 * s];
     const uint64_t target = w.piv_key[s];
     const int64_t slot = (int64_t)c * kBandChunk + threadIdx.x - P.band_off;
@@ -364,10 +374,12 @@ __global__ __launch_bounds__(1024) void scan_kernel(Work w, int32_t* poff, int32
   const int64_t lo = min(n, tid * per), hi = min(n, lo + per);
   int64_t local = 0;
   double2 acc = make_double2(0.0, 0.0);
+  const int n_leaf = clamp_count(w.ctl, w.ctl->n_leaf, w.caps.leaf);
   for (int64_t e = lo; e < hi; ++e) {
     const int c = w.cnt[pd.pbase + e];
     local += c;
-    if (c > 0) acc = dd_add(acc, w.leaf_cost[lidx[pd.pbase + e]]);
+    const int l = lidx[pd.pbase + e];
+    if (c > 0 && l >= 0 && l < n_leaf) acc = dd_add(acc, w.leaf_cost[l]);
   }
   int64_t total;
   int64_t run = block_excl_scan(local, tmp, &total);
@@ -388,13 +400,16 @@ __global__ __launch_bounds__(1024) void scan_kernel(Work w, int32_t* poff, int32
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(Work w, const int32_t* poff, int32_t* paths_out) {
-  const int n_leaf = w.ctl->n_leaf;
+  const int n_leaf = clamp_count(w.ctl, w.ctl->n_leaf, w.caps.leaf);
   for (int l = blockIdx.x; l < n_leaf; l += gridDim.x) {
     const LeafDesc Lf = w.leaves[l];
+    if (Lf.pair < 0 || Lf.pair >= w.n_pairs) continue;
     const PairDesc pd = w.pairs[Lf.pair];
     const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
+    if (e < 0 || e >= pd.M + pd.N - 1) continue;
     const int64_t slot_end = pd.pbase + e;
-    const int c = w.cnt[slot_end];
+    int c = w.cnt[slot_end];
+    if (c < 0 || c > e + 1 || poff[slot_end] + (int64_t)c > pd.M + pd.N - 1) c = 0;
     const int64_t o = pd.out_off + poff[slot_end];
     int2* out = reinterpret_cast<int2*>(paths_out);
     for (int q = threadIdx.x; q < c; q += blockDim.x) out[o + q] = w.tpath[slot_end - c + 1 + q];
@@ -403,11 +418,13 @@ __global__ __launch_bounds__(256) void copy_kernel(Work w, const int32_t* poff, 
 
 // leaf index by end diagonal, for the cost sum in path order
 __global__ void leaf_index_kernel(Work w, int32_t* lidx) {
-  const int n_leaf = w.ctl->n_leaf;
+  const int n_leaf = clamp_count(w.ctl, w.ctl->n_leaf, w.caps.leaf);
   for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < n_leaf; l += gridDim.x * blockDim.x) {
     const LeafDesc Lf = w.leaves[l];
+    if (Lf.pair < 0 || Lf.pair >= w.n_pairs) continue;
     const PairDesc pd = w.pairs[Lf.pair];
-    lidx[pd.pbase + (Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off)] = l;
+    const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
+    if (e >= 0 && e < pd.M + pd.N - 1) lidx[pd.pbase + e] = l;
   }
 }
 

@@ -89,9 +89,10 @@ __device__ __forceinline__ void fetch_chunk(const T* ring_in, const uint32_t* fl
   const int ch = col / kChunkCols;
   if (__hip_atomic_load(flag_in + ch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != tag) {
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(flag_in + ch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+    for (uint32_t it = 0;; ++it) {
+      if (__hip_atomic_load(flag_in + ch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == tag) break;
       __builtin_amdgcn_s_sleep(2);
-      if (wall_clock64() - t0 > w.spin_ticks) {
+      if (wall_clock64() - t0 > w.spin_ticks || it > kSpinIterCap) {
         set_error(w.ctl, kErrSpinTimeout);
         break;
       }
@@ -108,18 +109,29 @@ __global__ __launch_bounds__(kWave) void pass_kernel(const T* __restrict__ X, co
   __shared__ T bring[kWave];          // boundary row, [column & 63]
   const int lane = threadIdx.x;
   Ctl* ctl = w.ctl;
-  const int n_tickets = ctl->n_tickets;
+  const int n_tickets = clamp_count(ctl, ctl->n_tickets, w.caps.ticket);
+  const int n_pass = clamp_count(ctl, ctl->n_pass, 2 * w.caps.sub);
   const T INF = inf_t<T>();
 
-  for (;;) {
+  for (int iter = 0; iter <= n_tickets; ++iter) {  // each iteration consumes one ticket
     int tk = 0;
     if (lane == 0) tk = atomicAdd(&ctl->ticket, 1);
     tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
-    if (tk >= n_tickets) break;
+    if (tk >= n_tickets || tk < 0) break;
     const int2 tv = w.tickets[tk];
     const int p = __builtin_amdgcn_readfirstlane(tv.x);
     const int s = __builtin_amdgcn_readfirstlane(tv.y);
+    if (p < 0 || p >= n_pass) {
+      if (lane == 0) set_error(ctl, kErrBadPass);
+      continue;
+    }
     const PassDesc P = w.passes[p];
+    if (P.Mb != P.i1 - P.i0 + 1 || P.Nb != P.j1 - P.j0 + 1 || P.Mb < 1 || P.Nb < 1 || P.kstop < 0 ||
+        P.kstop > P.Mb + P.Nb - 2 || P.n_rows != min(P.Mb - 1, P.kstop) + 1 || s < 0 || s >= P.n_stripes ||
+        P.n_stripes != (P.n_rows + kWave - 1) / kWave) {
+      if (lane == 0) set_error(ctl, kErrBadPass);
+      continue;
+    }
 
     const int a0 = s * kWave;
     const int a = a0 + lane;
@@ -225,18 +237,24 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(const T* __restrict_
   uint32_t* lds_free = reinterpret_cast<uint32_t*>(bring + kWave);
   const int lane = threadIdx.x;
   Ctl* ctl = w.ctl;
-  const int n_leaf = ctl->n_leaf;
+  const int n_leaf = clamp_count(ctl, ctl->n_leaf, w.caps.leaf);
   const T INF = inf_t<T>();
 
-  for (;;) {
+  for (int iter = 0; iter <= n_leaf; ++iter) {  // each iteration consumes one ticket
     int tk = 0;
     if (lane == 0) tk = atomicAdd(&ctl->leaf_ticket, 1);
     tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
-    if (tk >= n_leaf) break;
+    if (tk >= n_leaf || tk < 0) break;
     const LeafDesc Lf = w.leaves[tk];
+    if (Lf.pair < 0 || Lf.pair >= w.n_pairs) {
+      if (lane == 0) set_error(ctl, kErrBadLeaf);
+      continue;
+    }
     const PairDesc pd = w.pairs[Lf.pair];
     const int Mb = Lf.i1 - Lf.i0 + 1, Nb = Lf.j1 - Lf.j0 + 1;
-    if (Mb < 1 || Nb < 1) {  // never produced by the planner; refuse rather than loop
+    // a leaf lies inside its pair and is non-empty; refuse anything else
+    if (Mb < 1 || Nb < 1 || Lf.i0 < pd.x_off || Lf.j0 < pd.y_off || Lf.i1 >= pd.x_off + pd.M ||
+        Lf.j1 >= pd.y_off + pd.N) {
       if (lane == 0) set_error(ctl, kErrBadLeaf);
       continue;
     }
@@ -333,7 +351,7 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(const T* __restrict_
         else { if (tr) --ri; else --cj; }
       }
       w.cnt[slot_end] = cnt_written;
-      atomicAdd((unsigned long long*)&ctl->cells, (unsigned long long)((int64_t)R * Cc));
+      atomicAdd((unsigned long long*)&ctl->leaf_cells, (unsigned long long)((int64_t)R * Cc));
       if (Lf.first && Lf.i1 == pd.x_off + pd.M - 1 && Lf.j1 == pd.y_off + pd.N - 1)
         w.smin[Lf.pair] = (double)fend;
     }

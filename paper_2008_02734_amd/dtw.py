@@ -32,15 +32,19 @@ class DtwError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("min_block", ctypes.c_int32),
-                ("validate_finite", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("validate_finite", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("s_min", ctypes.c_double), ("cost_lowp", ctypes.c_double),
                 ("cells_processed", ctypes.c_int64), ("path_len", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64), ("sweep_cells", ctypes.c_int64),
+                ("leaf_cells", ctypes.c_int64), ("levels", ctypes.c_int32),
                 ("leaves", ctypes.c_int32), ("device_error", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("reserved", ctypes.c_int32 * 3), ("ms_sweep", ctypes.c_double),
+                ("ms_split", ctypes.c_double), ("ms_plan", ctypes.c_double),
+                ("ms_leaf", ctypes.c_double), ("ms_other", ctypes.c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -85,12 +89,13 @@ def lib():
     return _lib
 
 
-def make_opts(precision="fp64", min_block=500, validate_finite=False):
+def make_opts(precision="fp64", min_block=500, validate_finite=False, profile=False):
     o = Opts()
     lib().dtw_default_opts(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.min_block = int(min_block)
     o.validate_finite = 1 if validate_finite else 0
+    o.profile = 1 if profile else 0
     return o
 
 

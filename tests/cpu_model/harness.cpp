@@ -16,6 +16,12 @@ thread_local dim3_cpu threadIdx, blockIdx, blockDim, gridDim;
 thread_local std::barrier<>* cpu_block_barrier = nullptr;
 
 #include "dtw_plan_kernels.inc"
+#ifdef MODEL_WAVE
+#include "wave_shim.h"
+uint64_t cpu_wave_slots[64];
+alignas(16) unsigned char cpu_dynamic_lds[163840];
+#include "dtw_wave_kernels.inc"
+#endif
 
 #define MODEL_CHECK(cond)                                                      \
   do {                                                                         \
@@ -45,6 +51,39 @@ static T model_cost(const T* x, const T* y, int D) {
     s = std::fma(e, e, s);
   }
   return std::sqrt(s);
+}
+
+static void model_check_queue(const Work& w) {
+  Ctl* ctl = w.ctl;
+  const int n_t = ctl->n_tickets, n_pass = ctl->n_pass;
+  MODEL_CHECK(n_pass >= 0 && n_pass <= 2 * w.caps.sub);
+  MODEL_CHECK(n_t >= 0 && n_t <= w.caps.ticket);
+  std::vector<std::vector<int>> seen(n_pass);
+  for (int p = 0; p < n_pass; ++p) seen[p].assign(w.passes[p].n_stripes, 0);
+  int last_s = 0;
+  for (int t = 0; t < n_t; ++t) {
+    const int2 tv = w.tickets[t];
+    MODEL_CHECK(tv.x >= 0 && tv.x < n_pass);
+    MODEL_CHECK(tv.y >= 0 && tv.y < w.passes[tv.x].n_stripes);
+    MODEL_CHECK(tv.y >= last_s);
+    last_s = tv.y;
+    seen[tv.x][tv.y] += 1;
+  }
+  for (int p = 0; p < n_pass; ++p)
+    for (int c : seen[p]) MODEL_CHECK(c == 1);
+}
+
+static void model_check_leaves(const Work& w) {
+  const int n_leaf = w.ctl->n_leaf;
+  MODEL_CHECK(n_leaf >= 0 && n_leaf <= w.caps.leaf);
+  for (int l = 0; l < n_leaf; ++l) {
+    const LeafDesc Lf = w.leaves[l];
+    MODEL_CHECK(Lf.pair >= 0 && Lf.pair < w.n_pairs);
+    const PairDesc pd = w.pairs[Lf.pair];
+    const int Mb = Lf.i1 - Lf.i0 + 1, Nb = Lf.j1 - Lf.j0 + 1;
+    MODEL_CHECK(Mb >= 1 && Nb >= 1);
+    MODEL_CHECK(Lf.i0 >= pd.x_off && Lf.i1 < pd.x_off + pd.M && Lf.j0 >= pd.y_off && Lf.j1 < pd.y_off + pd.N);
+  }
 }
 
 template <typename T>
@@ -187,13 +226,49 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
     }
     w.cnt[slot_end] = cnt;
     w.leaf_cost[l] = make_double2(cost, 0.0);
-    ctl->cells += (int64_t)Mb * Nb;
+    ctl->leaf_cells += (int64_t)Mb * Nb;
     if (Lf.first && Lf.i1 == pd.x_off + pd.M - 1 && Lf.j1 == pd.y_off + pd.N - 1)
       w.smin[Lf.pair] = (double)F[(size_t)Mb * Nb - 1];
   }
   ctl->leaf_ticket = n_leaf;
 }
 
+#ifdef MODEL_WAVE
+// The real wave kernels, one wave per workgroup, workgroups in sequence: the
+// first workgroup dequeues every stripe in queue order, so each stripe's
+// predecessor has published its boundary row before the stripe waits on it.
+#define MODEL_DISPATCH(D_VAR, CALL)                                 \
+  switch (D_VAR) {                                                  \
+    case 4: { constexpr int D_ = 4; CALL; } break;                 \
+    case 8: { constexpr int D_ = 8; CALL; } break;                 \
+    case 12: { constexpr int D_ = 12; CALL; } break;               \
+    case 16: { constexpr int D_ = 16; CALL; } break;               \
+    case 24: { constexpr int D_ = 24; CALL; } break;               \
+    case 32: { constexpr int D_ = 32; CALL; } break;               \
+    default: std::abort();                                          \
+  }
+hipError_t launch_pass(const Work& w, int level, bool f32, int, hipStream_t) {
+  model_check_queue(w);
+  const int D = pick_dmax(w.d);
+  if (f32) {
+    MODEL_DISPATCH(D, (cpu_launch(2, kWave, [&] { pass_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, level); })))
+  } else {
+    MODEL_DISPATCH(D, (cpu_launch(2, kWave, [&] { pass_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, level); })))
+  }
+  return hipSuccess;
+}
+hipError_t launch_leaf(const Work& w, bool f32, int, size_t, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
+                       int in_f64, hipStream_t) {
+  model_check_leaves(w);
+  const int D = pick_dmax(w.d);
+  if (f32) {
+    MODEL_DISPATCH(D, (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  } else {
+    MODEL_DISPATCH(D, (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  }
+  return hipSuccess;
+}
+#else
 hipError_t launch_pass(const Work& w, int, bool f32, int, hipStream_t) {
   if (f32) model_pass<float>(w);
   else model_pass<double>(w);
@@ -205,6 +280,7 @@ hipError_t launch_leaf(const Work& w, bool f32, int, size_t, int64_t, const void
   else model_leaf<double>(w, Xo, Yo, in_f64);
   return hipSuccess;
 }
+#endif
 hipError_t set_leaf_lds_limit(size_t) { return hipSuccess; }
 
 hipError_t launch_init(const Work& w, hipStream_t) {

@@ -1,0 +1,62 @@
+// Wave-level stand-ins for the CPU model (tests only): a workgroup of the
+// wave kernels is one 64-lane wave, run as 64 threads; every cross-lane
+// operation is an exchange through a shared slot array between two barrier
+// waits, which is exact for code where all 64 lanes reach the operation
+// together (the kernels only use them in converged code).
+#pragma once
+#include <chrono>
+#include <cstring>
+
+#include "hip/hip_runtime.h"
+
+extern thread_local uint64_t cpu_wave_slots_dummy;
+extern uint64_t cpu_wave_slots[64];
+extern unsigned char cpu_dynamic_lds[];
+
+template <class T>
+inline T cpu_wave_exchange(T v, int src) {
+  uint64_t bits = 0;
+  std::memcpy(&bits, &v, sizeof(T));
+  cpu_wave_slots[threadIdx.x] = bits;
+  cpu_block_barrier->arrive_and_wait();
+  const uint64_t r = cpu_wave_slots[src & 63];
+  cpu_block_barrier->arrive_and_wait();
+  T out;
+  std::memcpy(&out, &r, sizeof(T));
+  return out;
+}
+
+inline int cpu_update_dpp(int old, int src, int ctrl) {
+  if (ctrl != 0x138) std::abort();  // only wave_shr:1 is used
+  const int v = cpu_wave_exchange(src, (int)threadIdx.x - 1);
+  return threadIdx.x == 0 ? old : v;
+}
+
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) cpu_update_dpp((old), (src), (ctrl))
+#define __builtin_amdgcn_readfirstlane(v) cpu_wave_exchange((int)(v), 0)
+#define __builtin_amdgcn_readlane(v, l) cpu_wave_exchange((int)(v), (int)(l))
+#define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
+#define __builtin_amdgcn_s_barrier() cpu_block_barrier->arrive_and_wait()
+#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_sqrtf(x) std::sqrt((float)(x))
+#define __HIP_MEMORY_SCOPE_AGENT 0
+#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
+#define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
+
+template <class T> inline T __shfl(T v, int src) { return cpu_wave_exchange(v, src); }
+template <class T> inline T __shfl_xor(T v, int mask) { return cpu_wave_exchange(v, (int)threadIdx.x ^ mask); }
+
+inline int __double2loint(double d) { uint64_t b; std::memcpy(&b, &d, 8); return (int)(uint32_t)b; }
+inline int __double2hiint(double d) { uint64_t b; std::memcpy(&b, &d, 8); return (int)(uint32_t)(b >> 32); }
+inline double __hiloint2double(int hi, int lo) {
+  const uint64_t b = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+  double d;
+  std::memcpy(&d, &b, 8);
+  return d;
+}
+inline int __float_as_int(float f) { int i; std::memcpy(&i, &f, 4); return i; }
+inline float __int_as_float(int i) { float f; std::memcpy(&f, &i, 4); return f; }
+inline uint64_t wall_clock64() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch()).count() / 10;
+}

@@ -25,21 +25,49 @@ MODEL = os.path.join(ROOT, "tests", "cpu_model")
 MARK = "// ----------------------------------------------------------------- launchers"
 
 
-@pytest.fixture(scope="module")
-def model_exe(tmp_path_factory):
-    d = tmp_path_factory.mktemp("cpu_model")
+# The two textual edits the wave kernels need to compile for the host: the
+# inline-asm v_min becomes the same minimum in C++, and the dynamic LDS array
+# becomes a static buffer.
+WAVE_EDITS = [
+    ('asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));', "r = (b < a) ? b : a;"),
+    ('asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));', "r = (b < a) ? b : a;"),
+    ("extern __shared__ __align__(16) unsigned char lds_raw[];", "unsigned char* lds_raw = cpu_dynamic_lds;"),
+]
+
+
+def _build_model(d, wave):
     src = open(os.path.join(CSRC, "dtw_plan.hip")).read()
     assert MARK in src
     with open(d / "dtw_plan_kernels.inc", "w") as f:
         f.write(src[: src.index(MARK)] + "}  // namespace dtw\n")
-    exe = d / "cpu_model"
+    wsrc = open(os.path.join(CSRC, "dtw_wave.hip")).read()
+    body = wsrc[: wsrc.index(MARK)] + "}  // namespace dtw\n"
+    for old, new in WAVE_EDITS:
+        assert old in body, old
+        body = body.replace(old, new)
+    body = body.replace('#include "dtw_common.h"', "")
+    with open(d / "dtw_wave_kernels.inc", "w") as f:
+        f.write(body)
+    exe = d / ("cpu_model_wave" if wave else "cpu_model")
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-fno-omit-frame-pointer", "-Wno-unknown-pragmas", "-pthread",
            "-I", MODEL, "-I", str(d), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(MODEL, "harness.cpp"), os.path.join(MODEL, "driver.cpp"),
            "-x", "c++", os.path.join(CSRC, "dtw_api.hip"), "-o", str(exe)]
+    if wave:
+        cmd.insert(1, "-DMODEL_WAVE")
     subprocess.run(cmd, check=True)
     return str(exe)
+
+
+@pytest.fixture(scope="module")
+def model_exe(tmp_path_factory):
+    return _build_model(tmp_path_factory.mktemp("cpu_model"), wave=False)
+
+
+@pytest.fixture(scope="module")
+def wave_exe(tmp_path_factory):
+    return _build_model(tmp_path_factory.mktemp("cpu_model_wave"), wave=True)
 
 
 def run_model(exe, pairs, m, precision=0):
@@ -106,3 +134,18 @@ def test_model_batched(model_exe):
         c_ref, p_ref = oracle.full(X, Y)
         assert path.tolist() == p_ref.tolist()
         assert abs(cost - c_ref) <= 1e-12 * c_ref
+
+
+WAVE_CASES = [(37, 29, 3, 3), (70, 50, 12, 16), (130, 90, 5, 3), (20, 300, 4, 16), (9, 9, 2, 500)]
+
+
+@pytest.mark.parametrize("M,N,d,m", WAVE_CASES)
+def test_wave_model_matches_oracle(wave_exe, M, N, d, m):
+    # the real sweep and leaf kernels, emulated lane by lane
+    X, Y = synth.random_pair(8000 + M + N, M, N, d, "normal")
+    r = run_model(wave_exe, [(X, Y)], m)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    cost, path = r["results"][0]
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
