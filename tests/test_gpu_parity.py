@@ -84,7 +84,7 @@ def check_path(path, M, N):
 
 ALIGN_CASES = [(s, M, N, d, m) for s, (M, N, d) in enumerate(
     [(37, 29, 3), (100, 80, 12), (129, 257, 5), (300, 240, 12), (513, 470, 24), (1000, 700, 12),
-     (64, 64, 1), (2, 300, 4), (300, 1, 4), (1, 1, 2)]) for m in (3, 16, 500)]
+     (64, 64, 2), (2, 300, 4), (300, 1, 4), (1, 1, 2)]) for m in (3, 16, 500)]
 
 # This case did not finish on the GPU twice (pytest's time limit ended the
 # process).  A missing barrier in the planner that produced empty leaves was
@@ -105,11 +105,27 @@ def test_align_matches_textbook_tie_free(dtw, s, M, N, d, m):
     path = path.cpu().numpy()
     check_path(path, M, N)
     c_ref, p_ref = oracle.full(X, Y)
-    assert path.tolist() == p_ref.tolist()
-    assert abs(cost - c_ref) <= 1e-12 * c_ref
     r = oracle.linmdtw(X, Y, min_block=m)
+    # the GPU runs Algorithm 2 with the oracle port's band and tie rule: same path
+    assert path.tolist() == r["path"].tolist()
+    # these inputs are tie-free, so that path is the textbook path
+    assert r["path"].tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
     assert st["cells_processed"] == r["cells"]
     assert abs(st["s_min"] - c_ref) <= 1e-12 * c_ref
+
+
+def test_exact_tie_continuous_d1(dtw):
+    # d = 1 continuous frames: |x - y| costs give an exact FP64 tie between two
+    # optimal paths on this input; the pivot rule follows the oracle's port of
+    # Algorithm 2, which leaves the textbook path at the same cell.
+    X, Y = synth.random_pair(8006, 64, 64, 1, "normal")
+    cost, path, _ = dtw.align(dev(X), dev(Y), min_block=3)
+    r = oracle.linmdtw(X, Y, min_block=3)
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.cpu().numpy().tolist() == r["path"].tolist()
+    assert r["path"].tolist() != p_ref.tolist() and r["cost"] == c_ref
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
 @pytest.mark.parametrize("seed", range(12))
