@@ -93,7 +93,7 @@ struct Layout {
   int cbytes = 8;  // bytes of the compute type
   int D = 0;       // padded frame stride of the compute copies
   Region ctl, pairs, subs0, subs1, piv_key, piv_pos, smin, passes, tickets, hist, chunk_sub, bandF, bandC,
-      bandB, ring, flags, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, nonfinite;
+      bandB, ring, gens, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, nonfinite;
   size_t total = 0;
 };
 
@@ -128,7 +128,7 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   c.band = (3 * K0sum) / 2 + (3 + kBandChunk) * c.sub + 3 * Mmax + kBandChunk;
   c.chunk = c.band / kBandChunk + c.sub + 1;
   c.ring = 2 * kRing * (Nsum + c.sub) + kRing * Mmax;
-  c.flag = 2 * kRing * ((Nsum + kChunkCols - 1) / kChunkCols + 2 * c.sub) + kRing * (Mmax / kChunkCols + 2);
+  c.gen = 2 * kRing * c.sub + kRing;
   c.ticket = 2 * ((Msum + kWave - 1) / kWave + 2 * c.sub) + Mmax / kWave + 2;
   c.hist = Mmax / kWave + 3;
   c.leaf_words = ((int64_t)m * (K0sum + c.leaf)) / 16 + ((int64_t)m + 4) * c.leaf + 2 * (K0sum + c.leaf) + 16;
@@ -151,8 +151,8 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   put(L, L.bandF, 8 * c.band);
   put(L, L.bandC, 8 * c.band);
   put(L, L.bandB, 8 * c.band);
-  put(L, L.ring, 8 * c.ring);
-  put(L, L.flags, 4 * c.flag);
+  put(L, L.ring, (size_t)L.cbytes * c.ring);
+  put(L, L.gens, 4 * (size_t)c.gen);
   put(L, L.leaves, sizeof(LeafDesc) * c.leaf);
   put(L, L.leaf_scratch, 4 * c.leaf_words);
   put(L, L.tpath, 8 * c.pslots);
@@ -194,7 +194,8 @@ Work make_work(const Layout& L, void* ws, int d, int m, int precision) {
   w.bandC = at<double>(ws, L.bandC);
   w.bandB = at<double>(ws, L.bandB);
   w.ring = at<void>(ws, L.ring);
-  w.flags = at<uint32_t>(ws, L.flags);
+  w.ring_f32 = L.cbytes == 4 ? 1 : 0;
+  w.gens = at<uint32_t>(ws, L.gens);
   w.leaves = at<LeafDesc>(ws, L.leaves);
   w.leaf_scratch = at<uint32_t>(ws, L.leaf_scratch);
   w.tpath = at<int2>(ws, L.tpath);
@@ -343,7 +344,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   Work w = make_work(L, ws, d, m, opts.precision);
   w.X = X;
   w.Y = Y;
-  // one flag wait may last at most DTW_SPIN_LIMIT_MS (default 20 s)
+  // one boundary wait may last at most DTW_SPIN_LIMIT_MS (default 20 s)
   w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
   if (L.conv) {
     void* xc = at<void>(ws, L.xconv);
@@ -356,7 +357,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
   PROF_TRY(prof, kProfOther, launch_init(w, st));
 
-  const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WAVES_PER_CU", 4));
+  const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WG_PER_CU", 2));
   const int comb_grid = I.cus * 4;
   const size_t cring_bytes = (size_t)L.cbytes * (kWave * kWave + kWave);
   const size_t lds_bytes = (size_t)I.lds_max;

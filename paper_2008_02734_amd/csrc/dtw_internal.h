@@ -13,12 +13,25 @@
 namespace dtw {
 
 constexpr int kWave = 64;        // gfx950 wavefront width; one lane per DP row
-constexpr int kChunkCols = 32;   // boundary-row columns published per flag
 constexpr int kRing = 2;         // boundary-row slots per sweep (see pass kernel)
 constexpr int kBandChunk = 256;  // band cells per split-cost work item
 constexpr int kMaxMinBlock = 1024;
 constexpr int kLeafThreads = 64;
-constexpr uint32_t kSpinIterCap = 1u << 26;  // flag polls before a wait gives up
+constexpr uint32_t kSpinIterCap = 1u << 26;  // polls before a wait gives up
+
+// Pass kernel workgroup: one recurrence wave, kProducers frame-cost waves and
+// one boundary-input wave; phases of kPhase steps between barriers.
+constexpr int kProducers = 8;
+constexpr int kPassThreads = kWave * (kProducers + 2);
+constexpr int kPhase = 32;
+constexpr int kCostRing = 128;  // LDS cost slots, indexed by step
+constexpr int kPubGroup = 16;   // steps per boundary-row publication
+
+// Content of a boundary-ring cell that has not been written: a signalling
+// NaN.  No arithmetic result is a signalling NaN, so a cell holding any other
+// bit pattern carries a published value.
+constexpr uint64_t kRingEmpty64 = 0xFFF7A5A5A5A5A5A5ull;
+constexpr uint32_t kRingEmpty32 = 0xFFA5A5A5u;
 
 struct Block {
   int32_t i0, j0, i1, j1;  // inclusive, global frame indices
@@ -47,7 +60,7 @@ struct PassDesc {
   int32_t pad;
   int64_t band_off;   // element offset of the block's 3*L band slots
   int64_t ring_off;   // element offset of the kRing boundary rows (kRing*Nb)
-  int64_t flag_off;   // offset of the chunk flags (kRing*ceil(Nb/kChunkCols))
+  int64_t gen_off;    // offset of the kRing generation words of the rows
 };
 
 struct LeafDesc {
@@ -97,7 +110,7 @@ struct Caps {
   int64_t leaf;      // leaves over all levels
   int64_t band;      // band slots per level
   int64_t ring;      // boundary-row elements per level
-  int64_t flag;      // flags per level
+  int64_t gen;       // boundary-row generation words per level
   int64_t ticket;    // stripes per level
   int64_t chunk;     // band work items per level
   int64_t hist;      // histogram bins (max stripes + 1)
@@ -127,14 +140,15 @@ struct Work {
   double* bandF;        // forward accumulated cost on the band (S after combine)
   double* bandC;        // frame cost on the band
   double* bandB;        // backward accumulated cost on the band
-  void* ring;           // boundary rows, compute type
-  uint32_t* flags;
+  void* ring;           // boundary rows, compute type (cells empty between levels)
+  int32_t ring_f32;     // 1: ring cells are float, else double
+  uint32_t* gens;       // per boundary row: tag of the stripe that owns it
   LeafDesc* leaves;
   uint32_t* leaf_scratch;
   int2* tpath;          // diagonal-indexed path scratch
   int32_t* cnt;         // cells written by the leaf that ends on this diagonal
   double2* leaf_cost;   // per leaf (hi, lo) compensated sum
-  uint64_t spin_ticks;  // bound on one flag wait, device wall-clock ticks
+  uint64_t spin_ticks;  // bound on one boundary wait, device wall-clock ticks
   Caps caps;
 };
 

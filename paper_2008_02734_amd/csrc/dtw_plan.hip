@@ -41,7 +41,14 @@ __global__ void init_kernel(Work w) {
     Ctl c = {};
     *w.ctl = c;
   }
-  for (int64_t u = tid; u < w.caps.flag; u += nt) w.flags[u] = 0u;
+  for (int64_t u = tid; u < w.caps.gen; u += nt) w.gens[u] = 0u;
+  if (w.ring_f32) {
+    uint32_t* r = static_cast<uint32_t*>(w.ring);
+    for (int64_t u = tid; u < w.caps.ring; u += nt) r[u] = kRingEmpty32;
+  } else {
+    uint64_t* r = static_cast<uint64_t*>(w.ring);
+    for (int64_t u = tid; u < w.caps.ring; u += nt) r[u] = kRingEmpty64;
+  }
   for (int64_t u = tid; u < w.caps.pslots; u += nt) w.cnt[u] = 0;
   for (int64_t u = tid; u < w.n_pairs; u += nt) w.smin[u] = __builtin_nan("");
 }
@@ -53,8 +60,8 @@ __global__ void init_kernel(Work w) {
 //    previous level, read from its pivot (both children contain the pivot);
 //  - a candidate whose shorter side is below m becomes a leaf;
 //  - every other candidate gets a forward sweep to kf = ceil(K/2) and a
-//    backward sweep to kb = kf + [K even] (K = Mb + Nb - 1), band slots, a
-//    boundary-row ring and flags, and its stripes enter the level's queue in
+//    backward sweep to kb = kf + [K even] (K = Mb + Nb - 1), band slots and
+//    a boundary-row ring per sweep, and its stripes enter the level's queue in
 //    stripe-major order.
 __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final_level,
                                                     int64_t lds_leaf_bytes) {
@@ -154,12 +161,12 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
   if (final_level && n_sub > 0 && tid == 0) set_error(ctl, kErrNotLeafAtEnd);
   const int n_sub_run = final_level ? 0 : n_sub;
 
-  // sweep descriptors, band slots, rings, flags
-  int64_t chunk_base = 0, ring_base = 0, flag_base = 0;
+  // sweep descriptors, band slots, rings
+  int64_t chunk_base = 0, ring_base = 0;
   for (int64_t tile = 0; tile < n_sub_run; tile += nt) {
     const int64_t s = tile + tid;
     const bool valid = s < n_sub_run;
-    int64_t nchunk = 0, ring_e = 0, flag_e = 0;
+    int64_t nchunk = 0, ring_e = 0;
     Block c = {0, 0, 0, 0, 0, 0};
     if (valid) {
       c = cur[s];
@@ -167,12 +174,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       const int64_t L = min(Mb, Nb);
       nchunk = (3 * L + kBandChunk - 1) / kBandChunk;
       ring_e = 2 * kRing * Nb;  // forward sweep, then backward sweep
-      flag_e = 2 * kRing * ((Nb + kChunkCols - 1) / kChunkCols);
     }
-    int64_t tc, tr, tf;
+    int64_t tc, tr;
     const int64_t cb = block_excl_scan(nchunk, tmp, &tc);
     const int64_t rb = block_excl_scan(ring_e, tmp, &tr);
-    const int64_t fb = block_excl_scan(flag_e, tmp, &tf);
     if (valid) {
       const int Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
       const int K = Mb + Nb - 1;
@@ -186,16 +191,16 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       P.L = min(Mb, Nb);
       P.band_off = (chunk_base + cb) * kBandChunk;
       P.ring_off = ring_base + rb;
-      P.flag_off = flag_base + fb;
+      P.gen_off = 2 * kRing * s;
       const bool ok = (P.band_off + nchunk * kBandChunk <= w.caps.band) &&
-                      (P.ring_off + ring_e <= w.caps.ring) && (P.flag_off + flag_e <= w.caps.flag) &&
-                      (chunk_base + cb + nchunk <= w.caps.chunk);
+                      (P.ring_off + ring_e <= w.caps.ring) && (chunk_base + cb + nchunk <= w.caps.chunk) &&
+                      (P.gen_off + 2 * kRing <= w.caps.gen);
       if (!ok) set_error(ctl, kErrBandCap);
-      const int64_t ring0 = P.ring_off, flag0 = P.flag_off;
+      const int64_t ring0 = P.ring_off, gen0 = P.gen_off;
       for (int dir = 0; dir < 2; ++dir) {
         P.dir = dir;
         P.ring_off = ring0 + dir * (int64_t)kRing * Nb;
-        P.flag_off = flag0 + dir * (int64_t)kRing * ((Nb + kChunkCols - 1) / kChunkCols);
+        P.gen_off = gen0 + dir * kRing;
         P.kstop = dir ? kb : kf;
         P.n_rows = min(Mb - 1, P.kstop) + 1;
         P.n_stripes = ok ? (P.n_rows + kWave - 1) / kWave : 0;
@@ -211,7 +216,6 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
     }
     chunk_base += tc;
     ring_base += tr;
-    flag_base += tf;
   }
   __syncthreads();
 
@@ -463,7 +467,7 @@ __global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, in
   P.L = P.Mb;
   P.band_off = 0;
   P.ring_off = 0;
-  P.flag_off = 0;
+  P.gen_off = 0;
   w.passes[0] = P;
   for (int s = 0; s < P.n_stripes; ++s) w.tickets[s] = make_int2(0, s);
   c.n_tickets = P.n_stripes;

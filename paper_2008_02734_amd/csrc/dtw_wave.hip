@@ -62,159 +62,315 @@ __device__ __forceinline__ T frame_cost(const T (&x)[D], const T* __restrict__ y
   return sqrt_t(s);
 }
 
+// The same cost for two Y frames at once (each in the order above).
+template <typename T, int D>
+__device__ __forceinline__ void frame_cost2(const T (&x)[D], const T* __restrict__ y0, const T* __restrict__ y1,
+                                            T& c0, T& c1) {
+  T s0 = T(0), s1 = T(0);
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const T e0 = x[k] - y0[k];
+    const T e1 = x[k] - y1[k];
+    s0 = fma_t(e0, e0, s0);
+    s1 = fma_t(e1, e1, s1);
+  }
+  c0 = sqrt_t(s0);
+  c1 = sqrt_t(s1);
+}
+
 // ----------------------------------------------------------------- pass kernel
 //
-// One wave owns a stripe of 64 consecutive local rows of one sweep; lane r is
-// row a = 64*s + r.  At step t lane r evaluates column b = t - r, so the wave
-// advances along anti-diagonals exactly as Algorithm 1 does.  Each step:
-//   (A) the frame cost of column t for all 64 rows (the column's Y frame is
-//       wave-uniform and arrives through scalar loads), written to an LDS
-//       ring indexed by column;
-//   (B) the recurrence for cell (a, t - r): UP from lane r-1 by a DPP lane
-//       shift, DIAG = the UP value of the previous step, LEFT = own last value.
-// Row 64*s - 1 (the stripe above) arrives through a boundary row in HBM that
-// the previous stripe publishes kChunkCols columns at a time behind a flag.
-// Stripes are dequeued from a queue ordered stripe-major across all sweeps of
-// the level, so a stripe only ever waits on a stripe that was dequeued before
-// it by a running wave: the persistent grid cannot deadlock.
+// One workgroup owns a stripe of 64 consecutive local rows of one sweep and
+// splits the work of Algorithm 1 over three roles:
+//   wave 0      the recurrence.  Lane r is row a = a0 + r; at step t it
+//               evaluates column b = t - r, so every lane of step t lies on
+//               the diagonal k = a0 + t and the wave advances one diagonal
+//               per step.  UP comes from lane r-1 through a DPP lane shift
+//               (lane 0: the bottom row of the stripe above), DIAG is the
+//               previous step's UP and LEFT the lane's own previous value.
+//   waves 1..8  frame costs (Sec. 4.1) of whole columns, one phase ahead of
+//               the recurrence, into an LDS ring.  A column's Y frame is
+//               wave-uniform and arrives through scalar loads; the lane's X
+//               frame stays in registers.
+//   wave 9      boundary input: the bottom row of the stripe above, read from
+//               HBM one phase ahead into LDS.
+// Phases of kPhase steps are separated by workgroup barriers.
+//
+// Cost ring: lane r's cost for column j sits in slot (j + r) mod kCostRing,
+// so the recurrence reads slot t at step t (one address per step for the
+// whole wave).  At phase k the recurrence reads slots [32k, 32k+31] and the
+// producers write columns [32k+32, 32k+63], i.e. slots [32k+32, 32k+126]:
+// the two ranges never meet modulo 128.
+//
+// Bottom row hand-off between stripes: a per-sweep HBM ring of kRing rows
+// whose cells hold kRingEmpty until written.  Stripe s writes each value of
+// its bottom row into row s % 2 with a relaxed device-scope atomic store;
+// stripe s+1 polls each value it needs with relaxed device-scope loads until
+// it is not the empty pattern, then stores the empty pattern back and, at
+// the start of its next phase, waits for those stores to complete.  Every
+// value is its own flag, so neither side needs a fence.  Two orderings keep
+// a reused row correct (all chains below run through values one side
+// observed before it issued the next access):
+//  - writer: stripe s+2 writes column c of row s % 2 after computing its own
+//    column c, which needs column c of stripe s+1, which stripe s+1 computes
+//    at least one barrier after its input wave's reset of column c completed;
+//  - reader: stripe s+1 must not read row s % 2 before stripe s-1 has reset
+//    the values stripe s-2 left there.  Chunk p+1 is read only after chunk p
+//    of stripe s arrived, which stripe s computed after receiving column
+//    32p+31 of stripe s-1, published after stripe s-1's resets through chunk
+//    p+1 completed.  For chunk 0 the row's generation word stands in: stripe
+//    s sets it to its tag once it has received its first chunk from stripe
+//    s-1 (at once when s = 0), and stripe s+1 polls it before chunk 0.
+// Stripes are dequeued stripe-major across all sweeps of the level, so a
+// stripe only waits on a stripe that a running workgroup dequeued before it:
+// the persistent grid cannot deadlock.
 
-// Boundary row of the stripe above, kChunkCols columns starting at `col`:
-// wait for the chunk's flag, then copy it into the LDS ring `bring` that lane
-// 0 reads one value per step.  The wait is bounded by the device wall clock
-// (w.spin_ticks); on expiry the wave records an error and carries on, so a
-// broken protocol ends the kernel instead of hanging it.
-template <typename T>
-__device__ __forceinline__ void fetch_chunk(const T* ring_in, const uint32_t* flag_in, uint32_t tag, int col,
-                                            int Nb, T* bring, int lane, const Work& w) {
-  const int ch = col / kChunkCols;
-  if (__hip_atomic_load(flag_in + ch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+template <typename T> struct RingWord;
+template <> struct RingWord<double> {
+  using U = uint64_t;
+  static constexpr U kEmpty = kRingEmpty64;
+};
+template <> struct RingWord<float> {
+  using U = uint32_t;
+  static constexpr U kEmpty = kRingEmpty32;
+};
+
+// A wave-uniform integer moved into a vector register: LDS addresses built
+// from it keep their per-step parts as immediate offsets.
+__device__ __forceinline__ int in_vgpr(int x) {
+  int r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+
+constexpr int kStepGroup = 4;  // recurrence steps whose LDS operands are read together
+
+// Workgroup barrier that waits for this wave's LDS traffic only: global
+// stores in flight (boundary values, band cells) are not waited for.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// Wait until every global load and store of this wave has completed.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Poll one word until it holds a value other than `empty` (or, with
+// `until_equal`, until it equals `empty`'s argument taken as the target).
+// The wait is bounded by the device wall clock (w.spin_ticks) and an
+// iteration cap; on expiry the lane records an error and returns what it
+// read last, so a broken hand-off ends the kernel instead of hanging it.
+template <typename U>
+__device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_equal = false) {
+  U v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((v == empty) != until_equal) {
     const uint64_t t0 = wall_clock64();
     for (uint32_t it = 0;; ++it) {
-      if (__hip_atomic_load(flag_in + ch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == tag) break;
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((v == empty) == until_equal) break;
       if (wall_clock64() - t0 > w.spin_ticks || it > kSpinIterCap) {
         set_error(w.ctl, kErrSpinTimeout);
         break;
       }
     }
   }
-  const int c = col + lane;
-  if (lane < kChunkCols && c < Nb) bring[c & (kWave - 1)] = ring_in[c];
+  return v;
+}
+
+// Publish lane 63's values of the steps g0..t (g0 = t rounded down to a
+// multiple of kPubGroup) from the LDS history: lane 48+u stores step g0+u,
+// i.e. column g0 + u - 63 of the stripe's bottom row.
+template <typename T>
+__device__ __forceinline__ void publish(int t, int lane, const T* hist, typename RingWord<T>::U* ring_out,
+                                        int pub_max) {
+  const int st = (t & ~(kPubGroup - 1)) + (lane - (kWave - kPubGroup));
+  const int col = st - (kWave - 1);
+  if (lane >= kWave - kPubGroup && st <= t && col >= 0 && col <= pub_max) {
+    const T v = hist[(st & (kPubGroup - 1)) * kWave + (kWave - 1)];
+    __hip_atomic_store(ring_out + col, __builtin_bit_cast(typename RingWord<T>::U, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 template <typename T, int D>
-__global__ __launch_bounds__(kWave) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
-                                                     int level) {
-  __shared__ T cring[kWave * kWave];  // frame cost, [column & 63][lane]
-  __shared__ T bring[kWave];          // boundary row, [column & 63]
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+                                                            int level) {
+  using U = typename RingWord<T>::U;
+  __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
+  __shared__ T hist[kPubGroup * kWave];   // recurrence values of the last steps, [step & 15][lane]
+  __shared__ T bring[2 * kPhase];         // bottom row of the stripe above, [column & 63]
+  __shared__ int sh_ticket;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
   Ctl* ctl = w.ctl;
   const int n_tickets = clamp_count(ctl, ctl->n_tickets, w.caps.ticket);
   const int n_pass = clamp_count(ctl, ctl->n_pass, 2 * w.caps.sub);
   const T INF = inf_t<T>();
 
   for (int iter = 0; iter <= n_tickets; ++iter) {  // each iteration consumes one ticket
-    int tk = 0;
-    if (lane == 0) tk = atomicAdd(&ctl->ticket, 1);
-    tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
+    if (threadIdx.x == 0) sh_ticket = atomicAdd(&ctl->ticket, 1);
+    lds_barrier();
+    const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
+    lds_barrier();
     if (tk >= n_tickets || tk < 0) break;
     const int2 tv = w.tickets[tk];
     const int p = __builtin_amdgcn_readfirstlane(tv.x);
     const int s = __builtin_amdgcn_readfirstlane(tv.y);
     if (p < 0 || p >= n_pass) {
-      if (lane == 0) set_error(ctl, kErrBadPass);
+      if (threadIdx.x == 0) set_error(ctl, kErrBadPass);
       continue;
     }
     const PassDesc P = w.passes[p];
     if (P.Mb != P.i1 - P.i0 + 1 || P.Nb != P.j1 - P.j0 + 1 || P.Mb < 1 || P.Nb < 1 || P.kstop < 0 ||
         P.kstop > P.Mb + P.Nb - 2 || P.n_rows != min(P.Mb - 1, P.kstop) + 1 || s < 0 || s >= P.n_stripes ||
         P.n_stripes != (P.n_rows + kWave - 1) / kWave) {
-      if (lane == 0) set_error(ctl, kErrBadPass);
+      if (threadIdx.x == 0) set_error(ctl, kErrBadPass);
       continue;
     }
 
     const int a0 = s * kWave;
-    const int a = a0 + lane;
-    const int last_row = min(a0 + kWave - 1, P.n_rows - 1);
-    const bool row_ok = a <= last_row;
-    const int Lr = last_row - a0;
-    const int bmax_first = min(P.Nb - 1, P.kstop - a0);
-    const int bmax = row_ok ? min(P.Nb - 1, P.kstop - a) : -1;
+    const int Lr = min(kWave - 1, P.n_rows - 1 - a0);           // last lane with a row
+    const int need_max = min(P.Nb - 1, P.kstop - a0);           // last column of lane 0
     const int n_steps = min(P.Nb - 1 + Lr, P.kstop - a0) + 1;
-    const int K = P.Mb + P.Nb - 1;
-    const int jbase = P.dir ? P.j1 : P.j0;
-    const int jstep = P.dir ? -1 : 1;
-
-    T x[D];
-    {
-      const int gi = P.dir ? P.i1 - (row_ok ? a : 0) : P.i0 + (row_ok ? a : 0);
-      const T* xr = X + (int64_t)gi * D;
-#pragma unroll
-      for (int k = 0; k < D; ++k) x[k] = xr[k];
-    }
-
+    const int n_phases = (n_steps + kPhase - 1) / kPhase;
     const bool has_pred = s > 0;
     const bool has_succ = s + 1 < P.n_stripes;
-    const uint32_t my_tag = ((uint32_t)(level + 1) << 20) | (uint32_t)(s + 1);
-    const uint32_t pred_tag = my_tag - 1u;
-    const int nch = (P.Nb + kChunkCols - 1) / kChunkCols;
+    const int pub_max = has_succ ? min(P.Nb - 1, P.kstop - a0 - kWave) : -1;  // = need_max of stripe s+1
     T* ring = static_cast<T*>(w.ring) + P.ring_off;
-    T* ring_out = ring + (int64_t)(s % kRing) * P.Nb;
-    const T* ring_in = ring + (int64_t)((s + kRing - 1) % kRing) * P.Nb;
-    uint32_t* flag_out = w.flags + P.flag_off + (int64_t)(s % kRing) * nch;
-    const uint32_t* flag_in = w.flags + P.flag_off + (int64_t)((s + kRing - 1) % kRing) * nch;
+    U* ring_out = reinterpret_cast<U*>(ring + (int64_t)(s % kRing) * P.Nb);
+    U* ring_in = reinterpret_cast<U*>(ring + (int64_t)((s + kRing - 1) % kRing) * P.Nb);
+    const uint32_t my_tag = ((uint32_t)(level + 1) << 20) | (uint32_t)(s + 1);
 
-    // prologue: column 0 costs and the first boundary chunk
-    {
-      const int gj = __builtin_amdgcn_readfirstlane(jbase);
-      cring[lane] = frame_cost<T, D>(x, Y + (int64_t)gj * D);
-      if (has_pred) fetch_chunk(ring_in, flag_in, pred_tag, 0, P.Nb, bring, lane, w);
-    }
-
-    T f = T(0);       // own F(a, b-1)
-    T up_prev = INF;  // F(a-1, b-1)
-    for (int t = 0; t < n_steps; ++t) {
-      const int b = t - lane;
-      // reads for this step, before the writes below reuse their slots
-      const T c = cring[(b & (kWave - 1)) * kWave + lane];
-      const T bv = has_pred ? bring[t & (kWave - 1)] : INF;
-      // frame cost of the next column, all 64 rows
-      if (t + 1 <= bmax_first) {
-        const int gj = __builtin_amdgcn_readfirstlane(jbase + jstep * (t + 1));
-        cring[((t + 1) & (kWave - 1)) * kWave + lane] = frame_cost<T, D>(x, Y + (int64_t)gj * D);
-        if (has_pred && ((t + 1) % kChunkCols) == 0)
-          fetch_chunk(ring_in, flag_in, pred_tag, t + 1, P.Nb, bring, lane, w);
-      }
-      // recurrence on the skewed diagonal: UP from lane-1 (lane 0: the row above)
-      const T up = wave_shr1(bv, f);
-      if (row_ok && b >= 0 && b <= bmax) {
-        const T diag = (b == 0) ? INF : up_prev;
-        const T left = (b == 0) ? INF : f;
-        const T m = min_t(min_t(diag, up), left);
-        f = (a == 0 && b == 0) ? c : m + c;
-        const int k = a + b;
-        if (k >= P.kstop - 2) {
-          if (P.dir == 0 || P.raw) {
-            const int q = k - (P.kstop - 2);
-            const int lo = max(0, k - (P.Nb - 1));
-            const int64_t idx = P.band_off + (int64_t)q * P.L + (a - lo);
-            w.bandF[idx] = (double)f;
-            if (w.bandC) w.bandC[idx] = (double)c;
-          } else {
-            const int kfw = K - 1 - k;
-            const int q = kfw - (P.kf - 2);
-            const int af = P.Mb - 1 - a;
-            const int lo = max(0, kfw - (P.Nb - 1));
-            w.bandB[P.band_off + (int64_t)q * P.L + (af - lo)] = (double)f;
+    if (wave == 0) {
+      // ------------------------------------------------ recurrence
+      const int a = a0 + lane;
+      const int bmax = (lane <= Lr) ? min(P.Nb - 1, P.kstop - a) : -1;
+      const int K = P.Mb + P.Nb - 1;
+      // steps where every lane with a row is strictly inside its row and no
+      // band diagonal is reached: no predicate is needed there
+      const int t_lo = Lr + 1;
+      const int t_hi = min(P.Nb - 1, P.kstop - a0 - 3);
+      T f = T(0);       // own F(a, b-1)
+      T up_prev = INF;  // F(a-1, b-1)
+      lds_barrier();    // phase -1: first costs and boundary chunk
+      for (int k = 0; k < n_phases; ++k) {
+        const int t0 = k * kPhase;
+        const T* cp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
+        const T* bp = bring + in_vgpr(t0 & (2 * kPhase - 1));
+        if (t0 >= t_lo && t0 + kPhase - 1 <= t_hi) {
+          // operands of the next kStepGroup steps are read one group ahead
+          constexpr int G = kStepGroup;
+          T cb[2][G], bb[2][G];
+#pragma unroll
+          for (int i = 0; i < G; ++i) {
+            cb[0][i] = cp[i * kWave];
+            bb[0][i] = bp[i];
+          }
+#pragma unroll
+          for (int g = 0; g < kPhase / G; ++g) {
+            if (g + 1 < kPhase / G) {
+#pragma unroll
+              for (int i = 0; i < G; ++i) {
+                cb[(g + 1) & 1][i] = cp[((g + 1) * G + i) * kWave];
+                bb[(g + 1) & 1][i] = bp[(g + 1) * G + i];
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+              const int u = g * G + i;
+              const T up = wave_shr1(bb[g & 1][i], f);
+              f = min_t(min_t(up_prev, f), up) + cb[g & 1][i];
+              up_prev = up;
+              hist[(u & (kPubGroup - 1)) * kWave + lane] = f;
+              if ((u & (kPubGroup - 1)) == kPubGroup - 1 && has_succ)
+                publish<T>(t0 + u, lane, hist, ring_out, pub_max);
+            }
+          }
+        } else {
+          const int t1 = min(t0 + kPhase, n_steps);
+          for (int t = t0; t < t1; ++t) {
+            const int u = t - t0;
+            const int b = t - lane;
+            const T c = cp[u * kWave];
+            const T up = wave_shr1(bp[u], f);
+            if (b >= 0 && b <= bmax) {
+              const T diag = (b == 0) ? INF : up_prev;
+              const T left = (b == 0) ? INF : f;
+              f = (a == 0 && b == 0) ? c : min_t(min_t(diag, left), up) + c;
+              const int kd = a0 + t;  // = a + b
+              if (kd >= P.kstop - 2) {
+                if (P.dir == 0 || P.raw) {
+                  const int q = kd - (P.kstop - 2);
+                  const int lo = max(0, kd - (P.Nb - 1));
+                  const int64_t idx = P.band_off + (int64_t)q * P.L + (a - lo);
+                  w.bandF[idx] = (double)f;
+                  if (w.bandC) w.bandC[idx] = (double)c;
+                } else {
+                  const int kfw = K - 1 - kd;
+                  const int q = kfw - (P.kf - 2);
+                  const int af = P.Mb - 1 - a;
+                  const int lo = max(0, kfw - (P.Nb - 1));
+                  w.bandB[P.band_off + (int64_t)q * P.L + (af - lo)] = (double)f;
+                }
+              }
+            }
+            up_prev = up;
+            hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
+            if (has_succ && ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1))
+              publish<T>(t, lane, hist, ring_out, pub_max);
           }
         }
-        if (has_succ && lane == kWave - 1) {
-          ring_out[b] = f;
-          if ((b % kChunkCols) == kChunkCols - 1 || b == bmax)
-            __hip_atomic_store(flag_out + b / kChunkCols, my_tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        lds_barrier();
       }
-      up_prev = up;
+    } else if (wave <= kProducers) {
+      // ------------------------------------------------ frame costs
+      const int pw = wave - 1;
+      T x[D];
+      {
+        const int r = min(lane, Lr);  // lanes below the stripe's last row reuse it
+        const int gi = P.dir ? P.i1 - (a0 + r) : P.i0 + a0 + r;
+        const T* xr = X + (int64_t)gi * D;
+#pragma unroll
+        for (int q = 0; q < D; ++q) x[q] = xr[q];
+      }
+      for (int k = -1; k < n_phases; ++k) {
+        const int c0 = (k + 1) * kPhase;
+        if (c0 <= need_max) {
+          // two columns at a time: two independent fma chains per lane
+#pragma unroll
+          for (int i = 0; i < kPhase / kProducers; i += 2) {
+            const int j0 = c0 + pw + i * kProducers, j1 = j0 + kProducers;
+            const int jc0 = min(j0, need_max), jc1 = min(j1, need_max);
+            const int gj0 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc0 : P.j0 + jc0);
+            const int gj1 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc1 : P.j0 + jc1);
+            T cv0, cv1;
+            frame_cost2<T, D>(x, Y + (int64_t)gj0 * D, Y + (int64_t)gj1 * D, cv0, cv1);
+            // columns past need_max hold a clamped column's cost; nothing reads them
+            cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
+            cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
+          }
+        }
+        lds_barrier();
+      }
+    } else {
+      // ------------------------------------------------ boundary input
+      uint32_t* gen_out = w.gens + P.gen_off + s % kRing;
+      uint32_t* gen_in = w.gens + P.gen_off + (s + kRing - 1) % kRing;
+      if (has_pred) (void)poll_cell<uint32_t>(gen_in, my_tag - 1u, w, true);
+      for (int k = -1; k < n_phases; ++k) {
+        wait_vmem();  // the previous phase's resets have completed
+        const int col = (k + 1) * kPhase + lane;
+        if (lane < kPhase) {
+          T v = INF;
+          if (has_pred && col <= need_max) {
+            const U bits = poll_cell<U>(ring_in + col, RingWord<T>::kEmpty, w);
+            __hip_atomic_store(ring_in + col, RingWord<T>::kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v = __builtin_bit_cast(T, bits);
+          }
+          bring[col & (2 * kPhase - 1)] = v;
+        }
+        if (k == -1 && lane == 0)  // after the first chunk arrived (see above)
+          __hip_atomic_store(gen_out, my_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        lds_barrier();
+      }
+      wait_vmem();
     }
   }
 }
@@ -285,7 +441,7 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(const T* __restrict_
       {
         const int gj = __builtin_amdgcn_readfirstlane(c0);
         cring[lane] = frame_cost<T, D>(x, ColSrc + (int64_t)gj * D);
-        if (has_pred && lane < kChunkCols && lane < Cc) bring[lane] = brow[lane];
+        if (has_pred && lane < kPhase && lane < Cc) bring[lane] = brow[lane];
       }
       T f = T(0), up_prev = INF;
       uint32_t word = 0;
@@ -296,9 +452,9 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(const T* __restrict_
         if (t + 1 < Cc) {
           const int gj = __builtin_amdgcn_readfirstlane(c0 + t + 1);
           cring[((t + 1) & (kWave - 1)) * kWave + lane] = frame_cost<T, D>(x, ColSrc + (int64_t)gj * D);
-          if (has_pred && ((t + 1) % kChunkCols) == 0) {
+          if (has_pred && ((t + 1) % kPhase) == 0) {
             const int col = t + 1 + lane;
-            if (lane < kChunkCols && col < Cc) bring[col & (kWave - 1)] = brow[col];
+            if (lane < kPhase && col < Cc) bring[col & (kWave - 1)] = brow[col];
           }
         }
         const T up = wave_shr1(bv, f);
@@ -411,10 +567,10 @@ int pick_dmax(int d) {
 hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t st) {
   const int dm = pick_dmax(w.d);
   if (f32) {
-    DTW_DISPATCH_DMAX(dm, (pass_kernel<float, D_><<<grid, kWave, 0, st>>>(
+    DTW_DISPATCH_DMAX(dm, (pass_kernel<float, D_><<<grid, kPassThreads, 0, st>>>(
                               static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w, level)))
   } else {
-    DTW_DISPATCH_DMAX(dm, (pass_kernel<double, D_><<<grid, kWave, 0, st>>>(
+    DTW_DISPATCH_DMAX(dm, (pass_kernel<double, D_><<<grid, kPassThreads, 0, st>>>(
                               static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w, level)))
   }
   return hipGetLastError();

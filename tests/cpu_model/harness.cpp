@@ -14,11 +14,12 @@
 
 thread_local dim3_cpu threadIdx, blockIdx, blockDim, gridDim;
 thread_local std::barrier<>* cpu_block_barrier = nullptr;
+thread_local std::barrier<>* cpu_wave_barrier = nullptr;
 
 #include "dtw_plan_kernels.inc"
 #ifdef MODEL_WAVE
 #include "wave_shim.h"
-uint64_t cpu_wave_slots[64];
+uint64_t cpu_wave_slots[16][64];
 alignas(16) unsigned char cpu_dynamic_lds[163840];
 #include "dtw_wave_kernels.inc"
 #endif
@@ -251,9 +252,9 @@ hipError_t launch_pass(const Work& w, int level, bool f32, int, hipStream_t) {
   model_check_queue(w);
   const int D = pick_dmax(w.d);
   if (f32) {
-    MODEL_DISPATCH(D, (cpu_launch(2, kWave, [&] { pass_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, level); })))
+    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, level); })))
   } else {
-    MODEL_DISPATCH(D, (cpu_launch(2, kWave, [&] { pass_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, level); })))
+    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { pass_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, level); })))
   }
   return hipSuccess;
 }

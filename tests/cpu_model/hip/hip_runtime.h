@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -35,6 +36,7 @@ enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize };
 struct dim3_cpu { unsigned int x = 0, y = 1, z = 1; };
 extern thread_local dim3_cpu threadIdx, blockIdx, blockDim, gridDim;
 extern thread_local std::barrier<>* cpu_block_barrier;
+extern thread_local std::barrier<>* cpu_wave_barrier;  // the 64 threads of this thread's wave
 inline void __syncthreads() { cpu_block_barrier->arrive_and_wait(); }
 
 struct int2 { int x, y; };
@@ -91,12 +93,16 @@ inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms =
 inline void cpu_launch(int grid, int block, const std::function<void()>& body) {
   for (int b = 0; b < grid; ++b) {
     std::barrier<> bar(block);
+    const int n_waves = (block + 63) / 64;
+    std::vector<std::unique_ptr<std::barrier<>>> wbar;
+    for (int v = 0; v < n_waves; ++v) wbar.emplace_back(new std::barrier<>(std::min(64, block - 64 * v)));
     std::vector<std::thread> th;
     th.reserve(block);
     for (int t = 0; t < block; ++t)
       th.emplace_back([&, t, b] {
         threadIdx.x = t; blockIdx.x = b; blockDim.x = block; gridDim.x = grid;
         cpu_block_barrier = &bar;
+        cpu_wave_barrier = wbar[t / 64].get();
         body();
       });
     for (auto& x : th) x.join();

@@ -9,18 +9,20 @@
 
 #include "hip/hip_runtime.h"
 
-extern thread_local uint64_t cpu_wave_slots_dummy;
-extern uint64_t cpu_wave_slots[64];
+extern uint64_t cpu_wave_slots[16][64];
 extern unsigned char cpu_dynamic_lds[];
 
+// Lane index within the wave, and an exchange among the 64 lanes of one wave.
+inline int cpu_lane() { return (int)(threadIdx.x & 63); }
 template <class T>
 inline T cpu_wave_exchange(T v, int src) {
   uint64_t bits = 0;
   std::memcpy(&bits, &v, sizeof(T));
-  cpu_wave_slots[threadIdx.x] = bits;
-  cpu_block_barrier->arrive_and_wait();
-  const uint64_t r = cpu_wave_slots[src & 63];
-  cpu_block_barrier->arrive_and_wait();
+  uint64_t* slots = cpu_wave_slots[threadIdx.x / 64];
+  slots[cpu_lane()] = bits;
+  cpu_wave_barrier->arrive_and_wait();
+  const uint64_t r = slots[src & 63];
+  cpu_wave_barrier->arrive_and_wait();
   T out;
   std::memcpy(&out, &r, sizeof(T));
   return out;
@@ -28,8 +30,8 @@ inline T cpu_wave_exchange(T v, int src) {
 
 inline int cpu_update_dpp(int old, int src, int ctrl) {
   if (ctrl != 0x138) std::abort();  // only wave_shr:1 is used
-  const int v = cpu_wave_exchange(src, (int)threadIdx.x - 1);
-  return threadIdx.x == 0 ? old : v;
+  const int v = cpu_wave_exchange(src, cpu_lane() - 1);
+  return cpu_lane() == 0 ? old : v;
 }
 
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) cpu_update_dpp((old), (src), (ctrl))
@@ -40,11 +42,14 @@ inline int cpu_update_dpp(int old, int src, int ctrl) {
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_sqrtf(x) std::sqrt((float)(x))
 #define __HIP_MEMORY_SCOPE_AGENT 0
+#define __HIP_MEMORY_SCOPE_WORKGROUP 1
 #define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
 #define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
+#define __builtin_amdgcn_s_waitcnt(x) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_wave_barrier() cpu_wave_barrier->arrive_and_wait()
 
 template <class T> inline T __shfl(T v, int src) { return cpu_wave_exchange(v, src); }
-template <class T> inline T __shfl_xor(T v, int mask) { return cpu_wave_exchange(v, (int)threadIdx.x ^ mask); }
+template <class T> inline T __shfl_xor(T v, int mask) { return cpu_wave_exchange(v, cpu_lane() ^ mask); }
 
 inline int __double2loint(double d) { uint64_t b; std::memcpy(&b, &d, 8); return (int)(uint32_t)b; }
 inline int __double2hiint(double d) { uint64_t b; std::memcpy(&b, &d, 8); return (int)(uint32_t)(b >> 32); }

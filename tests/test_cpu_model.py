@@ -25,12 +25,16 @@ MODEL = os.path.join(ROOT, "tests", "cpu_model")
 MARK = "// ----------------------------------------------------------------- launchers"
 
 
-# The two textual edits the wave kernels need to compile for the host: the
-# inline-asm v_min becomes the same minimum in C++, and the dynamic LDS array
-# becomes a static buffer.
+# The textual edits the wave kernels need to compile for the host: each
+# inline-asm statement becomes its C++ meaning (minimum, register move,
+# workgroup barrier, completion of outstanding memory operations), and the
+# dynamic LDS array becomes a static buffer.
 WAVE_EDITS = [
     ('asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));', "r = (b < a) ? b : a;"),
     ('asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));', "r = (b < a) ? b : a;"),
+    ('asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));', "r = x;"),
+    ('asm volatile("s_waitcnt lgkmcnt(0)\\n\\ts_barrier" ::: "memory");', "__syncthreads();"),
+    ('asm volatile("s_waitcnt vmcnt(0)" ::: "memory");', "std::atomic_thread_fence(std::memory_order_seq_cst);"),
     ("extern __shared__ __align__(16) unsigned char lds_raw[];", "unsigned char* lds_raw = cpu_dynamic_lds;"),
 ]
 
