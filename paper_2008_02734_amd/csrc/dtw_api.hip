@@ -12,9 +12,9 @@
 
 namespace dtw {
 hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t st);
-hipError_t launch_leaf(const Work& w, bool f32, int grid, size_t lds_bytes, int64_t lds_leaf_bytes,
-                       const void* Xo, const void* Yo, int in_f64, hipStream_t st);
-hipError_t set_leaf_lds_limit(size_t bytes);
+hipError_t launch_leaf(const Work& w, bool f32, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
+                       int in_f64, hipStream_t st);
+hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32);
 hipError_t launch_init(const Work& w, hipStream_t st);
 hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t st);
 hipError_t launch_combine(const Work& w, int grid, hipStream_t st);
@@ -39,6 +39,7 @@ struct DevInfo {
   int lds_max = 0;
   int64_t wall_khz = 0;
   bool attr_set = false;
+  int64_t leaf_dyn[2] = {0, 0};  // dynamic LDS of the leaf kernels: FP64, FP32 compute
 };
 
 DevInfo& dev_info() {
@@ -324,7 +325,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   const int in_f64 = in_dtype == DTW_F64;
   DevInfo& I = dev_info();
   if (!I.attr_set) {
-    HIP_TRY(set_leaf_lds_limit((size_t)I.lds_max));
+    HIP_TRY(leaf_lds_setup(I.lds_max, &I.leaf_dyn[0], &I.leaf_dyn[1]));
     I.attr_set = true;
   }
 
@@ -359,9 +360,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
 
   const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WG_PER_CU", 2));
   const int comb_grid = I.cus * 4;
-  const size_t cring_bytes = (size_t)L.cbytes * (kWave * kWave + kWave);
-  const size_t lds_bytes = (size_t)I.lds_max;
-  const int64_t lds_leaf_bytes = (int64_t)lds_bytes - (int64_t)cring_bytes;
+  const int64_t lds_leaf_bytes = I.leaf_dyn[f32 ? 1 : 0];
   for (int lvl = 0; lvl <= L.lmax; ++lvl) {
     const int final_level = (lvl == L.lmax) ? 1 : 0;
     PROF_TRY(prof, kProfPlan, launch_plan(w, lvl, final_level, lds_leaf_bytes, st));
@@ -369,7 +368,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
     PROF_TRY(prof, kProfSweep, launch_pass(w, lvl, f32, pass_grid, st));
     PROF_TRY(prof, kProfSplit, launch_combine(w, comb_grid, st));
   }
-  PROF_TRY(prof, kProfLeaf, launch_leaf(w, f32, I.cus, lds_bytes, lds_leaf_bytes, X, Y, in_f64, st));
+  PROF_TRY(prof, kProfLeaf, launch_leaf(w, f32, I.cus, lds_leaf_bytes, X, Y, in_f64, st));
   PROF_TRY(prof, kProfOther,
            launch_assemble(w, at<int32_t>(ws, L.poff), at<int32_t>(ws, L.lidx), costs, lens, paths, I.cus * 2, st));
 

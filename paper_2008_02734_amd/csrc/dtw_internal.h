@@ -16,7 +16,6 @@ constexpr int kWave = 64;        // gfx950 wavefront width; one lane per DP row
 constexpr int kRing = 2;         // boundary-row slots per sweep (see pass kernel)
 constexpr int kBandChunk = 256;  // band cells per split-cost work item
 constexpr int kMaxMinBlock = 1024;
-constexpr int kLeafThreads = 64;
 constexpr uint32_t kSpinIterCap = 1u << 26;  // polls before a wait gives up
 
 // Pass kernel workgroup: one recurrence wave, kProducers frame-cost waves and

@@ -240,21 +240,27 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
 
     if (wave == 0) {
       // ------------------------------------------------ recurrence
+      //
+      // Before a lane reaches its row (b < 0) its value is +inf (or a NaN
+      // made from an unused cost slot); v_min returns the other operand of a
+      // NaN, so at b = 0 the minimum is exactly UP, and the unpredicated step
+      // is the recurrence of Algorithm 1 from the first step on.  Lane 0 of
+      // the block's first stripe starts with DIAG = 0, which makes its first
+      // cell F(0,0) = C(0,0) exactly.  Lanes past their row's last column
+      // keep computing values that no valid cell reads.  Only the steps that
+      // reach the band diagonals (the last three) take the predicated path.
       const int a = a0 + lane;
       const int bmax = (lane <= Lr) ? min(P.Nb - 1, P.kstop - a) : -1;
       const int K = P.Mb + P.Nb - 1;
-      // steps where every lane with a row is strictly inside its row and no
-      // band diagonal is reached: no predicate is needed there
-      const int t_lo = Lr + 1;
-      const int t_hi = min(P.Nb - 1, P.kstop - a0 - 3);
-      T f = T(0);       // own F(a, b-1)
-      T up_prev = INF;  // F(a-1, b-1)
-      lds_barrier();    // phase -1: first costs and boundary chunk
+      const int t_band = min(n_steps, max(0, P.kstop - a0 - 2));
+      T f = INF;                                          // own F(a, b-1)
+      T up_prev = (s == 0 && lane == 0) ? T(0) : INF;     // F(a-1, b-1)
+      lds_barrier();  // phase -1: first costs and boundary chunk
       for (int k = 0; k < n_phases; ++k) {
         const int t0 = k * kPhase;
         const T* cp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
         const T* bp = bring + in_vgpr(t0 & (2 * kPhase - 1));
-        if (t0 >= t_lo && t0 + kPhase - 1 <= t_hi) {
+        if (t0 + kPhase <= t_band) {
           // operands of the next kStepGroup steps are read one group ahead
           constexpr int G = kStepGroup;
           T cb[2][G], bb[2][G];
@@ -290,25 +296,25 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
             const int b = t - lane;
             const T c = cp[u * kWave];
             const T up = wave_shr1(bp[u], f);
-            if (b >= 0 && b <= bmax) {
+            if (t < t_band) {
+              f = min_t(min_t(up_prev, f), up) + c;
+            } else if (b >= 0 && b <= bmax) {
               const T diag = (b == 0) ? INF : up_prev;
               const T left = (b == 0) ? INF : f;
               f = (a == 0 && b == 0) ? c : min_t(min_t(diag, left), up) + c;
-              const int kd = a0 + t;  // = a + b
-              if (kd >= P.kstop - 2) {
-                if (P.dir == 0 || P.raw) {
-                  const int q = kd - (P.kstop - 2);
-                  const int lo = max(0, kd - (P.Nb - 1));
-                  const int64_t idx = P.band_off + (int64_t)q * P.L + (a - lo);
-                  w.bandF[idx] = (double)f;
-                  if (w.bandC) w.bandC[idx] = (double)c;
-                } else {
-                  const int kfw = K - 1 - kd;
-                  const int q = kfw - (P.kf - 2);
-                  const int af = P.Mb - 1 - a;
-                  const int lo = max(0, kfw - (P.Nb - 1));
-                  w.bandB[P.band_off + (int64_t)q * P.L + (af - lo)] = (double)f;
-                }
+              const int kd = a0 + t;  // = a + b >= kstop - 2
+              if (P.dir == 0 || P.raw) {
+                const int q = kd - (P.kstop - 2);
+                const int lo = max(0, kd - (P.Nb - 1));
+                const int64_t idx = P.band_off + (int64_t)q * P.L + (a - lo);
+                w.bandF[idx] = (double)f;
+                if (w.bandC) w.bandC[idx] = (double)c;
+              } else {
+                const int kfw = K - 1 - kd;
+                const int q = kfw - (P.kf - 2);
+                const int af = P.Mb - 1 - a;
+                const int lo = max(0, kfw - (P.Nb - 1));
+                w.bandB[P.band_off + (int64_t)q * P.L + (af - lo)] = (double)f;
               }
             }
             up_prev = up;
@@ -377,33 +383,162 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
 
 // ----------------------------------------------------------------- leaf
 
-// Textbook DTW on one leaf block by one wave: the shorter side is the row
-// dimension (so one wave sweeps it in ceil(R/64) passes of 64 rows), the
-// longer side the column dimension.  When the block is transposed (rows = Y
-// frames), the UP/LEFT roles swap; the stored 2-bit codes always use the
-// original meaning: 0 DIAG (i-1,j-1), 1 UP (i-1,j), 2 LEFT (i,j-1), chosen
-// DIAG, then UP, then LEFT on ties.  Row 0 of X moves LEFT, column 0 of Y UP.
+// Textbook DTW on one leaf block (Sec. 2.1) by one workgroup with the roles
+// of the pass kernel: the shorter side is the row dimension, swept in
+// ceil(R/64) stripes of 64 rows one after the other, the longer side the
+// column dimension.  The recurrence wave also stores a 2-bit backpointer per
+// cell: 0 DIAG (i-1,j-1), 1 UP (i-1,j), 2 LEFT (i,j-1), chosen DIAG, then UP,
+// then LEFT on ties; row 0 of X moves LEFT, column 0 of Y moves UP, so the
+// codes stored on row 0 and column 0 are never read.  When the block is
+// transposed (rows = Y frames) UP and LEFT swap roles, and the codes keep
+// their original meaning.  The bottom row of a stripe goes to the next stripe
+// through `brow`; the input wave copies it into the boundary ring one phase
+// ahead.  Lane 0 of the recurrence wave then walks the pointers back from the
+// block's last cell.  `bp` and `brow` point into LDS when the leaf fits there
+// and into global scratch otherwise; the caller inlines one copy per case so
+// that each copy addresses a single memory space.
+struct LeafShape {
+  bool tr;
+  int R, Cc, r0, c0, stride;
+};
+
 template <typename T, int D>
-__global__ __launch_bounds__(kLeafThreads) void leaf_kernel(const T* __restrict__ X, const T* __restrict__ Y,
-                                                           Work w, int64_t lds_leaf_bytes, const void* Xorig,
-                                                           const void* Yorig, int in_f64, int d) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* cring = reinterpret_cast<T*>(lds_raw);
-  T* bring = cring + kWave * kWave;
-  uint32_t* lds_free = reinterpret_cast<uint32_t*>(bring + kWave);
-  const int lane = threadIdx.x;
+__device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* __restrict__ ColSrc, const LeafShape& S,
+                                        uint32_t* bp, T* brow, T* cring, T* bring, int wave, int lane) {
+  const T INF = inf_t<T>();
+  T fend = T(0);
+  for (int sw = 0; sw < S.R; sw += kWave) {
+    const int Lr = min(kWave - 1, S.R - 1 - sw);
+    const int n_steps = S.Cc + Lr;
+    const int n_phases = (n_steps + kPhase - 1) / kPhase;
+    const bool has_pred = sw > 0;
+    const bool has_succ = sw + kWave < S.R;
+    if (wave == 0) {
+      // ------------------------------------------------ recurrence + pointers
+      // Unpredicated steps as in the pass kernel: +inf before a lane's row
+      // starts, DIAG = 0 for the block's first cell.
+      const int a = sw + lane;
+      const bool row_ok = lane <= Lr;
+      T f = INF;
+      T up_prev = (sw == 0 && lane == 0) ? T(0) : INF;
+      uint32_t word = 0;
+      int64_t bidx = (int64_t)a * S.stride;  // word of column 0 of the lane's row
+      lds_barrier();                          // phase -1
+      for (int k = 0; k < n_phases; ++k) {
+        const int t0 = k * kPhase;
+        const T* cp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
+        const T* bpl = bring + in_vgpr(t0 & (2 * kPhase - 1));
+        const int t1 = min(t0 + kPhase, n_steps);
+        for (int t = t0; t < t1; ++t) {
+          const int u = t - t0;
+          const int b = t - lane;
+          const T c = cp[u * kWave];
+          const T up = wave_shr1(bpl[u], f);
+          const T diag = up_prev, left = f;
+          uint32_t code;
+          if (diag <= up && diag <= left) code = 0u;
+          else if (S.tr ? (left <= up) : (up <= left)) code = 1u;
+          else code = 2u;
+          f = min_t(min_t(diag, up), left) + c;
+          up_prev = up;
+          word |= code << (2 * (b & 15));
+          const bool in_row = row_ok && b >= 0 && b < S.Cc;
+          if (in_row && ((b & 15) == 15 || b == S.Cc - 1)) bp[bidx + (b >> 4)] = word;
+          if ((b & 15) == 15) word = 0u;
+          if (has_succ && lane == kWave - 1 && b >= 0 && b < S.Cc) brow[b] = f;
+          if (a == S.R - 1 && b == S.Cc - 1) fend = f;
+        }
+        lds_barrier();
+      }
+    } else if (wave <= kProducers) {
+      // ------------------------------------------------ frame costs
+      const int pw = wave - 1;
+      T x[D];
+      {
+        const T* xr = RowSrc + (int64_t)(S.r0 + sw + min(lane, Lr)) * D;
+#pragma unroll
+        for (int q = 0; q < D; ++q) x[q] = xr[q];
+      }
+      for (int k = -1; k < n_phases; ++k) {
+        const int cb0 = (k + 1) * kPhase;
+        if (cb0 < S.Cc) {
+#pragma unroll
+          for (int i = 0; i < kPhase / kProducers; i += 2) {
+            const int j0 = cb0 + pw + i * kProducers, j1 = j0 + kProducers;
+            const int gj0 = __builtin_amdgcn_readfirstlane(S.c0 + min(j0, S.Cc - 1));
+            const int gj1 = __builtin_amdgcn_readfirstlane(S.c0 + min(j1, S.Cc - 1));
+            T cv0, cv1;
+            frame_cost2<T, D>(x, ColSrc + (int64_t)gj0 * D, ColSrc + (int64_t)gj1 * D, cv0, cv1);
+            cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
+            cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
+          }
+        }
+        lds_barrier();
+      }
+    } else {
+      // ------------------------------------------------ boundary input
+      for (int k = -1; k < n_phases; ++k) {
+        const int col = (k + 1) * kPhase + lane;
+        if (lane < kPhase) bring[col & (2 * kPhase - 1)] = (has_pred && col < S.Cc) ? brow[col] : INF;
+        lds_barrier();
+      }
+    }
+    // the stripe's bottom row is complete for the next stripe
+    __syncthreads();
+  }
+  return fend;
+}
+
+// Backtrace by one lane from the block's last cell; cells are written
+// backwards from slot_end of the diagonal-indexed path scratch.  Returns the
+// number of cells written (the block's first cell only for the pair's first
+// leaf: otherwise it is the previous leaf's last cell).
+__device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShape& S, const LeafDesc& Lf,
+                                              const PairDesc& pd, int64_t slot_end, int2* tpath) {
+  int cnt = 0;
+  int ri = S.R - 1, cj = S.Cc - 1;
+  for (int guard = 0; guard < S.R + S.Cc; ++guard) {  // every step decrements ri or cj
+    const bool at_start = (ri == 0 && cj == 0);
+    if (!at_start || Lf.first) {
+      const int gi = S.tr ? (Lf.i0 + cj) : (Lf.i0 + ri);
+      const int gj = S.tr ? (Lf.j0 + ri) : (Lf.j0 + cj);
+      tpath[slot_end - cnt] = make_int2((int)(gi - pd.x_off), (int)(gj - pd.y_off));
+      ++cnt;
+    }
+    if (at_start) break;
+    if (ri == 0) { --cj; continue; }  // first row / column: the only move
+    if (cj == 0) { --ri; continue; }
+    const uint32_t code = (bp[(int64_t)ri * S.stride + (cj >> 4)] >> (2 * (cj & 15))) & 3u;
+    if (code == 0u) { --ri; --cj; }
+    else if (code == 1u) { if (S.tr) --cj; else --ri; }
+    else { if (S.tr) --ri; else --cj; }
+  }
+  return cnt;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void leaf_kernel(
+    const T* __restrict__ X, const T* __restrict__ Y, Work w, int64_t lds_leaf_bytes, const void* Xorig,
+    const void* Yorig, int in_f64, int d) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];  // pointers and bottom row when they fit
+  __shared__ T cring[kCostRing * kWave];
+  __shared__ T bring[2 * kPhase];
+  __shared__ int sh_ticket;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
   Ctl* ctl = w.ctl;
   const int n_leaf = clamp_count(ctl, ctl->n_leaf, w.caps.leaf);
-  const T INF = inf_t<T>();
+  (void)lds_leaf_bytes;
 
   for (int iter = 0; iter <= n_leaf; ++iter) {  // each iteration consumes one ticket
-    int tk = 0;
-    if (lane == 0) tk = atomicAdd(&ctl->leaf_ticket, 1);
-    tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
+    if (threadIdx.x == 0) sh_ticket = atomicAdd(&ctl->leaf_ticket, 1);
+    lds_barrier();
+    const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
+    lds_barrier();
     if (tk >= n_leaf || tk < 0) break;
     const LeafDesc Lf = w.leaves[tk];
     if (Lf.pair < 0 || Lf.pair >= w.n_pairs) {
-      if (lane == 0) set_error(ctl, kErrBadLeaf);
+      if (threadIdx.x == 0) set_error(ctl, kErrBadLeaf);
       continue;
     }
     const PairDesc pd = w.pairs[Lf.pair];
@@ -411,133 +546,67 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(const T* __restrict_
     // a leaf lies inside its pair and is non-empty; refuse anything else
     if (Mb < 1 || Nb < 1 || Lf.i0 < pd.x_off || Lf.j0 < pd.y_off || Lf.i1 >= pd.x_off + pd.M ||
         Lf.j1 >= pd.y_off + pd.N) {
-      if (lane == 0) set_error(ctl, kErrBadLeaf);
+      if (threadIdx.x == 0) set_error(ctl, kErrBadLeaf);
       continue;
     }
-    const bool tr = Mb > Nb;
-    const int R = tr ? Nb : Mb, Cc = tr ? Mb : Nb;
-    const T* __restrict__ RowSrc = tr ? Y : X;
-    const T* __restrict__ ColSrc = tr ? X : Y;
-    const int r0 = tr ? Lf.j0 : Lf.i0, c0 = tr ? Lf.i0 : Lf.j0;
-    const int stride = (Cc + 15) / 16;
-    const int64_t bpw = (((int64_t)R * stride) + 1) & ~(int64_t)1;
-    uint32_t* bp = (Lf.scratch_off < 0) ? lds_free : (w.leaf_scratch + Lf.scratch_off);
-    T* brow = reinterpret_cast<T*>(bp + bpw);
-    T fend = T(0);
-
-    for (int sw = 0; sw < R; sw += kWave) {
-      const int a = sw + lane;
-      const bool row_ok = a < R;
-      const int Lr = min(kWave - 1, R - 1 - sw);
-      const int n_steps = Cc + Lr;
-      const bool has_pred = sw > 0;
-      const bool has_succ = sw + kWave < R;
-      T x[D];
-      {
-        const T* xr = RowSrc + (int64_t)(r0 + (row_ok ? a : 0)) * D;
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = xr[k];
-      }
-      {
-        const int gj = __builtin_amdgcn_readfirstlane(c0);
-        cring[lane] = frame_cost<T, D>(x, ColSrc + (int64_t)gj * D);
-        if (has_pred && lane < kPhase && lane < Cc) bring[lane] = brow[lane];
-      }
-      T f = T(0), up_prev = INF;
-      uint32_t word = 0;
-      for (int t = 0; t < n_steps; ++t) {
-        const int b = t - lane;
-        const T c = cring[(b & (kWave - 1)) * kWave + lane];
-        const T bv = has_pred ? bring[t & (kWave - 1)] : INF;
-        if (t + 1 < Cc) {
-          const int gj = __builtin_amdgcn_readfirstlane(c0 + t + 1);
-          cring[((t + 1) & (kWave - 1)) * kWave + lane] = frame_cost<T, D>(x, ColSrc + (int64_t)gj * D);
-          if (has_pred && ((t + 1) % kPhase) == 0) {
-            const int col = t + 1 + lane;
-            if (lane < kPhase && col < Cc) bring[col & (kWave - 1)] = brow[col];
-          }
-        }
-        const T up = wave_shr1(bv, f);
-        if (row_ok && b >= 0 && b < Cc) {
-          const T diag = (b == 0) ? INF : up_prev;
-          const T left = (b == 0) ? INF : f;
-          uint32_t code;
-          if (diag <= up && diag <= left) code = 0u;
-          else if (tr ? (left <= up) : (up <= left)) code = 1u;
-          else code = 2u;
-          const T m = min_t(min_t(diag, up), left);
-          f = (a == 0 && b == 0) ? c : m + c;
-          word |= code << (2 * (b & 15));
-          if ((b & 15) == 15 || b == Cc - 1) {
-            bp[(int64_t)a * stride + (b >> 4)] = word;
-            word = 0u;
-          }
-          if (has_succ && lane == kWave - 1) brow[b] = f;
-          if (a == R - 1 && b == Cc - 1) fend = f;
-        }
-        up_prev = up;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-
-    // backtrace from the block's last cell, writing cells backwards into the
-    // diagonal-indexed path scratch (the end cell sits on diagonal e)
+    LeafShape S;
+    S.tr = Mb > Nb;
+    S.R = S.tr ? Nb : Mb;
+    S.Cc = S.tr ? Mb : Nb;
+    S.r0 = S.tr ? Lf.j0 : Lf.i0;
+    S.c0 = S.tr ? Lf.i0 : Lf.j0;
+    S.stride = (S.Cc + 15) / 16;
+    const T* __restrict__ RowSrc = S.tr ? Y : X;
+    const T* __restrict__ ColSrc = S.tr ? X : Y;
+    const int64_t bpw = (((int64_t)S.R * S.stride) + 1) & ~(int64_t)1;
     const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
-    const int64_t slot_end = pd.pbase + e;
+    const int64_t slot_end = pd.pbase + e;  // the block's last cell sits on diagonal e
+    T fend;
     int cnt_written = 0;
-    fend = __shfl(fend, (R - 1) % kWave);
-    if (lane == 0) {
-      int ri = R - 1, cj = Cc - 1;
-      for (int guard = 0; guard < R + Cc; ++guard) {  // every step decrements ri or cj
-        const bool at_start = (ri == 0 && cj == 0);
-        if (!at_start || Lf.first) {
-          const int gi = tr ? (Lf.i0 + cj) : (Lf.i0 + ri);
-          const int gj = tr ? (Lf.j0 + ri) : (Lf.j0 + cj);
-          w.tpath[slot_end - cnt_written] = make_int2((int)(gi - pd.x_off), (int)(gj - pd.y_off));
-          ++cnt_written;
+    if (Lf.scratch_off < 0) {
+      uint32_t* bp = reinterpret_cast<uint32_t*>(lds_raw);
+      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, wave, lane);
+      if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
+    } else {
+      uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
+      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, wave, lane);
+      if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
+    }
+
+    if (wave == 0) {
+      fend = __shfl(fend, (S.R - 1) % kWave);
+      if (lane == 0) {
+        w.cnt[slot_end] = cnt_written;
+        atomicAdd((unsigned long long*)&ctl->leaf_cells, (unsigned long long)((int64_t)S.R * S.Cc));
+        if (Lf.first && Lf.i1 == pd.x_off + pd.M - 1 && Lf.j1 == pd.y_off + pd.N - 1)
+          w.smin[Lf.pair] = (double)fend;
+      }
+      // FP64 cost of the cells this leaf wrote, from the caller's inputs
+      cnt_written = __shfl(cnt_written, 0);
+      wait_vmem();  // lane 0's path cells are written before the wave reads them
+      double2 acc = make_double2(0.0, 0.0);
+      for (int q = lane; q < cnt_written; q += kWave) {
+        const int2 cell = w.tpath[slot_end - cnt_written + 1 + q];
+        const int64_t gi = pd.x_off + cell.x, gj = pd.y_off + cell.y;
+        double ss = 0.0;
+        if (in_f64) {
+          const double* xr = static_cast<const double*>(Xorig) + gi * d;
+          const double* yr = static_cast<const double*>(Yorig) + gj * d;
+          for (int k = 0; k < d; ++k) { const double ee = xr[k] - yr[k]; ss = __builtin_fma(ee, ee, ss); }
+        } else {
+          const float* xr = static_cast<const float*>(Xorig) + gi * d;
+          const float* yr = static_cast<const float*>(Yorig) + gj * d;
+          for (int k = 0; k < d; ++k) { const double ee = (double)xr[k] - (double)yr[k]; ss = __builtin_fma(ee, ee, ss); }
         }
-        if (at_start) break;
-        if (ri == 0) { --cj; continue; }  // first row / column: the only move
-        if (cj == 0) { --ri; continue; }
-        const uint32_t code = (bp[(int64_t)ri * stride + (cj >> 4)] >> (2 * (cj & 15))) & 3u;
-        if (code == 0u) { --ri; --cj; }
-        else if (code == 1u) { if (tr) --cj; else --ri; }
-        else { if (tr) --ri; else --cj; }
+        acc = two_sum_acc(acc, __builtin_sqrt(ss));
       }
-      w.cnt[slot_end] = cnt_written;
-      atomicAdd((unsigned long long*)&ctl->leaf_cells, (unsigned long long)((int64_t)R * Cc));
-      if (Lf.first && Lf.i1 == pd.x_off + pd.M - 1 && Lf.j1 == pd.y_off + pd.N - 1)
-        w.smin[Lf.pair] = (double)fend;
-    }
-    // FP64 cost of the cells this leaf wrote, from the caller's inputs
-    cnt_written = __shfl(cnt_written, 0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    double2 acc = make_double2(0.0, 0.0);
-    for (int q = lane; q < cnt_written; q += kWave) {
-      const int2 cell = w.tpath[slot_end - cnt_written + 1 + q];
-      const int64_t gi = pd.x_off + cell.x, gj = pd.y_off + cell.y;
-      double ss = 0.0;
-      if (in_f64) {
-        const double* xr = static_cast<const double*>(Xorig) + gi * d;
-        const double* yr = static_cast<const double*>(Yorig) + gj * d;
-        for (int k = 0; k < d; ++k) { const double ee = xr[k] - yr[k]; ss = __builtin_fma(ee, ee, ss); }
-      } else {
-        const float* xr = static_cast<const float*>(Xorig) + gi * d;
-        const float* yr = static_cast<const float*>(Yorig) + gj * d;
-        for (int k = 0; k < d; ++k) { const double ee = (double)xr[k] - (double)yr[k]; ss = __builtin_fma(ee, ee, ss); }
+      // fixed-order tree reduction over the wave
+      for (int off = 1; off < kWave; off <<= 1) {
+        const double2 other = make_double2(__shfl_xor(acc.x, off), __shfl_xor(acc.y, off));
+        acc = ((lane & off) == 0) ? dd_add(acc, other) : dd_add(other, acc);
       }
-      acc = two_sum_acc(acc, __builtin_sqrt(ss));
+      if (lane == 0) w.leaf_cost[tk] = acc;
     }
-    // fixed-order tree reduction over the wave
-    for (int off = 1; off < kWave; off <<= 1) {
-      const double2 other = make_double2(__shfl_xor(acc.x, off), __shfl_xor(acc.y, off));
-      acc = ((lane & off) == 0) ? dd_add(acc, other) : dd_add(other, acc);
-    }
-    if (lane == 0) w.leaf_cost[tk] = acc;
   }
 }
 
@@ -576,34 +645,57 @@ hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_leaf(const Work& w, bool f32, int grid, size_t lds_bytes, int64_t lds_leaf_bytes,
-                       const void* Xo, const void* Yo, int in_f64, hipStream_t st) {
+hipError_t launch_leaf(const Work& w, bool f32, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
+                       int in_f64, hipStream_t st) {
   const int dm = pick_dmax(w.d);
+  const size_t dyn = (size_t)lds_leaf_bytes;
   if (f32) {
-    DTW_DISPATCH_DMAX(dm, (leaf_kernel<float, D_><<<grid, kLeafThreads, lds_bytes, st>>>(
+    DTW_DISPATCH_DMAX(dm, (leaf_kernel<float, D_><<<grid, kPassThreads, dyn, st>>>(
                               static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w, lds_leaf_bytes,
                               Xo, Yo, in_f64, w.d)))
   } else {
-    DTW_DISPATCH_DMAX(dm, (leaf_kernel<double, D_><<<grid, kLeafThreads, lds_bytes, st>>>(
+    DTW_DISPATCH_DMAX(dm, (leaf_kernel<double, D_><<<grid, kPassThreads, dyn, st>>>(
                               static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w, lds_leaf_bytes,
                               Xo, Yo, in_f64, w.d)))
   }
   return hipGetLastError();
 }
 
-hipError_t set_leaf_lds_limit(size_t bytes) {
-  hipError_t e = hipSuccess;
-#define DTW_SET_ATTR(T_, D_)                                                                        \
-  {                                                                                                 \
-    hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel<T_, D_>),         \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);     \
-    if (r != hipSuccess) e = r;                                                                     \
+// Dynamic LDS left to the leaf kernels (pointers and bottom row) once their
+// static LDS is taken from `lds_max`, per compute type: the smallest over the
+// frame widths, also set as each kernel's dynamic LDS limit.
+hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32) {
+  int64_t lim[2] = {lds_max, lds_max};
+#define DTW_LEAF_STATIC(T_, D_, I_)                                                               \
+  {                                                                                               \
+    hipFuncAttributes a;                                                                          \
+    hipError_t r = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&leaf_kernel<T_, D_>)); \
+    if (r != hipSuccess) return r;                                                                \
+    const int64_t left = lds_max - (int64_t)a.sharedSizeBytes - 64;                               \
+    if (left < lim[I_]) lim[I_] = left;                                                           \
   }
-  DTW_SET_ATTR(double, 4) DTW_SET_ATTR(double, 8) DTW_SET_ATTR(double, 12) DTW_SET_ATTR(double, 16)
-  DTW_SET_ATTR(double, 24) DTW_SET_ATTR(double, 32) DTW_SET_ATTR(float, 4) DTW_SET_ATTR(float, 8)
-  DTW_SET_ATTR(float, 12) DTW_SET_ATTR(float, 16) DTW_SET_ATTR(float, 24) DTW_SET_ATTR(float, 32)
+  DTW_LEAF_STATIC(double, 4, 0) DTW_LEAF_STATIC(double, 8, 0) DTW_LEAF_STATIC(double, 12, 0)
+  DTW_LEAF_STATIC(double, 16, 0) DTW_LEAF_STATIC(double, 24, 0) DTW_LEAF_STATIC(double, 32, 0)
+  DTW_LEAF_STATIC(float, 4, 1) DTW_LEAF_STATIC(float, 8, 1) DTW_LEAF_STATIC(float, 12, 1)
+  DTW_LEAF_STATIC(float, 16, 1) DTW_LEAF_STATIC(float, 24, 1) DTW_LEAF_STATIC(float, 32, 1)
+#undef DTW_LEAF_STATIC
+  lim[0] &= ~(int64_t)255;
+  lim[1] &= ~(int64_t)255;
+  if (lim[0] < 0 || lim[1] < 0) return hipErrorInvalidValue;
+#define DTW_SET_ATTR(T_, D_, I_)                                                                  \
+  {                                                                                               \
+    hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel<T_, D_>),       \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim[I_]); \
+    if (r != hipSuccess) return r;                                                                \
+  }
+  DTW_SET_ATTR(double, 4, 0) DTW_SET_ATTR(double, 8, 0) DTW_SET_ATTR(double, 12, 0)
+  DTW_SET_ATTR(double, 16, 0) DTW_SET_ATTR(double, 24, 0) DTW_SET_ATTR(double, 32, 0)
+  DTW_SET_ATTR(float, 4, 1) DTW_SET_ATTR(float, 8, 1) DTW_SET_ATTR(float, 12, 1)
+  DTW_SET_ATTR(float, 16, 1) DTW_SET_ATTR(float, 24, 1) DTW_SET_ATTR(float, 32, 1)
 #undef DTW_SET_ATTR
-  return e;
+  *dyn_f64 = lim[0];
+  *dyn_f32 = lim[1];
+  return hipSuccess;
 }
 
 }  // namespace dtw

@@ -258,14 +258,14 @@ hipError_t launch_pass(const Work& w, int level, bool f32, int, hipStream_t) {
   }
   return hipSuccess;
 }
-hipError_t launch_leaf(const Work& w, bool f32, int, size_t, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
+hipError_t launch_leaf(const Work& w, bool f32, int, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
                        int in_f64, hipStream_t) {
   model_check_leaves(w);
   const int D = pick_dmax(w.d);
   if (f32) {
-    MODEL_DISPATCH(D, (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else {
-    MODEL_DISPATCH(D, (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { leaf_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   }
   return hipSuccess;
 }
@@ -275,14 +275,21 @@ hipError_t launch_pass(const Work& w, int, bool f32, int, hipStream_t) {
   else model_pass<double>(w);
   return hipSuccess;
 }
-hipError_t launch_leaf(const Work& w, bool f32, int, size_t, int64_t, const void* Xo, const void* Yo, int in_f64,
+hipError_t launch_leaf(const Work& w, bool f32, int, int64_t, const void* Xo, const void* Yo, int in_f64,
                        hipStream_t) {
   if (f32) model_leaf<float>(w, Xo, Yo, in_f64);
   else model_leaf<double>(w, Xo, Yo, in_f64);
   return hipSuccess;
 }
 #endif
-hipError_t set_leaf_lds_limit(size_t) { return hipSuccess; }
+// The model's LDS: the leaf kernels' static arrays are function statics, so
+// all of cpu_dynamic_lds is left for pointers and the bottom row; a smaller
+// figure keeps some leaves in global scratch as on the device.
+hipError_t leaf_lds_setup(int64_t, int64_t* dyn_f64, int64_t* dyn_f32) {
+  *dyn_f64 = 94 * 1024;
+  *dyn_f32 = 126 * 1024;
+  return hipSuccess;
+}
 
 hipError_t launch_init(const Work& w, hipStream_t) {
   cpu_launch(2, 64, [&] { init_kernel(w); });

@@ -30,8 +30,11 @@ MARK = "// ----------------------------------------------------------------- lau
 # workgroup barrier, completion of outstanding memory operations), and the
 # dynamic LDS array becomes a static buffer.
 WAVE_EDITS = [
-    ('asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));', "r = (b < a) ? b : a;"),
-    ('asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));', "r = (b < a) ? b : a;"),
+    # v_min in IEEE mode returns the other operand of a quiet NaN
+    ('asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));',
+     "r = (a != a) ? b : ((b != b) ? a : ((b < a) ? b : a));"),
+    ('asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));',
+     "r = (a != a) ? b : ((b != b) ? a : ((b < a) ? b : a));"),
     ('asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));', "r = x;"),
     ('asm volatile("s_waitcnt lgkmcnt(0)\\n\\ts_barrier" ::: "memory");', "__syncthreads();"),
     ('asm volatile("s_waitcnt vmcnt(0)" ::: "memory");', "std::atomic_thread_fence(std::memory_order_seq_cst);"),
