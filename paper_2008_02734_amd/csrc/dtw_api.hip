@@ -132,7 +132,10 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   c.gen = 2 * kRing * c.sub + kRing;
   c.ticket = 2 * ((Msum + kWave - 1) / kWave + 2 * c.sub) + Mmax / kWave + 2;
   c.hist = Mmax / kWave + 3;
-  c.leaf_words = ((int64_t)m * (K0sum + c.leaf)) / 16 + ((int64_t)m + 4) * c.leaf + 2 * (K0sum + c.leaf) + 16;
+  // per leaf: ceil(R/64)*64 <= R+63 rows of ceil((Cc+63)/16) <= Cc/16+5 words, R < m,
+  // sum of Cc over leaves <= K0sum + leaves; then 2 words per bottom-row column
+  c.leaf_words = (((int64_t)m + kWave) * (K0sum + c.leaf)) / 16 + ((int64_t)m + kWave) * 6 * c.leaf +
+                 2 * (K0sum + c.leaf) + 64;
   c.pslots = K0sum;
   const bool f32 = precision == DTW_PREC_FP32;
   L.cbytes = f32 ? 4 : 8;

@@ -121,8 +121,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       const int64_t Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
       is_leaf = (Mb < m) || (Nb < m);
       if (is_leaf) {
+        // pointer words by stripe and step (see the leaf kernel), then the
+        // bottom row of a stripe in the compute type (at most 2 words each)
         const int64_t R = min(Mb, Nb), Cc = max(Mb, Nb);
-        const int64_t bpw = ((R * ((Cc + 15) / 16)) + 1) & ~(int64_t)1;
+        const int64_t bpw = ((R + kWave - 1) / kWave) * ((Cc + kWave - 1 + 15) / 16) * kWave;
         const int64_t need = bpw + 2 * Cc;
         if (need * 4 > lds_leaf_bytes) words = need;
       }

@@ -281,12 +281,17 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
 #pragma unroll
             for (int i = 0; i < G; ++i) {
               const int u = g * G + i;
+              // the history takes the previous step's value, off this
+              // step's dependency chain; a group's last value is written
+              // and the group published at once, ahead of the barrier
+              if ((u & (kPubGroup - 1)) != 0) hist[((u - 1) & (kPubGroup - 1)) * kWave + lane] = f;
               const T up = wave_shr1(bb[g & 1][i], f);
               f = min_t(min_t(up_prev, f), up) + cb[g & 1][i];
               up_prev = up;
-              hist[(u & (kPubGroup - 1)) * kWave + lane] = f;
-              if ((u & (kPubGroup - 1)) == kPubGroup - 1 && has_succ)
-                publish<T>(t0 + u, lane, hist, ring_out, pub_max);
+              if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
+                hist[(kPubGroup - 1) * kWave + lane] = f;
+                if (has_succ) publish<T>(t0 + u, lane, hist, ring_out, pub_max);
+              }
             }
           }
         } else {
@@ -294,6 +299,7 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
           for (int t = t0; t < t1; ++t) {
             const int u = t - t0;
             const int b = t - lane;
+            if ((t & (kPubGroup - 1)) != 0) hist[((t - 1) & (kPubGroup - 1)) * kWave + lane] = f;
             const T c = cp[u * kWave];
             const T up = wave_shr1(bp[u], f);
             if (t < t_band) {
@@ -318,9 +324,10 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
               }
             }
             up_prev = up;
-            hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
-            if (has_succ && ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1))
-              publish<T>(t, lane, hist, ring_out, pub_max);
+            if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
+              hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
+              if (has_succ) publish<T>(t, lane, hist, ring_out, pub_max);
+            }
           }
         }
         lds_barrier();
@@ -386,25 +393,125 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
 // Textbook DTW on one leaf block (Sec. 2.1) by one workgroup with the roles
 // of the pass kernel: the shorter side is the row dimension, swept in
 // ceil(R/64) stripes of 64 rows one after the other, the longer side the
-// column dimension.  The recurrence wave also stores a 2-bit backpointer per
+// column dimension.  The recurrence wave also records a 2-bit backpointer per
 // cell: 0 DIAG (i-1,j-1), 1 UP (i-1,j), 2 LEFT (i,j-1), chosen DIAG, then UP,
-// then LEFT on ties; row 0 of X moves LEFT, column 0 of Y moves UP, so the
-// codes stored on row 0 and column 0 are never read.  When the block is
+// then LEFT on ties; row 0 of X moves LEFT and column 0 of Y moves UP, so the
+// codes recorded on row 0 and column 0 are never read.  When the block is
 // transposed (rows = Y frames) UP and LEFT swap roles, and the codes keep
-// their original meaning.  The bottom row of a stripe goes to the next stripe
-// through `brow`; the input wave copies it into the boundary ring one phase
-// ahead.  Lane 0 of the recurrence wave then walks the pointers back from the
-// block's last cell.  `bp` and `brow` point into LDS when the leaf fits there
-// and into global scratch otherwise; the caller inlines one copy per case so
-// that each copy addresses a single memory space.
+// their original meaning.
+//
+// Pointer layout, by step: lane r of stripe st records the codes of its
+// steps 16m..16m+15 (columns 16m-r..16m+15-r) in word ((st*Wm + m)*64 + r),
+// Wm = ceil((Cc+63)/16); all lanes store their word together every 16 steps.
+// The bottom row of a stripe reaches the next stripe through `brow`, written
+// from the recurrence values' LDS history every 16 steps, and the input wave
+// copies it into the boundary ring one phase ahead.  Lane 0 of the
+// recurrence wave then walks the pointers back from the block's last cell.
+// `bp` and `brow` point into LDS when the leaf fits there and into global
+// scratch otherwise; the caller inlines one copy per case so that each copy
+// addresses a single memory space.
 struct LeafShape {
   bool tr;
-  int R, Cc, r0, c0, stride;
+  int R, Cc, r0, c0, Wm;
 };
+
+// Lane 48+u stores step g0+u's value of lane 63 (column g0+u-63 of the
+// stripe's bottom row), g0 = t rounded down to a multiple of kPubGroup.
+template <typename T>
+__device__ __forceinline__ void leaf_publish(int t, int lane, const T* hist, T* brow, int Cc) {
+  const int st = (t & ~(kPubGroup - 1)) + (lane - (kWave - kPubGroup));
+  const int col = st - (kWave - 1);
+  if (lane >= kWave - kPubGroup && st <= t && col >= 0 && col < Cc)
+    brow[col] = hist[(st & (kPubGroup - 1)) * kWave + (kWave - 1)];
+}
+
+// One step of the leaf recurrence with its backpointer code.
+template <typename T, bool TR>
+__device__ __forceinline__ void leaf_step(T c, T bv, T& f, T& up_prev, uint32_t& word, int t) {
+  const T up = wave_shr1(bv, f);
+  const T diag = up_prev, left = f;
+  const T m_dl = min_t(diag, left);
+  f = min_t(m_dl, up) + c;
+  up_prev = up;
+  const bool is_diag = (diag <= left) && (diag <= up);
+  const bool is_up = TR ? (left <= up) : (up <= left);
+  const uint32_t code = is_diag ? 0u : (is_up ? 1u : 2u);
+  word |= code << (2 * (t & 15));
+}
+
+template <typename T, bool TR>
+__device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr, int n_steps, int n_phases,
+                                             bool has_succ, uint32_t* bpst, T* brow, const T* cring,
+                                             const T* bring, T* hist, int lane) {
+  const T INF = inf_t<T>();
+  // Unpredicated steps as in the pass kernel: +inf before a lane's row
+  // starts, DIAG = 0 for the block's first cell.
+  T f = INF;
+  T up_prev = (sw == 0 && lane == 0) ? T(0) : INF;
+  uint32_t word = 0;
+  lds_barrier();  // phase -1
+  for (int k = 0; k < n_phases; ++k) {
+    const int t0 = k * kPhase;
+    const T* cp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
+    const T* bp = bring + in_vgpr(t0 & (2 * kPhase - 1));
+    if (t0 + kPhase <= n_steps) {
+      constexpr int G = kStepGroup;
+      T cb[2][G], bb[2][G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        cb[0][i] = cp[i * kWave];
+        bb[0][i] = bp[i];
+      }
+#pragma unroll
+      for (int g = 0; g < kPhase / G; ++g) {
+        if (g + 1 < kPhase / G) {
+#pragma unroll
+          for (int i = 0; i < G; ++i) {
+            cb[(g + 1) & 1][i] = cp[((g + 1) * G + i) * kWave];
+            bb[(g + 1) & 1][i] = bp[(g + 1) * G + i];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          const int u = g * G + i;
+          // history as in the pass kernel: previous value off the chain,
+          // a group's last value written and published at once
+          if ((u & (kPubGroup - 1)) != 0) hist[((u - 1) & (kPubGroup - 1)) * kWave + lane] = f;
+          leaf_step<T, TR>(cb[g & 1][i], bb[g & 1][i], f, up_prev, word, u);
+          if ((u & 15) == 15) {
+            bpst[((t0 + u) >> 4) * kWave + lane] = word;
+            word = 0u;
+          }
+          if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
+            hist[(kPubGroup - 1) * kWave + lane] = f;
+            if (has_succ) leaf_publish<T>(t0 + u, lane, hist, brow, S.Cc);
+          }
+        }
+      }
+    } else {
+      for (int t = t0; t < n_steps; ++t) {
+        const int u = t - t0;
+        if ((t & (kPubGroup - 1)) != 0) hist[((t - 1) & (kPubGroup - 1)) * kWave + lane] = f;
+        leaf_step<T, TR>(cp[u * kWave], bp[u], f, up_prev, word, t);
+        if ((t & 15) == 15 || t == n_steps - 1) {
+          bpst[(t >> 4) * kWave + lane] = word;
+          word = 0u;
+        }
+        if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
+          hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
+          if (has_succ) leaf_publish<T>(t, lane, hist, brow, S.Cc);
+        }
+      }
+    }
+    lds_barrier();
+  }
+  (void)Lr;
+  return f;  // lane Lr ends on the stripe's last cell (its column Cc-1 is the last step)
+}
 
 template <typename T, int D>
 __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* __restrict__ ColSrc, const LeafShape& S,
-                                        uint32_t* bp, T* brow, T* cring, T* bring, int wave, int lane) {
+                                        uint32_t* bp, T* brow, T* cring, T* bring, T* hist, int wave, int lane) {
   const T INF = inf_t<T>();
   T fend = T(0);
   for (int sw = 0; sw < S.R; sw += kWave) {
@@ -414,42 +521,9 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     const bool has_pred = sw > 0;
     const bool has_succ = sw + kWave < S.R;
     if (wave == 0) {
-      // ------------------------------------------------ recurrence + pointers
-      // Unpredicated steps as in the pass kernel: +inf before a lane's row
-      // starts, DIAG = 0 for the block's first cell.
-      const int a = sw + lane;
-      const bool row_ok = lane <= Lr;
-      T f = INF;
-      T up_prev = (sw == 0 && lane == 0) ? T(0) : INF;
-      uint32_t word = 0;
-      int64_t bidx = (int64_t)a * S.stride;  // word of column 0 of the lane's row
-      lds_barrier();                          // phase -1
-      for (int k = 0; k < n_phases; ++k) {
-        const int t0 = k * kPhase;
-        const T* cp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
-        const T* bpl = bring + in_vgpr(t0 & (2 * kPhase - 1));
-        const int t1 = min(t0 + kPhase, n_steps);
-        for (int t = t0; t < t1; ++t) {
-          const int u = t - t0;
-          const int b = t - lane;
-          const T c = cp[u * kWave];
-          const T up = wave_shr1(bpl[u], f);
-          const T diag = up_prev, left = f;
-          uint32_t code;
-          if (diag <= up && diag <= left) code = 0u;
-          else if (S.tr ? (left <= up) : (up <= left)) code = 1u;
-          else code = 2u;
-          f = min_t(min_t(diag, up), left) + c;
-          up_prev = up;
-          word |= code << (2 * (b & 15));
-          const bool in_row = row_ok && b >= 0 && b < S.Cc;
-          if (in_row && ((b & 15) == 15 || b == S.Cc - 1)) bp[bidx + (b >> 4)] = word;
-          if ((b & 15) == 15) word = 0u;
-          if (has_succ && lane == kWave - 1 && b >= 0 && b < S.Cc) brow[b] = f;
-          if (a == S.R - 1 && b == S.Cc - 1) fend = f;
-        }
-        lds_barrier();
-      }
+      uint32_t* bpst = bp + (int64_t)(sw / kWave) * S.Wm * kWave;
+      fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane)
+                  : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane);
     } else if (wave <= kProducers) {
       // ------------------------------------------------ frame costs
       const int pw = wave - 1;
@@ -483,7 +557,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
         lds_barrier();
       }
     }
-    // the stripe's bottom row is complete for the next stripe
+    // the stripe's bottom row and pointers are complete for the next stripe
     __syncthreads();
   }
   return fend;
@@ -508,7 +582,10 @@ __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShap
     if (at_start) break;
     if (ri == 0) { --cj; continue; }  // first row / column: the only move
     if (cj == 0) { --ri; continue; }
-    const uint32_t code = (bp[(int64_t)ri * S.stride + (cj >> 4)] >> (2 * (cj & 15))) & 3u;
+    const int r = ri & (kWave - 1);
+    const int t = cj + r;
+    const uint32_t wd = bp[((int64_t)(ri >> 6) * S.Wm + (t >> 4)) * kWave + r];
+    const uint32_t code = (wd >> (2 * (t & 15))) & 3u;
     if (code == 0u) { --ri; --cj; }
     else if (code == 1u) { if (S.tr) --cj; else --ri; }
     else { if (S.tr) --ri; else --cj; }
@@ -517,11 +594,12 @@ __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShap
 }
 
 template <typename T, int D>
-__global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void leaf_kernel(
+__global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     const T* __restrict__ X, const T* __restrict__ Y, Work w, int64_t lds_leaf_bytes, const void* Xorig,
     const void* Yorig, int in_f64, int d) {
   extern __shared__ __align__(16) unsigned char lds_raw[];  // pointers and bottom row when they fit
   __shared__ T cring[kCostRing * kWave];
+  __shared__ T hist[kPubGroup * kWave];
   __shared__ T bring[2 * kPhase];
   __shared__ int sh_ticket;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -555,21 +633,21 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void leaf_kernel(
     S.Cc = S.tr ? Mb : Nb;
     S.r0 = S.tr ? Lf.j0 : Lf.i0;
     S.c0 = S.tr ? Lf.i0 : Lf.j0;
-    S.stride = (S.Cc + 15) / 16;
+    S.Wm = (S.Cc + kWave - 1 + 15) / 16;
     const T* __restrict__ RowSrc = S.tr ? Y : X;
     const T* __restrict__ ColSrc = S.tr ? X : Y;
-    const int64_t bpw = (((int64_t)S.R * S.stride) + 1) & ~(int64_t)1;
+    const int64_t bpw = (int64_t)((S.R + kWave - 1) / kWave) * S.Wm * kWave;
     const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
     const int64_t slot_end = pd.pbase + e;  // the block's last cell sits on diagonal e
     T fend;
     int cnt_written = 0;
     if (Lf.scratch_off < 0) {
       uint32_t* bp = reinterpret_cast<uint32_t*>(lds_raw);
-      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, wave, lane);
+      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, hist, wave, lane);
       if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
     } else {
       uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
-      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, wave, lane);
+      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, hist, wave, lane);
       if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
     }
 
