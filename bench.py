@@ -41,6 +41,26 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pass_kernel_f64_d12_20000x16000_hbm_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2008_02734_amd", "csrc", "dtw_wave.hip")
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter record
+    (FETCH_SIZE and WRITE_SIZE scaled by a calibrating copy), or None when the
+    sweep kernel's source has changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_RECORD).read()
+        rec = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line and " " not in line.split(": ")[0])
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if not sha.startswith(rec["kernel_source_sha256_prefix"].strip()):
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,7 +68,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (calibration of HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe << 17, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8, "dispatches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method is measured on one "
               f"MI355X and the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
@@ -121,7 +152,7 @@ def main():
             "peak": peak,
             "unit": "Gcells/s",
             "frac": (achieved / peak) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic() if args.config == 2 else None,
             "launches_per_step": sweep_launches,
             "sweep_cells_per_step": st["sweep_cells"],
             "avg_sweep_launch_ms": sweep_ms / max(1, sweep_launches),
