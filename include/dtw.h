@@ -85,7 +85,10 @@ typedef struct dtw_stats {
   double s_min;            /* min of F + B - C at the top split (the optimal cost up to
                               rounding), or the full-table cost when the whole problem is
                               one leaf                                                     */
-  double cost_lowp;        /* reserved: internal reduced-precision cost (0 in FP64 mode)  */
+  double cost_lowp;        /* reduced-precision modes: s_min as the low-precision sweeps
+                              see it (their accumulated costs widened to FP64), i.e. the
+                              internal optimum before the FP64 re-evaluation of the path;
+                              0 in FP64 mode                                              */
   int64_t cells_processed; /* cells evaluated by both half sweeps of every split plus the
                               cells of every leaf table (progress measure of Sec. 3.2)     */
   int64_t path_len;        /* number of (i,j) pairs written                               */

@@ -394,6 +394,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
       stats->ms_other = ms[kProfOther];
     }
     stats->s_min = smin;
+    stats->cost_lowp = (opts.precision == DTW_PREC_FP64) ? 0.0 : smin;
     stats->cells_processed = c.cells + c.leaf_cells;
     stats->sweep_cells = c.cells;
     stats->leaf_cells = c.leaf_cells;

@@ -1,0 +1,93 @@
+"""Reduced-precision forms against the FP64 oracle (the benchmark spec precision form).
+
+FP32 form: frame costs and the accumulated-cost recurrence in FP32 on the
+VALU; band sums S = F + B - C and the argmin in FP64 (the FP32 values
+widened); the returned cost is the FP64 sum of FP64 frame costs along the
+returned path.  The gate is the relative error of that cost against the
+oracle's optimum, <= 1e-5.  The frame deviation of the path from the FP64
+path (Sec. 5.3 discrepancy) is reported.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2008_02734_amd import metrics, synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_REL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dtw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_02734_amd import dtw as mod
+    mod.lib()
+    return mod
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def check_path(p, M, N):
+    assert tuple(p[0]) == (0, 0) and tuple(p[-1]) == (M - 1, N - 1)
+    steps = {tuple(s) for s in np.diff(p, axis=0).tolist()}
+    assert steps <= {(0, 1), (1, 0), (1, 1)}
+
+
+def fp32_case(dtw, X, Y, m, in_dtype=torch.float64):
+    M, N = X.shape[0], Y.shape[0]
+    cost, path, st = dtw.align(dev(X, in_dtype), dev(Y, in_dtype), precision="fp32", min_block=m)
+    p = path.cpu().numpy()
+    check_path(p, M, N)
+    Xo = X.astype(np.float64) if in_dtype == torch.float64 else X.astype(np.float32).astype(np.float64)
+    Yo = Y.astype(np.float64) if in_dtype == torch.float64 else Y.astype(np.float32).astype(np.float64)
+    c_ref, p_ref = oracle.full(Xo, Yo)
+    # the returned cost is the FP64 cost of the returned path
+    assert abs(cost - oracle.path_cost(Xo, Yo, p)) <= 1e-12 * c_ref
+    rel = (cost - c_ref) / c_ref
+    assert -1e-12 <= rel <= FP32_REL_TOL, rel
+    dev_ = metrics.summary(p, p_ref)
+    lowp_rel = abs(st["cost_lowp"] - c_ref) / c_ref
+    print(f"M={M} N={N} m={m}: rel cost err {rel:.2e}, internal FP32 cost err {lowp_rel:.2e}, "
+          f"frame deviation mean {dev_['mean_frames']:.3f} max {dev_['max_frames']}")
+    return rel, dev_, st
+
+
+def test_fp32_config2_pair(dtw):
+    X, Y = synth.config_pair(2)
+    rel, dv, st = fp32_case(dtw, X, Y, 500)
+    assert st["device_error"] == 0 and st["levels"] >= 5
+    assert st["cost_lowp"] > 0
+
+
+@pytest.mark.parametrize("m", [500, 64, 16])
+def test_fp32_config1_pair(dtw, m):
+    X, Y = synth.config_pair(1)
+    fp32_case(dtw, X, Y, m)
+
+
+@pytest.mark.parametrize("p", range(4))
+def test_fp32_chroma_d24_float_inputs(dtw, p):
+    # the batched form's frames: d = 24 chroma-like, FP32 inputs
+    M, N = synth.batch_shapes(4, lo=1000, hi=6000)[p]
+    X, Y = synth.make_pair(4, p, M, N, 24, "chroma")
+    fp32_case(dtw, X.astype(np.float32), Y.astype(np.float32), 500, in_dtype=torch.float32)
+
+
+def test_fp32_batched_equals_single(dtw):
+    shapes = synth.batch_shapes(6, lo=500, hi=3000)
+    Xs, Ys = [], []
+    for p, (M, N) in enumerate(shapes):
+        X, Y = synth.make_pair(4, 100 + p, M, N, 24, "chroma")
+        Xs.append(dev(X.astype(np.float32), torch.float32))
+        Ys.append(dev(Y.astype(np.float32), torch.float32))
+    costs, paths, st = dtw.align_batched(Xs, Ys, precision="fp32", min_block=500)
+    assert st["device_error"] == 0
+    for b in range(len(shapes)):
+        c1, p1, _ = dtw.align(Xs[b], Ys[b], precision="fp32", min_block=500)
+        assert costs[b].item() == c1
+        assert torch.equal(paths[b], p1)
