@@ -130,7 +130,8 @@ dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
  *   stats       host, may be NULL; when set the call synchronises `stream`
  *   stream      hipStream_t or NULL
  * Supported feature dimensions: 1 <= d <= 32 for DTW_PREC_FP64 / FP32,
- * d a multiple of 32 up to 256 for DTW_PREC_BF16_COST. */
+ * 1 <= d <= 128 for DTW_PREC_BF16_COST (frames zero-padded to 32, 64 or 128);
+ * other d give DTW_ERR_UNSUPPORTED. */
 dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t d,
                      int32_t in_dtype, const dtw_opts* opts, void* workspace,
                      size_t ws_bytes, double* cost_out, int32_t* path_out,

@@ -11,9 +11,9 @@
 #include "dtw_internal.h"
 
 namespace dtw {
-hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t st);
-hipError_t launch_leaf(const Work& w, bool f32, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
-                       int in_f64, hipStream_t st);
+hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st);
+hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
+                       hipStream_t st);
 hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32);
 hipError_t launch_init(const Work& w, hipStream_t st);
 hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t st);
@@ -22,10 +22,13 @@ hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* 
                            int32_t* paths, int grid, hipStream_t st);
 hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
                               hipStream_t st);
+hipError_t launch_bf16_stage(const void* in, int in_f64, int64_t rows, int d, int D, uint16_t* out, float* norms,
+                             hipStream_t st);
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st);
 hipError_t launch_diag(const Work& w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
-                       int32_t kstop, bool f32, int grid, double* out, hipStream_t st);
+                       int32_t kstop, int grid, double* out, hipStream_t st);
 int pick_dmax(int d);
+int pick_dgram(int d);
 }  // namespace dtw
 
 using namespace dtw;
@@ -94,7 +97,8 @@ struct Layout {
   int cbytes = 8;  // bytes of the compute type
   int D = 0;       // padded frame stride of the compute copies
   Region ctl, pairs, subs0, subs1, piv_key, piv_pos, smin, passes, tickets, hist, chunk_sub, bandF, bandC,
-      bandB, ring, gens, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, nonfinite;
+      bandB, ring, gens, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, xnorm, ynorm,
+      nonfinite;
   size_t total = 0;
 };
 
@@ -104,7 +108,13 @@ void put(Layout& L, Region& r, size_t bytes) {
   L.total = r.off + bytes;
 }
 
-bool valid_precision(int p) { return p == DTW_PREC_FP64 || p == DTW_PREC_FP32; }
+bool valid_precision(int p) { return p == DTW_PREC_FP64 || p == DTW_PREC_FP32 || p == DTW_PREC_BF16_COST; }
+
+// Padded frame width of the compute copies for a precision, 0 if unsupported.
+int frame_width(int d, int precision) {
+  if (d < 1) return 0;
+  return precision == DTW_PREC_BF16_COST ? pick_dgram(d) : pick_dmax(d);
+}
 
 // Xrows / Yrows: frames of X / Y that the compute copies must cover.
 Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vector<int64_t>& Ns, int d,
@@ -137,10 +147,11 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   c.leaf_words = (((int64_t)m + kWave) * (K0sum + c.leaf)) / 16 + ((int64_t)m + kWave) * 6 * c.leaf +
                  2 * (K0sum + c.leaf) + 64;
   c.pslots = K0sum;
-  const bool f32 = precision == DTW_PREC_FP32;
+  const bool gram = precision == DTW_PREC_BF16_COST;
+  const bool f32 = precision == DTW_PREC_FP32 || gram;  // compute type of the recurrence
   L.cbytes = f32 ? 4 : 8;
-  L.D = pick_dmax(d);
-  L.conv = (f32 && in_dtype == DTW_F64) || (!f32 && in_dtype == DTW_F32) || (L.D != d);
+  L.D = frame_width(d, precision);
+  L.conv = gram || (f32 && in_dtype == DTW_F64) || (!f32 && in_dtype == DTW_F32) || (L.D != d);
   put(L, L.ctl, sizeof(Ctl));
   put(L, L.pairs, sizeof(PairDesc) * n_pairs);
   put(L, L.subs0, sizeof(Block) * c.sub);
@@ -165,8 +176,13 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   put(L, L.lidx, 4 * c.pslots);
   put(L, L.leaf_cost, 16 * c.leaf);
   if (L.conv) {
-    put(L, L.xconv, (size_t)L.cbytes * Xrows * L.D);
-    put(L, L.yconv, (size_t)L.cbytes * Yrows * L.D);
+    const size_t eb = gram ? 2 : (size_t)L.cbytes;  // bf16 frames in the Gram form
+    put(L, L.xconv, eb * Xrows * L.D);
+    put(L, L.yconv, eb * Yrows * L.D);
+  }
+  if (gram) {
+    put(L, L.xnorm, 4 * (size_t)Xrows);
+    put(L, L.ynorm, 4 * (size_t)Yrows);
   }
   put(L, L.nonfinite, 4);
   return L;
@@ -288,6 +304,37 @@ struct Profiler {
     HIP_TRY((P).end());            \
   } while (0)
 
+// Compute copies of the inputs when the layout asks for them: padded /
+// converted frames for the Euclidean forms, bf16 frames and their FP32
+// squared norms for the Gram form.  Points w.X / w.Y (and w.Xn / w.Yn) at
+// what the kernels read.
+hipError_t stage_inputs(const Layout& L, void* ws, const void* X, const void* Y, int in_f64, int64_t xrows,
+                        int64_t yrows, int d, int precision, Work& w, hipStream_t st) {
+  w.X = X;
+  w.Y = Y;
+  w.Xn = nullptr;
+  w.Yn = nullptr;
+  if (!L.conv) return hipSuccess;
+  void* xc = at<void>(ws, L.xconv);
+  void* yc = at<void>(ws, L.yconv);
+  hipError_t e;
+  if (precision == DTW_PREC_BF16_COST) {
+    float* xn = at<float>(ws, L.xnorm);
+    float* yn = at<float>(ws, L.ynorm);
+    e = launch_bf16_stage(X, in_f64, xrows, d, L.D, static_cast<uint16_t*>(xc), xn, st);
+    if (e == hipSuccess) e = launch_bf16_stage(Y, in_f64, yrows, d, L.D, static_cast<uint16_t*>(yc), yn, st);
+    w.Xn = xn;
+    w.Yn = yn;
+  } else {
+    const int out_f64 = precision == DTW_PREC_FP64 ? 1 : 0;
+    e = launch_pad_convert(X, in_f64, xc, out_f64, xrows, d, L.D, st);
+    if (e == hipSuccess) e = launch_pad_convert(Y, in_f64, yc, out_f64, yrows, d, L.D, st);
+  }
+  w.X = xc;
+  w.Y = yc;
+  return e;
+}
+
 // Core of dtw_align and dtw_align_batched.
 dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, const int64_t* yo, int d,
                int in_dtype, const dtw_opts* opts_in, void* ws, size_t ws_bytes, double* costs,
@@ -299,7 +346,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   if (n_pairs < 1 || !X || !Y || !xo || !yo || !ws || !costs || !paths || !lens) return DTW_ERR_INVALID_ARG;
   if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
   if (d < 1) return DTW_ERR_INVALID_ARG;
-  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  if (frame_width(d, opts.precision) == 0) return DTW_ERR_UNSUPPORTED;
   std::vector<int64_t> Ms(n_pairs), Ns(n_pairs);
   std::vector<PairDesc> pd(n_pairs);
   int64_t pbase = 0, Mtot = 0, Ntot = 0;
@@ -324,7 +371,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   const int m = opts.min_block;
   Layout L = plan_layout(n_pairs, Ms, Ns, d, in_dtype, opts.precision, m, Mtot, Ntot);
   if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
-  const bool f32 = opts.precision == DTW_PREC_FP32;
+  const bool f32 = opts.precision != DTW_PREC_FP64;  // FP32 recurrence (FP32 and Gram forms)
   const int in_f64 = in_dtype == DTW_F64;
   DevInfo& I = dev_info();
   if (!I.attr_set) {
@@ -350,14 +397,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   w.Y = Y;
   // one boundary wait may last at most DTW_SPIN_LIMIT_MS (default 20 s)
   w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
-  if (L.conv) {
-    void* xc = at<void>(ws, L.xconv);
-    void* yc = at<void>(ws, L.yconv);
-    PROF_TRY(prof, kProfOther, launch_pad_convert(X, in_f64, xc, !f32, Mtot, d, L.D, st));
-    PROF_TRY(prof, kProfOther, launch_pad_convert(Y, in_f64, yc, !f32, Ntot, d, L.D, st));
-    w.X = xc;
-    w.Y = yc;
-  }
+  PROF_TRY(prof, kProfOther, stage_inputs(L, ws, X, Y, in_f64, Mtot, Ntot, d, opts.precision, w, st));
   HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
   PROF_TRY(prof, kProfOther, launch_init(w, st));
 
@@ -368,10 +408,10 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
     const int final_level = (lvl == L.lmax) ? 1 : 0;
     PROF_TRY(prof, kProfPlan, launch_plan(w, lvl, final_level, lds_leaf_bytes, st));
     if (final_level) break;
-    PROF_TRY(prof, kProfSweep, launch_pass(w, lvl, f32, pass_grid, st));
+    PROF_TRY(prof, kProfSweep, launch_pass(w, lvl, pass_grid, st));
     PROF_TRY(prof, kProfSplit, launch_combine(w, comb_grid, st));
   }
-  PROF_TRY(prof, kProfLeaf, launch_leaf(w, f32, I.cus, lds_leaf_bytes, X, Y, in_f64, st));
+  PROF_TRY(prof, kProfLeaf, launch_leaf(w, I.cus, lds_leaf_bytes, X, Y, in_f64, st));
   PROF_TRY(prof, kProfOther,
            launch_assemble(w, at<int32_t>(ws, L.poff), at<int32_t>(ws, L.lidx), costs, lens, paths, I.cus * 2, st));
 
@@ -446,7 +486,7 @@ dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
   if (rc != DTW_OK) return rc;
   if (!bytes || M < 1 || N < 1 || d < 1 || M > INT32_MAX || N > INT32_MAX) return DTW_ERR_INVALID_ARG;
   if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
-  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  if (frame_width(d, opts.precision) == 0) return DTW_ERR_UNSUPPORTED;
   std::vector<int64_t> Ms{M}, Ns{N};
   *bytes = plan_layout(1, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, M, N).total;
   return DTW_OK;
@@ -469,7 +509,7 @@ dtw_status dtw_workspace_size_batched(int32_t B, const int64_t* x_offsets, const
   if (rc != DTW_OK) return rc;
   if (!bytes || B < 1 || !x_offsets || !y_offsets || d < 1) return DTW_ERR_INVALID_ARG;
   if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
-  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  if (frame_width(d, opts.precision) == 0) return DTW_ERR_UNSUPPORTED;
   std::vector<int64_t> Ms(B), Ns(B);
   int64_t Xrows = 0, Yrows = 0;
   for (int b = 0; b < B; ++b) {
@@ -500,10 +540,9 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype, i
   if (i1 > INT32_MAX || j1 > INT32_MAX) return DTW_ERR_INVALID_ARG;
   if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
   if (!valid_precision(precision)) return DTW_ERR_UNSUPPORTED;
-  if (pick_dmax(d) == 0) return DTW_ERR_UNSUPPORTED;
+  if (frame_width(d, precision) == 0) return DTW_ERR_UNSUPPORTED;
   const int64_t Mb = i1 - i0 + 1, Nb = j1 - j0 + 1;
   if (kstop < 2 || kstop > Mb + Nb - 2) return DTW_ERR_INVALID_ARG;
-  const bool f32 = precision == DTW_PREC_FP32;
   const int in_f64 = in_dtype == DTW_F64;
   std::vector<int64_t> Ms{Mb}, Ns{Nb};
   // same layout as dtw_workspace_size(i1+1, j1+1, d, in_dtype, opts with this precision)
@@ -516,21 +555,12 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype, i
   if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   Work w = make_work(L, workspace, d, 500, precision);
-  w.X = X;
-  w.Y = Y;
-  if (L.conv) {
-    void* xc = at<void>(workspace, L.xconv);
-    void* yc = at<void>(workspace, L.yconv);
-    HIP_TRY(launch_pad_convert(X, in_f64, xc, !f32, i1 + 1, d, L.D, st));
-    HIP_TRY(launch_pad_convert(Y, in_f64, yc, !f32, j1 + 1, d, L.D, st));
-    w.X = xc;
-    w.Y = yc;
-  }
+  HIP_TRY(stage_inputs(L, workspace, X, Y, in_f64, i1 + 1, j1 + 1, d, precision, w, st));
   w.bandC = nullptr;
   DevInfo& I = dev_info();
   w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
-  HIP_TRY(launch_diag(w, (int32_t)i0, (int32_t)j0, (int32_t)i1, (int32_t)j1, reverse ? 1 : 0, (int32_t)kstop, f32,
-                      I.cus * 4, out, st));
+  HIP_TRY(launch_diag(w, (int32_t)i0, (int32_t)j0, (int32_t)i1, (int32_t)j1, reverse ? 1 : 0, (int32_t)kstop,
+                      I.cus * 2, out, st));
   return DTW_OK;
 }
 

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dtw.h"
+
 namespace dtw {
 
 constexpr int kWave = 64;        // gfx950 wavefront width; one lane per DP row
@@ -25,6 +27,11 @@ constexpr int kPassThreads = kWave * (kProducers + 2);
 constexpr int kPhase = 32;
 constexpr int kCostRing = 128;  // LDS cost slots, indexed by step
 constexpr int kPubGroup = 16;   // steps per boundary-row publication
+
+// Frame cost forms: the exact Euclidean cost on the VALU (FP64 or FP32), or
+// the BF16 Gram form on the matrix cores (dtw_gram.h).
+constexpr int kCostEuclid = 0;
+constexpr int kCostGram = 1;
 
 // Content of a boundary-ring cell that has not been written: a signalling
 // NaN.  No arithmetic result is a signalling NaN, so a cell holding any other
@@ -125,8 +132,10 @@ struct Work {
   int32_t min_block;
   int32_t d;
   int32_t precision;
-  const void* X;        // compute-type copies (or the caller's arrays)
+  const void* X;        // compute-type copies (or the caller's arrays); bf16 in the Gram form
   const void* Y;
+  const float* Xn;      // Gram form: squared norms of the bf16 frames, FP32
+  const float* Yn;
   Block* subs[2];
   uint64_t* piv_key;    // per block of the current level: bits of min split cost
   uint64_t* piv_pos;    // per block: (q << 32) | local row of the argmin

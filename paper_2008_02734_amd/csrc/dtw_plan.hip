@@ -453,6 +453,37 @@ __global__ void nonfinite_kernel(const TI* in, int64_t n, int32_t* flag) {
     if (!__builtin_isfinite((double)in[u])) atomicOr(flag, 1);
 }
 
+// Input staging of the Gram form: each frame rounded to bf16 (round to
+// nearest even; FP64 inputs are first rounded to FP32), zero-padded to D
+// dimensions, and its squared norm from the rounded values in FP32.  One wave
+// per frame: lane l holds dimensions l and l + 64; the norm is reduced over
+// the wave in a fixed order.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void bf16_stage_kernel(const TI* __restrict__ in, int64_t rows, int d, int D,
+                                                          uint16_t* __restrict__ out, float* __restrict__ norms) {
+  const int lane = threadIdx.x % 64;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; r < rows; r += nw) {
+    float s = 0.0f;
+    for (int k = lane; k < D; k += 64) {
+      const float f = (k < d) ? (float)in[r * d + k] : 0.0f;
+      const uint16_t h = f32_to_bf16_rne(f);
+      out[r * D + k] = h;
+      const float g = __builtin_bit_cast(float, (uint32_t)h << 16);
+      s = __builtin_fmaf(g, g, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) norms[r] = s;
+  }
+}
+
 __global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
                                   int32_t kstop) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -479,7 +510,7 @@ __global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, in
 
 // ----------------------------------------------------------------- launchers
 
-hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t st);
+hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st);
 
 hipError_t launch_init(const Work& w, hipStream_t st) {
   init_kernel<<<256, 256, 0, st>>>(w);
@@ -515,6 +546,13 @@ hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64
     pad_convert_kernel<float, float><<<grid, 256, 0, st>>>((const float*)in, (float*)out, rows, d, D);
   return hipGetLastError();
 }
+hipError_t launch_bf16_stage(const void* in, int in_f64, int64_t rows, int d, int D, uint16_t* out, float* norms,
+                             hipStream_t st) {
+  const int grid = (int)min((int64_t)2048, (rows + 3) / 4 + 1);
+  if (in_f64) bf16_stage_kernel<double><<<grid, 256, 0, st>>>((const double*)in, rows, d, D, out, norms);
+  else bf16_stage_kernel<float><<<grid, 256, 0, st>>>((const float*)in, rows, d, D, out, norms);
+  return hipGetLastError();
+}
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st) {
   const int grid = (int)min((int64_t)1024, (n + 255) / 256 + 1);
   if (in_f64) nonfinite_kernel<double><<<grid, 256, 0, st>>>((const double*)in, n, flag);
@@ -522,10 +560,10 @@ hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag
   return hipGetLastError();
 }
 hipError_t launch_diag(const Work& w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
-                       int32_t kstop, bool f32, int grid, double* out, hipStream_t st) {
+                       int32_t kstop, int grid, double* out, hipStream_t st) {
   init_kernel<<<256, 256, 0, st>>>(w);
   diag_setup_kernel<<<1, 1, 0, st>>>(w, i0, j0, i1, j1, dir, kstop);
-  hipError_t e = launch_pass(w, 0, f32, grid, st);
+  hipError_t e = launch_pass(w, 0, grid, st);
   if (e != hipSuccess) return e;
   diag_out_kernel<<<64, 256, 0, st>>>(w, out);
   return hipGetLastError();

@@ -4,6 +4,7 @@
 // wave-level primitives (DPP lane shift, readfirstlane, scalar frame loads)
 // live only in this file.
 #include "dtw_common.h"
+#include "dtw_gram.h"
 
 #pragma clang fp contract(off)
 
@@ -189,7 +190,53 @@ __device__ __forceinline__ void publish(int t, int lane, const T* hist, typename
   }
 }
 
-template <typename T, int D>
+// BF16 Gram-form producer (dtw_gram.h): waves 1 and 2 compute the 32x32
+// cost tiles of stripe rows 0..31 and 32..63 for the 32 columns of the next
+// phase with DP/16 matrix-core operations each, then the FP32 epilogue
+// sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring; the other producer
+// waves only keep the barrier count.  Row r of the stripe is frame
+// gi0 + gis*(a0 + r) of Xb, column j is frame gj0 + gjs*j of Yb; rows past Lr
+// reuse row Lr and columns past need_max reuse column need_max.
+template <int DP>
+__device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, const uint16_t* __restrict__ Yb,
+                                              const float* __restrict__ Xn, const float* __restrict__ Yn, int gi0,
+                                              int gis, int gj0, int gjs, int a0, int Lr, int need_max, int n_phases,
+                                              int wave, int lane, float* cring) {
+  constexpr int KB = DP / 16;
+  const int tile = wave - 1;
+  const bool active = tile < 2;
+  const int half = lane >> 5, l32 = lane & 31;
+  bf16x8_t A[KB];
+  float nx[16];
+  if (active) {
+    const uint16_t* xr = Xb + (int64_t)(gi0 + gis * (a0 + min(tile * 32 + l32, Lr))) * DP + 8 * half;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) A[kb] = load_bf16x8(xr + 16 * kb);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) nx[q] = Xn[gi0 + gis * (a0 + min(tile * 32 + 8 * (q / 4) + 4 * half + q % 4, Lr))];
+  }
+  for (int k = -1; k < n_phases; ++k) {
+    const int c0 = (k + 1) * kPhase;
+    if (active && c0 <= need_max) {
+      const int j = c0 + l32;
+      const int gj = gj0 + gjs * min(j, need_max);
+      const uint16_t* yr = Yb + (int64_t)gj * DP + 8 * half;
+      f32x16_t acc = f32x16_zero();
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32x32x16(A[kb], load_bf16x8(yr + 16 * kb), acc);
+      const float ny = Yn[gj];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int row = tile * 32 + 8 * (q / 4) + 4 * half + q % 4;
+        const float v = fmaxf(__builtin_fmaf(-2.0f, acc[q], nx[q] + ny), 0.0f);
+        cring[((j + row) & (kCostRing - 1)) * kWave + row] = __builtin_amdgcn_sqrtf(v);
+      }
+    }
+    lds_barrier();
+  }
+}
+
+template <typename T, int D, int CM>
 __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   using U = typename RingWord<T>::U;
@@ -332,6 +379,12 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
         }
         lds_barrier();
       }
+    } else if (wave <= kProducers && CM == kCostGram) {
+      // ------------------------------------------------ frame costs, BF16 Gram form
+      if constexpr (CM == kCostGram)
+        gram_producer<D>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
+                         P.dir ? P.i1 : P.i0, P.dir ? -1 : 1, P.dir ? P.j1 : P.j0, P.dir ? -1 : 1, a0, Lr,
+                         need_max, n_phases, wave, lane, reinterpret_cast<float*>(cring));
     } else if (wave <= kProducers) {
       // ------------------------------------------------ frame costs
       const int pw = wave - 1;
@@ -509,9 +562,11 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
   return f;  // lane Lr ends on the stripe's last cell (its column Cc-1 is the last step)
 }
 
-template <typename T, int D>
-__device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* __restrict__ ColSrc, const LeafShape& S,
-                                        uint32_t* bp, T* brow, T* cring, T* bring, T* hist, int wave, int lane) {
+template <typename T, int D, int CM>
+__device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* __restrict__ ColSrc,
+                                        const float* __restrict__ RowN, const float* __restrict__ ColN,
+                                        const LeafShape& S, uint32_t* bp, T* brow, T* cring, T* bring, T* hist,
+                                        int wave, int lane) {
   const T INF = inf_t<T>();
   T fend = T(0);
   for (int sw = 0; sw < S.R; sw += kWave) {
@@ -524,6 +579,12 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
       uint32_t* bpst = bp + (int64_t)(sw / kWave) * S.Wm * kWave;
       fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane)
                   : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane);
+    } else if (wave <= kProducers && CM == kCostGram) {
+      // ------------------------------------------------ frame costs, BF16 Gram form
+      if constexpr (CM == kCostGram)
+        gram_producer<D>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
+                         ColN, S.r0 + sw, 1, S.c0, 1, 0, Lr, S.Cc - 1, n_phases, wave, lane,
+                         reinterpret_cast<float*>(cring));
     } else if (wave <= kProducers) {
       // ------------------------------------------------ frame costs
       const int pw = wave - 1;
@@ -593,7 +654,7 @@ __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShap
   return cnt;
 }
 
-template <typename T, int D>
+template <typename T, int D, int CM>
 __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     const T* __restrict__ X, const T* __restrict__ Y, Work w, int64_t lds_leaf_bytes, const void* Xorig,
     const void* Yorig, int in_f64, int d) {
@@ -634,8 +695,13 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     S.r0 = S.tr ? Lf.j0 : Lf.i0;
     S.c0 = S.tr ? Lf.i0 : Lf.j0;
     S.Wm = (S.Cc + kWave - 1 + 15) / 16;
-    const T* __restrict__ RowSrc = S.tr ? Y : X;
-    const T* __restrict__ ColSrc = S.tr ? X : Y;
+    // in the Gram form X and Y are the bf16 frames, reached through w.X / w.Y
+    const T* __restrict__ Xs = (CM == kCostGram) ? static_cast<const T*>(w.X) : X;
+    const T* __restrict__ Ys = (CM == kCostGram) ? static_cast<const T*>(w.Y) : Y;
+    const T* __restrict__ RowSrc = S.tr ? Ys : Xs;
+    const T* __restrict__ ColSrc = S.tr ? Xs : Ys;
+    const float* __restrict__ RowN = S.tr ? w.Yn : w.Xn;
+    const float* __restrict__ ColN = S.tr ? w.Xn : w.Yn;
     const int64_t bpw = (int64_t)((S.R + kWave - 1) / kWave) * S.Wm * kWave;
     const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
     const int64_t slot_end = pd.pbase + e;  // the block's last cell sits on diagonal e
@@ -643,11 +709,13 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     int cnt_written = 0;
     if (Lf.scratch_off < 0) {
       uint32_t* bp = reinterpret_cast<uint32_t*>(lds_raw);
-      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, hist, wave, lane);
+      fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
+                                  hist, wave, lane);
       if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
     } else {
       uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
-      fend = leaf_sweep<T, D>(RowSrc, ColSrc, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring, hist, wave, lane);
+      fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
+                                  hist, wave, lane);
       if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
     }
 
@@ -711,66 +779,91 @@ int pick_dmax(int d) {
     default: return hipErrorInvalidValue;            \
   }
 
-hipError_t launch_pass(const Work& w, int level, bool f32, int grid, hipStream_t st) {
-  const int dm = pick_dmax(w.d);
-  if (f32) {
-    DTW_DISPATCH_DMAX(dm, (pass_kernel<float, D_><<<grid, kPassThreads, 0, st>>>(
-                              static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w, level)))
+// Padded frame width of the Gram form's bf16 copies (multiples of 16 for
+// the matrix-core K blocks).
+int pick_dgram(int d) {
+  if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  if (d <= 128) return 128;
+  return 0;
+}
+
+#define DTW_DISPATCH_DGRAM(DM, CALL)                   \
+  switch (DM) {                                        \
+    case 32: { constexpr int D_ = 32; CALL; } break;   \
+    case 64: { constexpr int D_ = 64; CALL; } break;   \
+    case 128: { constexpr int D_ = 128; CALL; } break; \
+    default: return hipErrorInvalidValue;              \
+  }
+
+// Sweep launch for the precision of `w`: FP64 or FP32 Euclidean costs on the
+// VALU, or BF16 Gram costs on the matrix cores with the FP32 recurrence.
+hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
+  if (w.precision == DTW_PREC_BF16_COST) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGram><<<grid, kPassThreads, 0, st>>>(
+                                            nullptr, nullptr, w, level)))
+  } else if (w.precision == DTW_PREC_FP32) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), (pass_kernel<float, D_, kCostEuclid><<<grid, kPassThreads, 0, st>>>(
+                                          static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w, level)))
   } else {
-    DTW_DISPATCH_DMAX(dm, (pass_kernel<double, D_><<<grid, kPassThreads, 0, st>>>(
-                              static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w, level)))
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), (pass_kernel<double, D_, kCostEuclid><<<grid, kPassThreads, 0, st>>>(
+                                          static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w, level)))
   }
   return hipGetLastError();
 }
 
-hipError_t launch_leaf(const Work& w, bool f32, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
-                       int in_f64, hipStream_t st) {
-  const int dm = pick_dmax(w.d);
+hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
+                       hipStream_t st) {
   const size_t dyn = (size_t)lds_leaf_bytes;
-  if (f32) {
-    DTW_DISPATCH_DMAX(dm, (leaf_kernel<float, D_><<<grid, kPassThreads, dyn, st>>>(
-                              static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w, lds_leaf_bytes,
-                              Xo, Yo, in_f64, w.d)))
+  if (w.precision == DTW_PREC_BF16_COST) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (leaf_kernel<float, D_, kCostGram><<<grid, kPassThreads, dyn, st>>>(
+                                            nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
+  } else if (w.precision == DTW_PREC_FP32) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), (leaf_kernel<float, D_, kCostEuclid><<<grid, kPassThreads, dyn, st>>>(
+                                          static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w,
+                                          lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
   } else {
-    DTW_DISPATCH_DMAX(dm, (leaf_kernel<double, D_><<<grid, kPassThreads, dyn, st>>>(
-                              static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w, lds_leaf_bytes,
-                              Xo, Yo, in_f64, w.d)))
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), (leaf_kernel<double, D_, kCostEuclid><<<grid, kPassThreads, dyn, st>>>(
+                                          static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w,
+                                          lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
   }
   return hipGetLastError();
 }
 
 // Dynamic LDS left to the leaf kernels (pointers and bottom row) once their
-// static LDS is taken from `lds_max`, per compute type: the smallest over the
-// frame widths, also set as each kernel's dynamic LDS limit.
+// static LDS is taken from `lds_max`, per compute type (FP64; FP32 and the
+// Gram form): the smallest over the frame widths, also set as each kernel's
+// dynamic LDS limit.
 hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32) {
   int64_t lim[2] = {lds_max, lds_max};
-#define DTW_LEAF_STATIC(T_, D_, I_)                                                               \
-  {                                                                                               \
-    hipFuncAttributes a;                                                                          \
-    hipError_t r = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&leaf_kernel<T_, D_>)); \
-    if (r != hipSuccess) return r;                                                                \
-    const int64_t left = lds_max - (int64_t)a.sharedSizeBytes - 64;                               \
-    if (left < lim[I_]) lim[I_] = left;                                                           \
+#define DTW_LEAF_STATIC(T_, D_, CM_, I_)                                                                \
+  {                                                                                                     \
+    hipFuncAttributes a;                                                                                \
+    hipError_t r = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&leaf_kernel<T_, D_, CM_>)); \
+    if (r != hipSuccess) return r;                                                                      \
+    const int64_t left = lds_max - (int64_t)a.sharedSizeBytes - 64;                                     \
+    if (left < lim[I_]) lim[I_] = left;                                                                 \
   }
-  DTW_LEAF_STATIC(double, 4, 0) DTW_LEAF_STATIC(double, 8, 0) DTW_LEAF_STATIC(double, 12, 0)
-  DTW_LEAF_STATIC(double, 16, 0) DTW_LEAF_STATIC(double, 24, 0) DTW_LEAF_STATIC(double, 32, 0)
-  DTW_LEAF_STATIC(float, 4, 1) DTW_LEAF_STATIC(float, 8, 1) DTW_LEAF_STATIC(float, 12, 1)
-  DTW_LEAF_STATIC(float, 16, 1) DTW_LEAF_STATIC(float, 24, 1) DTW_LEAF_STATIC(float, 32, 1)
+#define DTW_LEAF_ALL(M_)                                                                                  \
+  M_(double, 4, kCostEuclid, 0) M_(double, 8, kCostEuclid, 0) M_(double, 12, kCostEuclid, 0)              \
+  M_(double, 16, kCostEuclid, 0) M_(double, 24, kCostEuclid, 0) M_(double, 32, kCostEuclid, 0)            \
+  M_(float, 4, kCostEuclid, 1) M_(float, 8, kCostEuclid, 1) M_(float, 12, kCostEuclid, 1)                 \
+  M_(float, 16, kCostEuclid, 1) M_(float, 24, kCostEuclid, 1) M_(float, 32, kCostEuclid, 1)               \
+  M_(float, 32, kCostGram, 1) M_(float, 64, kCostGram, 1) M_(float, 128, kCostGram, 1)
+  DTW_LEAF_ALL(DTW_LEAF_STATIC)
 #undef DTW_LEAF_STATIC
   lim[0] &= ~(int64_t)255;
   lim[1] &= ~(int64_t)255;
   if (lim[0] < 0 || lim[1] < 0) return hipErrorInvalidValue;
-#define DTW_SET_ATTR(T_, D_, I_)                                                                  \
-  {                                                                                               \
-    hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel<T_, D_>),       \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim[I_]); \
-    if (r != hipSuccess) return r;                                                                \
+#define DTW_SET_ATTR(T_, D_, CM_, I_)                                                                     \
+  {                                                                                                     \
+    hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel<T_, D_, CM_>),        \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim[I_]);       \
+    if (r != hipSuccess) return r;                                                                      \
   }
-  DTW_SET_ATTR(double, 4, 0) DTW_SET_ATTR(double, 8, 0) DTW_SET_ATTR(double, 12, 0)
-  DTW_SET_ATTR(double, 16, 0) DTW_SET_ATTR(double, 24, 0) DTW_SET_ATTR(double, 32, 0)
-  DTW_SET_ATTR(float, 4, 1) DTW_SET_ATTR(float, 8, 1) DTW_SET_ATTR(float, 12, 1)
-  DTW_SET_ATTR(float, 16, 1) DTW_SET_ATTR(float, 24, 1) DTW_SET_ATTR(float, 32, 1)
+  DTW_LEAF_ALL(DTW_SET_ATTR)
 #undef DTW_SET_ATTR
+#undef DTW_LEAF_ALL
   *dyn_f64 = lim[0];
   *dyn_f32 = lim[1];
   return hipSuccess;

@@ -8,6 +8,9 @@
 // write; they also check the stripe queue and every buffer index they use.
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <cmath>
+#include <limits>
 #include <vector>
 
 #include "hip/hip_runtime.h"
@@ -16,12 +19,16 @@ thread_local dim3_cpu threadIdx, blockIdx, blockDim, gridDim;
 thread_local std::barrier<>* cpu_block_barrier = nullptr;
 thread_local std::barrier<>* cpu_wave_barrier = nullptr;
 
-#include "dtw_plan_kernels.inc"
-#ifdef MODEL_WAVE
 #include "wave_shim.h"
 uint64_t cpu_wave_slots[16][64];
 alignas(16) unsigned char cpu_dynamic_lds[163840];
+#include "dtw_plan_kernels.inc"
+#ifdef MODEL_WAVE
 #include "dtw_wave_kernels.inc"
+namespace dtw {
+uint16_t cpu_mfma_a[16][64][8];
+uint16_t cpu_mfma_b[16][64][8];
+}  // namespace dtw
 #endif
 
 #define MODEL_CHECK(cond)                                                      \
@@ -42,6 +49,43 @@ int pick_dmax(int d) {
   if (d <= 24) return 24;
   if (d <= 32) return 32;
   return 0;
+}
+
+template <typename T>
+static T model_cost(const T* x, const T* y, int D);
+
+int pick_dgram(int d) {
+  if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  if (d <= 128) return 128;
+  return 0;
+}
+
+static float model_bf16(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Gram-form cost from the staged bf16 frames and FP32 norms (k-order FP32 sum).
+static float model_gram_cost(const uint16_t* x, const uint16_t* y, float nx, float ny, int D) {
+  float dot = 0.0f;
+  for (int k = 0; k < D; ++k) dot += model_bf16(x[k]) * model_bf16(y[k]);
+  const float v = std::fmax(std::fma(-2.0f, dot, nx + ny), 0.0f);
+  return std::sqrt(v);
+}
+
+// The frame cost of (gi, gj) in the form the Work asks for.
+template <typename T>
+static T model_frame_cost(const Work& w, int64_t gi, int64_t gj) {
+  if (w.precision == DTW_PREC_BF16_COST) {
+    const int D = pick_dgram(w.d);
+    return (T)model_gram_cost(static_cast<const uint16_t*>(w.X) + gi * D, static_cast<const uint16_t*>(w.Y) + gj * D,
+                              w.Xn[gi], w.Yn[gj], D);
+  }
+  const int D = pick_dmax(w.d);
+  return model_cost(static_cast<const T*>(w.X) + gi * D, static_cast<const T*>(w.Y) + gj * D, D);
 }
 
 template <typename T>
@@ -106,9 +150,6 @@ static void model_pass(const Work& w) {
   }
   for (int p = 0; p < n_pass; ++p)
     for (int c : seen[p]) MODEL_CHECK(c == 1);
-  const int D = pick_dmax(w.d);
-  const T* X = static_cast<const T*>(w.X);
-  const T* Y = static_cast<const T*>(w.Y);
   const T INF = std::numeric_limits<T>::infinity();
   for (int p = 0; p < n_pass; ++p) {
     const PassDesc P = w.passes[p];
@@ -122,7 +163,7 @@ static void model_pass(const Work& w) {
       for (int b = 0; b <= bmax; ++b) {
         const int64_t gi = P.dir ? P.i1 - a : P.i0 + a;
         const int64_t gj = P.dir ? P.j1 - b : P.j0 + b;
-        const T c = model_cost(X + gi * D, Y + gj * D, D);
+        const T c = model_frame_cost<T>(w, gi, gj);
         T f;
         if (a == 0 && b == 0) f = c;
         else {
@@ -161,10 +202,7 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
   Ctl* ctl = w.ctl;
   const int n_leaf = ctl->n_leaf;
   MODEL_CHECK(n_leaf >= 0 && n_leaf <= w.caps.leaf);
-  const int D = pick_dmax(w.d);
   const int d = w.d;
-  const T* X = static_cast<const T*>(w.X);
-  const T* Y = static_cast<const T*>(w.Y);
   const T INF = std::numeric_limits<T>::infinity();
   for (int l = 0; l < n_leaf; ++l) {
     const LeafDesc Lf = w.leaves[l];
@@ -176,14 +214,14 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
     MODEL_CHECK(std::min(Mb, Nb) < w.min_block);
     if (Lf.scratch_off >= 0) {
       const int64_t R = std::min(Mb, Nb), Cc = std::max(Mb, Nb);
-      const int64_t need = (((R * ((Cc + 15) / 16)) + 1) & ~(int64_t)1) + 2 * Cc;
+      const int64_t need = ((R + 63) / 64) * ((Cc + 63 + 15) / 16) * 64 + 2 * Cc;
       MODEL_CHECK(Lf.scratch_off + need <= w.caps.leaf_words);
     }
     std::vector<T> F((size_t)Mb * Nb);
     std::vector<unsigned char> P((size_t)Mb * Nb);
     for (int i = 0; i < Mb; ++i)
       for (int j = 0; j < Nb; ++j) {
-        const T c = model_cost(X + (int64_t)(Lf.i0 + i) * D, Y + (int64_t)(Lf.j0 + j) * D, D);
+        const T c = model_frame_cost<T>(w, Lf.i0 + i, Lf.j0 + j);
         T f;
         unsigned char mv = 0;
         if (i == 0 && j == 0) f = c;
@@ -248,36 +286,44 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
     case 32: { constexpr int D_ = 32; CALL; } break;               \
     default: std::abort();                                          \
   }
-hipError_t launch_pass(const Work& w, int level, bool f32, int, hipStream_t) {
+#define MODEL_DISPATCH_GRAM(D_VAR, CALL)                            \
+  switch (D_VAR) {                                                  \
+    case 32: { constexpr int D_ = 32; CALL; } break;               \
+    case 64: { constexpr int D_ = 64; CALL; } break;               \
+    case 128: { constexpr int D_ = 128; CALL; } break;             \
+    default: std::abort();                                          \
+  }
+hipError_t launch_pass(const Work& w, int level, int, hipStream_t) {
   model_check_queue(w);
-  const int D = pick_dmax(w.d);
-  if (f32) {
-    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, level); })))
+  if (w.precision == DTW_PREC_BF16_COST) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
+  } else if (w.precision == DTW_PREC_FP32) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, level); })))
   } else {
-    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { pass_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, level); })))
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, level); })))
   }
   return hipSuccess;
 }
-hipError_t launch_leaf(const Work& w, bool f32, int, int64_t lds_leaf_bytes, const void* Xo, const void* Yo,
-                       int in_f64, hipStream_t) {
+hipError_t launch_leaf(const Work& w, int, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
+                       hipStream_t) {
   model_check_leaves(w);
-  const int D = pick_dmax(w.d);
-  if (f32) {
-    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  if (w.precision == DTW_PREC_BF16_COST) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostGram>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  } else if (w.precision == DTW_PREC_FP32) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else {
-    MODEL_DISPATCH(D, (cpu_launch(2, kPassThreads, [&] { leaf_kernel<double, D_>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   }
   return hipSuccess;
 }
 #else
-hipError_t launch_pass(const Work& w, int, bool f32, int, hipStream_t) {
-  if (f32) model_pass<float>(w);
+hipError_t launch_pass(const Work& w, int, int, hipStream_t) {
+  if (w.precision != DTW_PREC_FP64) model_pass<float>(w);
   else model_pass<double>(w);
   return hipSuccess;
 }
-hipError_t launch_leaf(const Work& w, bool f32, int, int64_t, const void* Xo, const void* Yo, int in_f64,
-                       hipStream_t) {
-  if (f32) model_leaf<float>(w, Xo, Yo, in_f64);
+hipError_t launch_leaf(const Work& w, int, int64_t, const void* Xo, const void* Yo, int in_f64, hipStream_t) {
+  if (w.precision != DTW_PREC_FP64) model_leaf<float>(w, Xo, Yo, in_f64);
   else model_leaf<double>(w, Xo, Yo, in_f64);
   return hipSuccess;
 }
@@ -323,12 +369,18 @@ hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64
     cpu_launch(2, 64, [&] { pad_convert_kernel<float, float>((const float*)in, (float*)out, rows, d, D); });
   return hipSuccess;
 }
+hipError_t launch_bf16_stage(const void* in, int in_f64, int64_t rows, int d, int D, uint16_t* out, float* norms,
+                             hipStream_t) {
+  if (in_f64) cpu_launch(2, 256, [&] { bf16_stage_kernel<double>((const double*)in, rows, d, D, out, norms); });
+  else cpu_launch(2, 256, [&] { bf16_stage_kernel<float>((const float*)in, rows, d, D, out, norms); });
+  return hipSuccess;
+}
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t) {
   if (in_f64) cpu_launch(2, 64, [&] { nonfinite_kernel<double>((const double*)in, n, flag); });
   else cpu_launch(2, 64, [&] { nonfinite_kernel<float>((const float*)in, n, flag); });
   return hipSuccess;
 }
-hipError_t launch_diag(const Work&, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, bool, int, double*,
+hipError_t launch_diag(const Work&, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int, double*,
                        hipStream_t) {
   return hipErrorInvalidValue;  // the sweep itself is a wave kernel: GPU tests cover it
 }

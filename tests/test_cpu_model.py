@@ -156,3 +156,40 @@ def test_wave_model_matches_oracle(wave_exe, M, N, d, m):
     c_ref, p_ref = oracle.full(X, Y)
     assert path.tolist() == p_ref.tolist()
     assert abs(cost - c_ref) <= 1e-12 * c_ref
+
+
+# ------------------------------------------------------------ BF16 Gram form
+
+BF16_REL_TOL = 1e-2
+
+
+def _gram_case(M, N, d, seed):
+    X, Y = synth.make_pair(3, seed, M, N, d, "embedding")
+    return X, Y
+
+
+@pytest.mark.parametrize("M,N,d,m", [(150, 120, 64, 16), (90, 140, 128, 500), (70, 70, 20, 3)])
+def test_model_gram_form(model_exe, M, N, d, m):
+    # orchestration with the Gram-form costs: a valid path whose FP64 cost is
+    # within the BF16 tolerance of the oracle's optimum
+    X, Y = _gram_case(M, N, d, M + N)
+    r = run_model(model_exe, [(X, Y)], m, precision=2)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    cost, path = r["results"][0]
+    c_ref, _ = oracle.full(X, Y)
+    assert abs(cost - oracle.path_cost(X, Y, path)) <= 1e-12 * c_ref
+    assert -1e-12 <= (cost - c_ref) / c_ref <= BF16_REL_TOL
+
+
+@pytest.mark.parametrize("M,N,d,m", [(90, 70, 64, 16), (100, 60, 128, 500)])
+def test_wave_model_gram_form(model_exe, wave_exe, M, N, d, m):
+    # the real kernels with the matrix-core operation emulated in the device's
+    # lane layout: same path as the plain model (both sum the bf16 products
+    # in k order in FP32)
+    X, Y = _gram_case(M, N, d, 7 * M + N)
+    r_wave = run_model(wave_exe, [(X, Y)], m, precision=2)
+    r_plain = run_model(model_exe, [(X, Y)], m, precision=2)
+    assert r_wave["rc"] == 0 and r_wave["device_error"] == 0, r_wave
+    assert r_wave["results"][0][1].tolist() == r_plain["results"][0][1].tolist()
+    # the FP64 path cost: compensated per-leaf sums on the device, a plain sum in the model
+    assert abs(r_wave["results"][0][0] - r_plain["results"][0][0]) <= 1e-12 * r_plain["results"][0][0]

@@ -91,3 +91,91 @@ def test_fp32_batched_equals_single(dtw):
         c1, p1, _ = dtw.align(Xs[b], Ys[b], precision="fp32", min_block=500)
         assert costs[b].item() == c1
         assert torch.equal(paths[b], p1)
+
+
+# ------------------------------------------------------------------ BF16 Gram form
+#
+# Frame costs sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) from frames rounded to bf16
+# (dot products on the matrix cores, FP32 accumulation), recurrence in FP32,
+# band sums and argmin in FP64; gate: relative cost error <= 1e-2.
+
+BF16_REL_TOL = 1e-2
+
+
+def bf16_round(a):
+    """Round to bf16 (nearest even) through FP32, as the input staging does."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_case(dtw, X, Y, m):
+    M, N = X.shape[0], Y.shape[0]
+    cost, path, st = dtw.align(dev(X), dev(Y), precision="bf16", min_block=m)
+    assert st["device_error"] == 0
+    p = path.cpu().numpy()
+    check_path(p, M, N)
+    c_ref, p_ref = oracle.full(X, Y)
+    assert abs(cost - oracle.path_cost(X, Y, p)) <= 1e-12 * c_ref
+    rel = (cost - c_ref) / c_ref
+    assert -1e-12 <= rel <= BF16_REL_TOL, rel
+    dv = metrics.summary(p, p_ref)
+    print(f"bf16 M={M} N={N} d={X.shape[1]} m={m}: rel cost err {rel:.2e}, internal cost err "
+          f"{abs(st['cost_lowp'] - c_ref) / c_ref:.2e}, frame deviation mean {dv['mean_frames']:.3f} "
+          f"max {dv['max_frames']} within 1 frame {dv['frac_le_1']:.4f}")
+    return rel, dv, st
+
+
+@pytest.mark.parametrize("M,N", [(3000, 2500), (6000, 4800)])
+def test_bf16_embedding_d128(dtw, M, N):
+    X, Y = synth.make_pair(3, M, M, N, 128, "embedding")
+    bf16_case(dtw, X, Y, 500)
+
+
+@pytest.mark.parametrize("d,m", [(20, 16), (64, 500), (100, 64)])
+def test_bf16_other_widths(dtw, d, m):
+    X, Y = synth.make_pair(3, 1000 + d, 700, 560, d, "embedding")
+    bf16_case(dtw, X, Y, m)
+
+
+def test_bf16_sweep_band_against_gram_reference(dtw):
+    # one sweep (Algorithm 1) in the Gram form against an FP64 DP on the Gram
+    # costs of the bf16-rounded frames: only FP32 dot/recurrence rounding differs
+    M, N, d = 300, 260, 128
+    X, Y = synth.make_pair(3, 77, M, N, d, "embedding")
+    Xr, Yr = bf16_round(X), bf16_round(Y)
+    nx = (Xr * Xr).sum(1)
+    ny = (Yr * Yr).sum(1)
+    C = np.sqrt(np.maximum(nx[:, None] + ny[None, :] - 2.0 * Xr @ Yr.T, 0.0))
+    F = np.full((M, N), np.inf)
+    F[0, 0] = C[0, 0]
+    for i in range(M):
+        for j in range(N):
+            if i == 0 and j == 0:
+                continue
+            best = min(F[i - 1, j - 1] if i and j else np.inf, F[i - 1, j] if i else np.inf,
+                       F[i, j - 1] if j else np.inf)
+            F[i, j] = best + C[i, j]
+    K = M + N - 1
+    kstop = (K + 1) // 2
+    got = dtw.diag(dev(X), dev(Y), 0, 0, M - 1, N - 1, 0, kstop, precision="bf16").cpu().numpy()
+    for q in range(3):
+        k = kstop - 2 + q
+        for a in range(max(0, k - N + 1), min(M - 1, k) + 1):
+            ref = F[a, k - a]
+            assert abs(got[q, a] - ref) <= 2e-5 * ref, (q, a, got[q, a], ref)
+
+
+def test_bf16_batched_equals_single(dtw):
+    shapes = [(800, 700), (1500, 1300), (300, 420)]
+    Xs, Ys = [], []
+    for p, (M, N) in enumerate(shapes):
+        X, Y = synth.make_pair(3, 200 + p, M, N, 128, "embedding")
+        Xs.append(dev(X.astype(np.float32), torch.float32))
+        Ys.append(dev(Y.astype(np.float32), torch.float32))
+    costs, paths, st = dtw.align_batched(Xs, Ys, precision="bf16", min_block=500)
+    assert st["device_error"] == 0
+    for b in range(len(shapes)):
+        c1, p1, _ = dtw.align(Xs[b], Ys[b], precision="bf16", min_block=500)
+        assert costs[b].item() == c1
+        assert torch.equal(paths[b], p1)
