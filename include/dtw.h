@@ -173,6 +173,77 @@ dtw_status dtw_align_batched(int32_t B, const void* X_packed, const int64_t* x_o
                              const int64_t* path_offsets, int64_t* path_lens_out,
                              dtw_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving form (continuous batching; the paper has no serving layer).
+ *
+ * A server owns one device memory pool, allocated once by dtw_server_create;
+ * no other call of the server allocates device memory.  Requests queue in
+ * submission order.  A scheduler thread admits requests from the head of the
+ * queue into a batch as long as the batch's whole footprint (workspace,
+ * packed inputs, packed outputs) fits in free pool memory, the batch holds at
+ * most max_batch requests and all of them share precision, d, input type and
+ * min_block (the head of the queue first, then later requests of its class
+ * in submission order); it then runs the batch as dtw_align_batched would (one launch per
+ * recursion level for all of its pairs, the recursion state on the device) on
+ * a stream of its own.  Up to max_slots batches are in flight at once, so
+ * requests that arrive while others run are admitted as slots and memory free
+ * up, and their work overlaps on the device.  Each result is identical to a
+ * dtw_align call on the same request.
+ *
+ * Ownership: the caller owns every request's inputs and outputs (device
+ * pointers) and keeps them valid until the request has finished (poll or
+ * wait returned DTW_OK for it).  Errors: DTW_ERR_INVALID_ARG for a bad
+ * argument, DTW_ERR_WORKSPACE when a request alone cannot fit in the pool,
+ * DTW_ERR_UNSUPPORTED for a d the precision does not support,
+ * DTW_ERR_NOT_FOUND for an unknown or already collected ticket, DTW_ERR_BUSY
+ * from dtw_server_poll while the request is queued or running.  A result
+ * whose device-side consistency check failed has status DTW_ERR_INTERNAL. */
+typedef struct dtw_server dtw_server;
+
+typedef struct dtw_server_opts {
+  size_t pool_bytes;  /* device memory pool, default 8 GiB                      */
+  int32_t max_slots;  /* batches in flight at once, 1..16, default 4            */
+  int32_t max_batch;  /* requests per batch, >= 1, default 64                   */
+  int32_t device;     /* HIP device ordinal, default 0                          */
+  int32_t reserved[5];
+} dtw_server_opts;
+
+typedef struct dtw_request {
+  const void* X;          /* device, M x d                                      */
+  int64_t M;
+  const void* Y;          /* device, N x d                                      */
+  int64_t N;
+  int32_t d;
+  int32_t in_dtype;       /* dtw_dtype                                          */
+  dtw_opts opts;          /* precision and min_block as for dtw_align           */
+  double* cost_out;       /* device, 1 double                                   */
+  int32_t* path_out;      /* device, 2 * path_cap int32                         */
+  int64_t path_cap;       /* >= M + N - 1                                       */
+  int64_t* path_len_out;  /* device, 1 int64                                    */
+} dtw_request;
+
+typedef struct dtw_result {
+  int32_t status;         /* DTW_OK, or the error of the request's batch        */
+  int32_t device_error;   /* device-side consistency code of the batch, 0 ok   */
+  int32_t batch_size;     /* requests in the batch this request ran in          */
+  int32_t reserved;
+  int64_t t_submit_ns;    /* host steady-clock times: submission, admission     */
+  int64_t t_admit_ns;     /* into a batch, and completion observed by the       */
+  int64_t t_done_ns;      /* scheduler                                          */
+} dtw_result;
+
+void dtw_server_default_opts(dtw_server_opts* opts);
+dtw_status dtw_server_create(const dtw_server_opts* opts, dtw_server** server);
+/* Queue one request; returns at once with a ticket. */
+dtw_status dtw_server_submit(dtw_server* server, const dtw_request* request, uint64_t* ticket);
+/* DTW_ERR_BUSY while the request is queued or running; once it has finished,
+ * fills `result`, releases the ticket and returns DTW_OK. */
+dtw_status dtw_server_poll(dtw_server* server, uint64_t ticket, dtw_result* result);
+/* As dtw_server_poll, but blocks until the request has finished. */
+dtw_status dtw_server_wait(dtw_server* server, uint64_t ticket, dtw_result* result);
+/* Waits for every submitted request, then releases the pool and the streams. */
+dtw_status dtw_server_destroy(dtw_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -339,7 +339,7 @@ hipError_t stage_inputs(const Layout& L, void* ws, const void* X, const void* Y,
 dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, const int64_t* yo, int d,
                int in_dtype, const dtw_opts* opts_in, void* ws, size_t ws_bytes, double* costs,
                int32_t* paths, const int64_t* path_offsets, int64_t path_cap_single, int64_t* lens,
-               dtw_stats* stats, hipStream_t st) {
+               dtw_stats* stats, hipStream_t st, int32_t** device_error_word = nullptr) {
   dtw_opts opts;
   dtw_status rc = read_opts(opts_in, &opts);
   if (rc != DTW_OK) return rc;
@@ -393,6 +393,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   Profiler prof;
   HIP_TRY(prof.init(opts.profile != 0 && stats != nullptr, st));
   Work w = make_work(L, ws, d, m, opts.precision);
+  if (device_error_word) *device_error_word = &w.ctl->error;
   w.X = X;
   w.Y = Y;
   // one boundary wait may last at most DTW_SPIN_LIMIT_MS (default 20 s)
@@ -449,6 +450,28 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
 }
 
 }  // namespace
+
+namespace dtw {
+// Entry points of the serving loop (dtw_server.hip): workspace of a batch,
+// and the batch enqueued on a stream without any host synchronisation; the
+// device error word of the batch is returned for a later asynchronous read.
+dtw_status batch_workspace(int32_t B, const int64_t* x_offsets, const int64_t* y_offsets, int32_t d,
+                           int32_t in_dtype, const dtw_opts* opts, size_t* bytes) {
+  return dtw_workspace_size_batched(B, x_offsets, y_offsets, d, in_dtype, opts, bytes);
+}
+dtw_status enqueue_batch(int32_t B, const void* X, const int64_t* xo, const void* Y, const int64_t* yo, int32_t d,
+                         int32_t in_dtype, const dtw_opts* opts, void* ws, size_t ws_bytes, double* costs,
+                         int32_t* paths, const int64_t* path_offsets, int64_t* lens, hipStream_t st,
+                         int32_t** device_error_word) {
+  dtw_opts o;
+  dtw_status rc = read_opts(opts, &o);
+  if (rc != DTW_OK) return rc;
+  o.validate_finite = 0;  // the serving loop never synchronises
+  o.profile = 0;
+  return run(B, X, Y, xo, yo, d, in_dtype, &o, ws, ws_bytes, costs, paths, path_offsets, 0, lens, nullptr, st,
+             device_error_word);
+}
+}  // namespace dtw
 
 extern "C" {
 

@@ -222,3 +222,113 @@ def diag(X, Y, i0, j0, i1, j1, reverse, kstop, precision="fp64", stream=None):
                         _stream_ptr(stream))
     _check(rc, "dtw_diag")
     return out
+
+
+# ------------------------------------------------------------------ serving form
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("M", ctypes.c_int64), ("Y", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("d", ctypes.c_int32), ("in_dtype", ctypes.c_int32), ("opts", Opts),
+                ("cost_out", ctypes.c_void_p), ("path_out", ctypes.c_void_p), ("path_cap", ctypes.c_int64),
+                ("path_len_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("device_error", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_bound", False):
+        vp = ctypes.c_void_p
+        L.dtw_server_default_opts.argtypes = [ctypes.POINTER(ServerOpts)]
+        L.dtw_server_default_opts.restype = None
+        L.dtw_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        L.dtw_server_create.restype = ctypes.c_int32
+        L.dtw_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.dtw_server_submit.restype = ctypes.c_int32
+        for name in ("dtw_server_poll", "dtw_server_wait"):
+            f = getattr(L, name)
+            f.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+            f.restype = ctypes.c_int32
+        L.dtw_server_destroy.argtypes = [vp]
+        L.dtw_server_destroy.restype = ctypes.c_int32
+        L._server_bound = True
+    return L
+
+
+class Server:
+    """Continuous-batching request loop of the library (dtw_server_* in
+    include/dtw.h).  Inputs must be fully written before submit; outputs are
+    device tensors owned here until the result is collected."""
+
+    BUSY = -6
+
+    def __init__(self, pool_bytes=8 << 30, max_slots=4, max_batch=64, device=0):
+        L = _server_lib()
+        o = ServerOpts()
+        L.dtw_server_default_opts(ctypes.byref(o))
+        o.pool_bytes, o.max_slots, o.max_batch, o.device = int(pool_bytes), int(max_slots), int(max_batch), int(device)
+        h = ctypes.c_void_p()
+        _check(L.dtw_server_create(ctypes.byref(o), ctypes.byref(h)), "dtw_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, X, Y, precision="fp64", min_block=500):
+        if X.dtype != Y.dtype or X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+            raise ValueError("X and Y must be 2-D with equal dtype and feature dimension")
+        torch.cuda.current_stream(X.device).synchronize()  # inputs written before the server's stream reads them
+        M, d = X.shape
+        N = Y.shape[0]
+        cost = torch.empty(1, dtype=torch.float64, device=X.device)
+        path = torch.empty((M + N - 1, 2), dtype=torch.int32, device=X.device)
+        plen = torch.empty(1, dtype=torch.int64, device=X.device)
+        r = Request(_dev(X).value, M, _dev(Y).value, N, d, _dtype_code(X), make_opts(precision, min_block),
+                    cost.data_ptr(), path.data_ptr(), M + N - 1, plen.data_ptr())
+        tk = ctypes.c_uint64()
+        _check(_server_lib().dtw_server_submit(self._h, ctypes.byref(r), ctypes.byref(tk)), "dtw_server_submit")
+        self._live[tk.value] = (X, Y, cost, path, plen)
+        return tk.value
+
+    def _collect(self, ticket, block):
+        res = Result()
+        f = _server_lib().dtw_server_wait if block else _server_lib().dtw_server_poll
+        rc = f(self._h, ticket, ctypes.byref(res))
+        if rc == self.BUSY:
+            return None
+        _check(rc, "dtw_server_poll")
+        X, Y, cost, path, plen = self._live.pop(ticket)
+        out = res.to_dict()
+        if res.status == 0:
+            n = int(plen.item())
+            out.update(cost=float(cost.item()), path=path[:n])
+        return out
+
+    def poll(self, ticket):
+        """None while the request is queued or running, else its result dict."""
+        return self._collect(ticket, False)
+
+    def wait(self, ticket):
+        return self._collect(ticket, True)
+
+    def close(self):
+        if self._h:
+            _check(_server_lib().dtw_server_destroy(self._h), "dtw_server_destroy")
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
