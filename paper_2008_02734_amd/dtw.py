@@ -171,39 +171,57 @@ def align(X, Y, precision="fp64", min_block=500, validate_finite=False, stream=N
     return float(al.cost.item()), al.path[:n], st
 
 
+class BatchAligner:
+    """Reusable packed inputs and buffers for repeated batched alignments of
+    one fixed set of pairs (dtw_align_batched)."""
+
+    def __init__(self, Xs, Ys, precision="fp64", min_block=500, profile=False):
+        self.B = len(Xs)
+        dev = Xs[0].device
+        self.d = Xs[0].shape[1]
+        xo, yo, po = [0], [0], [0]
+        for X, Y in zip(Xs, Ys):
+            xo.append(xo[-1] + X.shape[0])
+            yo.append(yo[-1] + Y.shape[0])
+            po.append(po[-1] + X.shape[0] + Y.shape[0] - 1)
+        self.po = po
+        self.Xp = torch.cat(list(Xs)).contiguous()
+        self.Yp = torch.cat(list(Ys)).contiguous()
+        arr = lambda v: (ctypes.c_int64 * len(v))(*v)
+        self.xo_a, self.yo_a, self.po_a = arr(xo), arr(yo), arr(po)
+        self.opts = make_opts(precision, min_block, profile=profile)
+        n = ctypes.c_size_t()
+        _check(lib().dtw_workspace_size_batched(self.B, self.xo_a, self.yo_a, self.d, _dtype_code(self.Xp),
+                                                ctypes.byref(self.opts), ctypes.byref(n)),
+               "dtw_workspace_size_batched")
+        self.ws_bytes = n.value
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        self.costs = torch.empty(self.B, dtype=torch.float64, device=dev)
+        self.paths = torch.empty((po[-1], 2), dtype=torch.int32, device=dev)
+        self.lens = torch.empty(self.B, dtype=torch.int64, device=dev)
+
+    def run(self, stream=None):
+        st = Stats()
+        rc = lib().dtw_align_batched(self.B, _dev(self.Xp), self.xo_a, _dev(self.Yp), self.yo_a, self.d,
+                                     _dtype_code(self.Xp), ctypes.byref(self.opts),
+                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                     ctypes.c_void_p(self.costs.data_ptr()), ctypes.c_void_p(self.paths.data_ptr()),
+                                     self.po_a, ctypes.c_void_p(self.lens.data_ptr()), ctypes.byref(st),
+                                     _stream_ptr(stream))
+        _check(rc, "dtw_align_batched")
+        return st.to_dict()
+
+    def path_list(self):
+        lens_h = self.lens.tolist()
+        return [self.paths[self.po[b]:self.po[b] + lens_h[b]] for b in range(self.B)]
+
+
 def align_batched(Xs, Ys, precision="fp64", min_block=500, stream=None):
     """Align B independent pairs in one call.  Returns (costs [B] float64 tensor,
     list of path tensors, stats dict)."""
-    B = len(Xs)
-    dev = Xs[0].device
-    d = Xs[0].shape[1]
-    xo = [0]
-    yo = [0]
-    po = [0]
-    for X, Y in zip(Xs, Ys):
-        xo.append(xo[-1] + X.shape[0])
-        yo.append(yo[-1] + Y.shape[0])
-        po.append(po[-1] + X.shape[0] + Y.shape[0] - 1)
-    Xp = torch.cat(list(Xs)).contiguous()
-    Yp = torch.cat(list(Ys)).contiguous()
-    arr = lambda v: (ctypes.c_int64 * len(v))(*v)
-    xo_a, yo_a, po_a = arr(xo), arr(yo), arr(po)
-    o = make_opts(precision, min_block)
-    n = ctypes.c_size_t()
-    _check(lib().dtw_workspace_size_batched(B, xo_a, yo_a, d, _dtype_code(Xp), ctypes.byref(o), ctypes.byref(n)),
-           "dtw_workspace_size_batched")
-    ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
-    costs = torch.empty(B, dtype=torch.float64, device=dev)
-    paths = torch.empty((po[-1], 2), dtype=torch.int32, device=dev)
-    lens = torch.empty(B, dtype=torch.int64, device=dev)
-    st = Stats()
-    rc = lib().dtw_align_batched(B, _dev(Xp), xo_a, _dev(Yp), yo_a, d, _dtype_code(Xp), ctypes.byref(o),
-                                 ctypes.c_void_p(ws.data_ptr()), n.value, ctypes.c_void_p(costs.data_ptr()),
-                                 ctypes.c_void_p(paths.data_ptr()), po_a, ctypes.c_void_p(lens.data_ptr()),
-                                 ctypes.byref(st), _stream_ptr(stream))
-    _check(rc, "dtw_align_batched")
-    lens_h = lens.tolist()
-    return costs, [paths[po[b]:po[b] + lens_h[b]] for b in range(B)], st.to_dict()
+    ba = BatchAligner(Xs, Ys, precision, min_block)
+    st = ba.run(stream)
+    return ba.costs, ba.path_list(), st
 
 
 def diag(X, Y, i0, j0, i1, j1, reverse, kstop, precision="fp64", stream=None):
