@@ -190,54 +190,92 @@ __device__ __forceinline__ void publish(int t, int lane, const T* hist, typename
   }
 }
 
-// BF16 Gram-form producer (dtw_gram.h): waves 1 and 2 compute the 32x32
-// cost tiles of stripe rows 0..31 and 32..63 for the 32 columns of the next
-// phase with DP/16 matrix-core operations each, then the FP32 epilogue
-// sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring; the other producer
-// waves only keep the barrier count.  Row r of the stripe is frame
-// gi0 + gis*(a0 + r) of Xb, column j is frame gj0 + gjs*j of Yb; rows past Lr
-// reuse row Lr and columns past need_max reuse column need_max.
+// BF16 Gram-form producer (dtw_gram.h).  At the start of a stripe the eight
+// producer waves copy its 64 bf16 X frames into LDS (rows padded by 16 bytes
+// so the operand reads of 16 lanes fall in distinct banks) and take one
+// barrier, which the other waves of the group match with gram_stage_barrier.
+// The 64 x 32 cost block of a phase is two 32x32 tiles (stripe rows 0..31 and
+// 32..63); producer wave w (1..8) owns tile (w-1) & 1 of every fourth phase,
+// (w-1) >> 1 being its phase residue.  It issues the loads of its next
+// block's bf16 Y frames right after writing its current block, so they have
+// three phases to arrive, and at its phase it runs DP/16 matrix-core
+// operations (X operand read from LDS) and the FP32 epilogue
+// sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring.  The tile is formed
+// transposed (Y frames as the first operand): each lane's results then share
+// one stripe row, and the 32 lanes of a half-wave write 32 distinct rows of
+// the ring at once.  Row r of the stripe is frame gi0 + gis*(a0 + r) of Xb,
+// column j is frame gj0 + gjs*j of Yb; rows past Lr reuse row Lr and columns
+// past need_max reuse column need_max.
 template <int DP>
 __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, const uint16_t* __restrict__ Yb,
                                               const float* __restrict__ Xn, const float* __restrict__ Yn, int gi0,
                                               int gis, int gj0, int gjs, int a0, int Lr, int need_max, int n_phases,
                                               int wave, int lane, float* cring) {
   constexpr int KB = DP / 16;
-  const int tile = wave - 1;
-  const bool active = tile < 2;
-  const int half = lane >> 5, l32 = lane & 31;
-  bf16x8_t A[KB];
-  float nx[16];
-  if (active) {
-    const uint16_t* xr = Xb + (int64_t)(gi0 + gis * (a0 + min(tile * 32 + l32, Lr))) * DP + 8 * half;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) A[kb] = load_bf16x8(xr + 16 * kb);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) nx[q] = Xn[gi0 + gis * (a0 + min(tile * 32 + 8 * (q / 4) + 4 * half + q % 4, Lr))];
+  constexpr int XS = DP + 8;  // LDS row stride of the staged frames, in bf16
+  __shared__ __align__(16) uint16_t xs[kWave * XS];
+  __shared__ float ny_stage[kProducers][32];  // |y|^2 of a block's columns, per producer wave
+  const int pw = wave - 1;
+  for (int idx = pw * kWave + lane; idx < kWave * (DP / 8); idx += kProducers * kWave) {
+    const int r = idx / (DP / 8), c = idx % (DP / 8);
+    const uint4 v = *reinterpret_cast<const uint4*>(Xb + (int64_t)(gi0 + gis * (a0 + min(r, Lr))) * DP + 8 * c);
+    *reinterpret_cast<uint4*>(xs + r * XS + 8 * c) = v;
   }
-  for (int k = -1; k < n_phases; ++k) {
-    const int c0 = (k + 1) * kPhase;
-    if (active && c0 <= need_max) {
-      const int j = c0 + l32;
-      const int gj = gj0 + gjs * min(j, need_max);
+  const int tile = pw & 1, res = pw >> 1;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int row = tile * 32 + l32;  // stripe row of all of this lane's results
+  const float nx = Xn[gi0 + gis * (a0 + min(row, Lr))];
+  bf16x8_t Yo[KB];
+  float ny_own = 0.0f;
+  auto issue = [&](int kw) {  // loads of the block written at iteration kw
+    const int c0 = (kw + 1) * kPhase;
+    if (c0 <= need_max) {
+      const int gj = gj0 + gjs * min(c0 + l32, need_max);
       const uint16_t* yr = Yb + (int64_t)gj * DP + 8 * half;
-      f32x16_t acc = f32x16_zero();
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32x32x16(A[kb], load_bf16x8(yr + 16 * kb), acc);
-      const float ny = Yn[gj];
+      for (int kb = 0; kb < KB; ++kb) Yo[kb] = load_bf16x8(yr + 16 * kb);
+      ny_own = Yn[gj];
+    }
+  };
+  int kw = res - 1;
+  issue(kw);
+  lds_barrier();  // the staged frames are visible (matched by gram_stage_barrier)
+  const uint16_t* xrow = xs + row * XS + 8 * half;
+  for (int k = -1; k < n_phases; ++k) {
+    if (k == kw) {
+      const int c0 = (k + 1) * kPhase;
+      if (c0 <= need_max) {
+        f32x16_t acc = f32x16_zero();
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int row = tile * 32 + 8 * (q / 4) + 4 * half + q % 4;
-        const float v = fmaxf(__builtin_fmaf(-2.0f, acc[q], nx[q] + ny), 0.0f);
-        cring[((j + row) & (kCostRing - 1)) * kWave + row] = __builtin_amdgcn_sqrtf(v);
+        for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32x32x16(Yo[kb], load_bf16x8(xrow + 16 * kb), acc);
+        // register q of this lane holds column 8*(q/4) + 4*half + q%4 of the block
+        float* nys = ny_stage[pw];
+        if (half == 0) nys[l32] = ny_own;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int jj = 8 * (q / 4) + 4 * half + q % 4;
+          const float v = fmaxf(__builtin_fmaf(-2.0f, acc[q], nx + nys[jj]), 0.0f);
+          cring[((c0 + jj + row) & (kCostRing - 1)) * kWave + row] = __builtin_amdgcn_sqrtf(v);
+        }
+        __builtin_amdgcn_wave_barrier();
       }
+      kw += 4;
+      issue(kw);
     }
     lds_barrier();
   }
 }
 
+// The barrier that the recurrence and input waves take to match the producer
+// waves' frame staging in the Gram form (none in the Euclidean form).
+template <int CM>
+__device__ __forceinline__ void gram_stage_barrier() {
+  if constexpr (CM == kCostGram) lds_barrier();
+}
+
 template <typename T, int D, int CM>
-__global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+__global__ __launch_bounds__(kPassThreads, ((D >= 32 && CM != kCostGram) ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
@@ -302,6 +340,7 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
       const int t_band = min(n_steps, max(0, P.kstop - a0 - 2));
       T f = INF;                                          // own F(a, b-1)
       T up_prev = (s == 0 && lane == 0) ? T(0) : INF;     // F(a-1, b-1)
+      gram_stage_barrier<CM>();
       lds_barrier();  // phase -1: first costs and boundary chunk
       for (int k = 0; k < n_phases; ++k) {
         const int t0 = k * kPhase;
@@ -417,6 +456,7 @@ __global__ __launch_bounds__(kPassThreads, (D >= 32 ? 4 : 5)) void pass_kernel(c
       }
     } else {
       // ------------------------------------------------ boundary input
+      gram_stage_barrier<CM>();
       uint32_t* gen_out = w.gens + P.gen_off + s % kRing;
       uint32_t* gen_in = w.gens + P.gen_off + (s + kRing - 1) % kRing;
       if (has_pred) (void)poll_cell<uint32_t>(gen_in, my_tag - 1u, w, true);
@@ -577,6 +617,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     const bool has_succ = sw + kWave < S.R;
     if (wave == 0) {
       uint32_t* bpst = bp + (int64_t)(sw / kWave) * S.Wm * kWave;
+      gram_stage_barrier<CM>();
       fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane)
                   : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane);
     } else if (wave <= kProducers && CM == kCostGram) {
@@ -612,6 +653,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
       }
     } else {
       // ------------------------------------------------ boundary input
+      gram_stage_barrier<CM>();
       for (int k = -1; k < n_phases; ++k) {
         const int col = (k + 1) * kPhase + lane;
         if (lane < kPhase) bring[col & (2 * kPhase - 1)] = (has_pred && col < S.Cc) ? brow[col] : INF;

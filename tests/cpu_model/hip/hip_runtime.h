@@ -40,6 +40,7 @@ extern thread_local std::barrier<>* cpu_wave_barrier;  // the 64 threads of this
 inline void __syncthreads() { cpu_block_barrier->arrive_and_wait(); }
 
 struct int2 { int x, y; };
+struct uint4 { unsigned x, y, z, w; };
 struct double2 { double x, y; };
 inline int2 make_int2(int a, int b) { return int2{a, b}; }
 inline double2 make_double2(double a, double b) { return double2{a, b}; }
