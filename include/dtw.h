@@ -129,7 +129,8 @@ dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
  *   path_len_out device, 1 int64
  *   stats       host, may be NULL; when set the call synchronises `stream`
  *   stream      hipStream_t or NULL
- * Supported feature dimensions: 1 <= d <= 32 for DTW_PREC_FP64 / FP32,
+ * Supported feature dimensions: 1 <= d <= 128 for DTW_PREC_FP64 / FP32 (frames
+ * zero-padded to 4, 8, 12, 16, 24, 32, 64 or 128),
  * 1 <= d <= 128 for DTW_PREC_BF16_COST (frames zero-padded to 32, 64 or 128);
  * other d give DTW_ERR_UNSUPPORTED. */
 dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t d,

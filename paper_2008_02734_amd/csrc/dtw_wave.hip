@@ -79,6 +79,41 @@ __device__ __forceinline__ void frame_cost2(const T (&x)[D], const T* __restrict
   c1 = sqrt_t(s1);
 }
 
+// Frame widths of 64 and more: the lane's frame xl is read in chunks of 16
+// dimensions (from LDS in the sweep, where the stripe's frames are staged, or
+// from HBM in the leaf) and each chunk serves four wave-uniform Y frames, so
+// register use stays bounded and every cost keeps the dimension order of
+// frame_cost.
+template <typename T, int D>
+__device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const T* __restrict__ y0,
+                                                 const T* __restrict__ y1, const T* __restrict__ y2,
+                                                 const T* __restrict__ y3, T (&c)[4]) {
+  constexpr int KC = 16;
+  static_assert(D % KC == 0, "wide frame widths are multiples of 16");
+  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll 2
+  for (int kc = 0; kc < D; kc += KC) {
+    T xc[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) xc[q] = xl[kc + q];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      const T e0 = xc[q] - y0[kc + q];
+      const T e1 = xc[q] - y1[kc + q];
+      const T e2 = xc[q] - y2[kc + q];
+      const T e3 = xc[q] - y3[kc + q];
+      s0 = fma_t(e0, e0, s0);
+      s1 = fma_t(e1, e1, s1);
+      s2 = fma_t(e2, e2, s2);
+      s3 = fma_t(e3, e3, s3);
+    }
+  }
+  c[0] = sqrt_t(s0);
+  c[1] = sqrt_t(s1);
+  c[2] = sqrt_t(s2);
+  c[3] = sqrt_t(s3);
+}
+
 // ----------------------------------------------------------------- pass kernel
 //
 // One workgroup owns a stripe of 64 consecutive local rows of one sweep and
@@ -268,14 +303,21 @@ __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, c
 }
 
 // The barrier that the recurrence and input waves take to match the producer
-// waves' frame staging in the Gram form (none in the Euclidean form).
+// waves' staging of the stripe's frames in LDS: the Gram form (sweep and
+// leaf) and the sweep's Euclidean form at frame widths of 64 and more.
+template <bool kStaged>
+__device__ __forceinline__ void stage_barrier() {
+  if constexpr (kStaged) lds_barrier();
+}
 template <int CM>
 __device__ __forceinline__ void gram_stage_barrier() {
-  if constexpr (CM == kCostGram) lds_barrier();
+  stage_barrier<CM == kCostGram>();
 }
+template <int CM, int D>
+constexpr bool kPassStagesRows = (CM == kCostGram) || (D >= 64);
 
 template <typename T, int D, int CM>
-__global__ __launch_bounds__(kPassThreads, ((D >= 32 && CM != kCostGram) ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+__global__ __launch_bounds__(kPassThreads, (CM == kCostGram ? 5 : D == 32 ? 4 : (D >= 64 && sizeof(T) == 8) ? 3 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
@@ -284,6 +326,8 @@ __global__ __launch_bounds__(kPassThreads, ((D >= 32 && CM != kCostGram) ? 4 : 5
   __shared__ int sh_ticket;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
+  // the recurrence wave issues first on its SIMD: its dependency chain sets the pace
+  if (wave == 0) __builtin_amdgcn_s_setprio(3);
   Ctl* ctl = w.ctl;
   const int n_tickets = clamp_count(ctl, ctl->n_tickets, w.caps.ticket);
   const int n_pass = clamp_count(ctl, ctl->n_pass, 2 * w.caps.sub);
@@ -340,7 +384,7 @@ __global__ __launch_bounds__(kPassThreads, ((D >= 32 && CM != kCostGram) ? 4 : 5
       const int t_band = min(n_steps, max(0, P.kstop - a0 - 2));
       T f = INF;                                          // own F(a, b-1)
       T up_prev = (s == 0 && lane == 0) ? T(0) : INF;     // F(a-1, b-1)
-      gram_stage_barrier<CM>();
+      stage_barrier<kPassStagesRows<CM, D>>();
       lds_barrier();  // phase -1: first costs and boundary chunk
       for (int k = 0; k < n_phases; ++k) {
         const int t0 = k * kPhase;
@@ -424,39 +468,76 @@ __global__ __launch_bounds__(kPassThreads, ((D >= 32 && CM != kCostGram) ? 4 : 5
         gram_producer<D>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
                          P.dir ? P.i1 : P.i0, P.dir ? -1 : 1, P.dir ? P.j1 : P.j0, P.dir ? -1 : 1, a0, Lr,
                          need_max, n_phases, wave, lane, reinterpret_cast<float*>(cring));
+    } else if (wave <= kProducers && D >= 64) {
+      // ------------------------------------------------ frame costs, wide frames
+      if constexpr (D >= 64 && CM != kCostGram) {
+        // the stripe's frames in LDS, rows padded by 16 bytes (bank spread of the chunk reads)
+        constexpr int XS = D + 16 / (int)sizeof(T);
+        constexpr int CPR = D * (int)sizeof(T) / 16;  // 16-byte chunks per frame
+        __shared__ __align__(16) T xs[kWave * XS];
+        const int pw = wave - 1;
+        for (int idx = pw * kWave + lane; idx < kWave * CPR; idx += kProducers * kWave) {
+          const int r = idx / CPR, c = idx % CPR;
+          const int gi = P.dir ? P.i1 - (a0 + min(r, Lr)) : P.i0 + a0 + min(r, Lr);
+          *reinterpret_cast<uint4*>(xs + r * XS + c * (16 / (int)sizeof(T))) =
+              *reinterpret_cast<const uint4*>(X + (int64_t)gi * D + c * (16 / (int)sizeof(T)));
+        }
+        lds_barrier();  // staged frames visible (matched by stage_barrier in the other waves)
+        const T* xl = xs + lane * XS;
+        for (int k = -1; k < n_phases; ++k) {
+          const int c0 = (k + 1) * kPhase;
+          if (c0 <= need_max) {
+            int gj[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int jc = min(c0 + pw + i * kProducers, need_max);
+              gj[i] = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc : P.j0 + jc);
+            }
+            T cv[4];
+            frame_cost4_wide<T, D>(xl, Y + (int64_t)gj[0] * D, Y + (int64_t)gj[1] * D, Y + (int64_t)gj[2] * D,
+                                   Y + (int64_t)gj[3] * D, cv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              cring[((c0 + pw + i * kProducers + lane) & (kCostRing - 1)) * kWave + lane] = cv[i];
+          }
+          lds_barrier();
+        }
+      }
     } else if (wave <= kProducers) {
       // ------------------------------------------------ frame costs
-      const int pw = wave - 1;
-      T x[D];
-      {
-        const int r = min(lane, Lr);  // lanes below the stripe's last row reuse it
-        const int gi = P.dir ? P.i1 - (a0 + r) : P.i0 + a0 + r;
-        const T* xr = X + (int64_t)gi * D;
-#pragma unroll
-        for (int q = 0; q < D; ++q) x[q] = xr[q];
-      }
-      for (int k = -1; k < n_phases; ++k) {
-        const int c0 = (k + 1) * kPhase;
-        if (c0 <= need_max) {
-          // two columns at a time: two independent fma chains per lane
-#pragma unroll
-          for (int i = 0; i < kPhase / kProducers; i += 2) {
-            const int j0 = c0 + pw + i * kProducers, j1 = j0 + kProducers;
-            const int jc0 = min(j0, need_max), jc1 = min(j1, need_max);
-            const int gj0 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc0 : P.j0 + jc0);
-            const int gj1 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc1 : P.j0 + jc1);
-            T cv0, cv1;
-            frame_cost2<T, D>(x, Y + (int64_t)gj0 * D, Y + (int64_t)gj1 * D, cv0, cv1);
-            // columns past need_max hold a clamped column's cost; nothing reads them
-            cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
-            cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
-          }
+      if constexpr (D < 64) {
+        const int pw = wave - 1;
+        T x[D];
+        {
+          const int r = min(lane, Lr);  // lanes below the stripe's last row reuse it
+          const int gi = P.dir ? P.i1 - (a0 + r) : P.i0 + a0 + r;
+          const T* xr = X + (int64_t)gi * D;
+  #pragma unroll
+          for (int q = 0; q < D; ++q) x[q] = xr[q];
         }
-        lds_barrier();
+        for (int k = -1; k < n_phases; ++k) {
+          const int c0 = (k + 1) * kPhase;
+          if (c0 <= need_max) {
+            // two columns at a time: two independent fma chains per lane
+  #pragma unroll
+            for (int i = 0; i < kPhase / kProducers; i += 2) {
+              const int j0 = c0 + pw + i * kProducers, j1 = j0 + kProducers;
+              const int jc0 = min(j0, need_max), jc1 = min(j1, need_max);
+              const int gj0 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc0 : P.j0 + jc0);
+              const int gj1 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc1 : P.j0 + jc1);
+              T cv0, cv1;
+              frame_cost2<T, D>(x, Y + (int64_t)gj0 * D, Y + (int64_t)gj1 * D, cv0, cv1);
+              // columns past need_max hold a clamped column's cost; nothing reads them
+              cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
+              cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
+            }
+          }
+          lds_barrier();
+        }
       }
     } else {
       // ------------------------------------------------ boundary input
-      gram_stage_barrier<CM>();
+      stage_barrier<kPassStagesRows<CM, D>>();
       uint32_t* gen_out = w.gens + P.gen_off + s % kRing;
       uint32_t* gen_in = w.gens + P.gen_off + (s + kRing - 1) % kRing;
       if (has_pred) (void)poll_cell<uint32_t>(gen_in, my_tag - 1u, w, true);
@@ -626,30 +707,53 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
         gram_producer<D>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
                          ColN, S.r0 + sw, 1, S.c0, 1, 0, Lr, S.Cc - 1, n_phases, wave, lane,
                          reinterpret_cast<float*>(cring));
+    } else if (wave <= kProducers && D >= 64) {
+      // ------------------------------------------------ frame costs, wide frames (read from HBM)
+      if constexpr (D >= 64 && CM != kCostGram) {
+        const int pw = wave - 1;
+        const T* xl = RowSrc + (int64_t)(S.r0 + sw + min(lane, Lr)) * D;
+        for (int k = -1; k < n_phases; ++k) {
+          const int cb0 = (k + 1) * kPhase;
+          if (cb0 < S.Cc) {
+            int gj[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gj[i] = __builtin_amdgcn_readfirstlane(S.c0 + min(cb0 + pw + i * kProducers, S.Cc - 1));
+            T cv[4];
+            frame_cost4_wide<T, D>(xl, ColSrc + (int64_t)gj[0] * D, ColSrc + (int64_t)gj[1] * D,
+                                   ColSrc + (int64_t)gj[2] * D, ColSrc + (int64_t)gj[3] * D, cv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              cring[((cb0 + pw + i * kProducers + lane) & (kCostRing - 1)) * kWave + lane] = cv[i];
+          }
+          lds_barrier();
+        }
+      }
     } else if (wave <= kProducers) {
       // ------------------------------------------------ frame costs
-      const int pw = wave - 1;
-      T x[D];
-      {
-        const T* xr = RowSrc + (int64_t)(S.r0 + sw + min(lane, Lr)) * D;
-#pragma unroll
-        for (int q = 0; q < D; ++q) x[q] = xr[q];
-      }
-      for (int k = -1; k < n_phases; ++k) {
-        const int cb0 = (k + 1) * kPhase;
-        if (cb0 < S.Cc) {
-#pragma unroll
-          for (int i = 0; i < kPhase / kProducers; i += 2) {
-            const int j0 = cb0 + pw + i * kProducers, j1 = j0 + kProducers;
-            const int gj0 = __builtin_amdgcn_readfirstlane(S.c0 + min(j0, S.Cc - 1));
-            const int gj1 = __builtin_amdgcn_readfirstlane(S.c0 + min(j1, S.Cc - 1));
-            T cv0, cv1;
-            frame_cost2<T, D>(x, ColSrc + (int64_t)gj0 * D, ColSrc + (int64_t)gj1 * D, cv0, cv1);
-            cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
-            cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
-          }
+      if constexpr (D < 64) {
+        const int pw = wave - 1;
+        T x[D];
+        {
+          const T* xr = RowSrc + (int64_t)(S.r0 + sw + min(lane, Lr)) * D;
+  #pragma unroll
+          for (int q = 0; q < D; ++q) x[q] = xr[q];
         }
-        lds_barrier();
+        for (int k = -1; k < n_phases; ++k) {
+          const int cb0 = (k + 1) * kPhase;
+          if (cb0 < S.Cc) {
+  #pragma unroll
+            for (int i = 0; i < kPhase / kProducers; i += 2) {
+              const int j0 = cb0 + pw + i * kProducers, j1 = j0 + kProducers;
+              const int gj0 = __builtin_amdgcn_readfirstlane(S.c0 + min(j0, S.Cc - 1));
+              const int gj1 = __builtin_amdgcn_readfirstlane(S.c0 + min(j1, S.Cc - 1));
+              T cv0, cv1;
+              frame_cost2<T, D>(x, ColSrc + (int64_t)gj0 * D, ColSrc + (int64_t)gj1 * D, cv0, cv1);
+              cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
+              cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
+            }
+          }
+          lds_barrier();
+        }
       }
     } else {
       // ------------------------------------------------ boundary input
@@ -707,6 +811,7 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
   __shared__ int sh_ticket;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
+  if (wave == 0) __builtin_amdgcn_s_setprio(3);  // the recurrence wave sets the pace
   Ctl* ctl = w.ctl;
   const int n_leaf = clamp_count(ctl, ctl->n_leaf, w.caps.leaf);
   (void)lds_leaf_bytes;
@@ -807,6 +912,8 @@ int pick_dmax(int d) {
   if (d <= 16) return 16;
   if (d <= 24) return 24;
   if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  if (d <= 128) return 128;
   return 0;
 }
 
@@ -818,6 +925,8 @@ int pick_dmax(int d) {
     case 16: { constexpr int D_ = 16; CALL; } break; \
     case 24: { constexpr int D_ = 24; CALL; } break; \
     case 32: { constexpr int D_ = 32; CALL; } break; \
+    case 64: { constexpr int D_ = 64; CALL; } break; \
+    case 128: { constexpr int D_ = 128; CALL; } break; \
     default: return hipErrorInvalidValue;            \
   }
 
@@ -889,8 +998,10 @@ hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32) {
 #define DTW_LEAF_ALL(M_)                                                                                  \
   M_(double, 4, kCostEuclid, 0) M_(double, 8, kCostEuclid, 0) M_(double, 12, kCostEuclid, 0)              \
   M_(double, 16, kCostEuclid, 0) M_(double, 24, kCostEuclid, 0) M_(double, 32, kCostEuclid, 0)            \
+  M_(double, 64, kCostEuclid, 0) M_(double, 128, kCostEuclid, 0)                                          \
   M_(float, 4, kCostEuclid, 1) M_(float, 8, kCostEuclid, 1) M_(float, 12, kCostEuclid, 1)                 \
   M_(float, 16, kCostEuclid, 1) M_(float, 24, kCostEuclid, 1) M_(float, 32, kCostEuclid, 1)               \
+  M_(float, 64, kCostEuclid, 1) M_(float, 128, kCostEuclid, 1)                                            \
   M_(float, 32, kCostGram, 1) M_(float, 64, kCostGram, 1) M_(float, 128, kCostGram, 1)
   DTW_LEAF_ALL(DTW_LEAF_STATIC)
 #undef DTW_LEAF_STATIC

@@ -48,6 +48,8 @@ int pick_dmax(int d) {
   if (d <= 16) return 16;
   if (d <= 24) return 24;
   if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  if (d <= 128) return 128;
   return 0;
 }
 
@@ -284,6 +286,8 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
     case 16: { constexpr int D_ = 16; CALL; } break;               \
     case 24: { constexpr int D_ = 24; CALL; } break;               \
     case 32: { constexpr int D_ = 32; CALL; } break;               \
+    case 64: { constexpr int D_ = 64; CALL; } break;               \
+    case 128: { constexpr int D_ = 128; CALL; } break;             \
     default: std::abort();                                          \
   }
 #define MODEL_DISPATCH_GRAM(D_VAR, CALL)                            \

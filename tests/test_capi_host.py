@@ -52,7 +52,7 @@ def test_argument_errors_before_any_device_work():
     assert _align(L, cost=0) == -1
     assert _align(L, cap=18) == -2        # M + N - 1 = 19 needed
     assert _align(L, wsb=16) == -3
-    assert _align(L, d=33) == -8          # feature dimension not built
+    assert _align(L, d=129) == -8         # feature dimension not built
     bad = dtw.make_opts(min_block=2)
     assert _align(L, opts=bad) == -1      # recursion would not terminate
     bad = dtw.make_opts(min_block=2000)

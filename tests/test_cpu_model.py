@@ -143,7 +143,8 @@ def test_model_batched(model_exe):
         assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
-WAVE_CASES = [(37, 29, 3, 3), (70, 50, 12, 16), (130, 90, 5, 3), (20, 300, 4, 16), (9, 9, 2, 500)]
+WAVE_CASES = [(37, 29, 3, 3), (70, 50, 12, 16), (130, 90, 5, 3), (20, 300, 4, 16), (9, 9, 2, 500),
+              (90, 75, 64, 16), (70, 100, 100, 500), (80, 60, 128, 3)]
 
 
 @pytest.mark.parametrize("M,N,d,m", WAVE_CASES)

@@ -50,6 +50,9 @@ SWEEP_CASES = [
     (200, 180, 12, (17, 9, 180, 170), "mid"),  # sub-block
     (65, 64, 1, None, "mid"),         # one row past a full stripe
     (40, 400, 32, None, "mid"),       # single stripe, long row
+    (150, 130, 64, None, "mid"),      # wide frames staged in LDS
+    (90, 200, 100, None, "mid"),      # wide frames, padded to 128
+    (200, 150, 128, (5, 3, 190, 140), "mid"),  # wide frames, sub-block
 ]
 
 
@@ -93,6 +96,23 @@ ALIGN_CASES = [(s, M, N, d, m) for s, (M, N, d) in enumerate(
 # runs the case to the oracle's path; it stays off the GPU until a cause is
 # shown.
 HUNG_ON_GPU = {(0, 37, 29, 3, 3)}
+
+
+WIDE_CASES = [(700, 560, 64, 500), (650, 900, 100, 16), (1200, 1000, 128, 500), (129, 70, 128, 3)]
+
+
+@pytest.mark.parametrize("M,N,d,m", WIDE_CASES)
+def test_align_wide_frames(dtw, M, N, d, m):
+    # frame widths 64..128: the sweep reads the stripe's frames from LDS in
+    # 16-dimension chunks, the leaf from HBM; the same exact bar as above
+    X, Y = synth.random_pair(9100 + d + m, M, N, d, "normal")
+    cost, path, st = dtw.align(dev(X), dev(Y), min_block=m)
+    assert st["device_error"] == 0
+    path = path.cpu().numpy()
+    check_path(path, M, N)
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
 @pytest.mark.parametrize("s,M,N,d,m", ALIGN_CASES)

@@ -78,6 +78,13 @@ def test_fp32_chroma_d24_float_inputs(dtw, p):
     fp32_case(dtw, X.astype(np.float32), Y.astype(np.float32), 500, in_dtype=torch.float32)
 
 
+@pytest.mark.parametrize("M,N,d", [(3000, 2500, 128), (1500, 1800, 64)])
+def test_fp32_wide_embedding(dtw, M, N, d):
+    # wide frames on the VALU in FP32 (the Euclidean form at d = 64..128)
+    X, Y = synth.make_pair(3, 400 + d, M, N, d, "embedding")
+    fp32_case(dtw, X.astype(np.float32), Y.astype(np.float32), 500, in_dtype=torch.float32)
+
+
 def test_fp32_batched_equals_single(dtw):
     shapes = synth.batch_shapes(6, lo=500, hi=3000)
     Xs, Ys = [], []
