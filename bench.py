@@ -143,6 +143,9 @@ def bench_single(args, cfg):
         "levels": st["levels"], "leaves": st["leaves"],
         "roofline": roofline(stats, prec, d, kname, measured_traffic() if cfg == 2 else None),
     })
+    if cfg == 3 and not args.no_fp64_comparison:
+        out["fp64_same_input"] = fp64_comparison_single(Xd, Yd, W, al)
+        out["fp64_same_input"]["speedup_of_reduced_precision"] = out["fp64_same_input"]["ms"] / ms
     if not args.no_cpu_baseline:
         import oracle
         # the oracle's full table on the pair (cfg 1, 2) or on its leading
@@ -164,6 +167,30 @@ def bench_single(args, cfg):
             cs, ps, _ = dtw.align(Xd[:Ms].contiguous(), Yd[:Ns].contiguous(), precision=prec, min_block=W["m"])
             out["parity"] = {"block": [Ms, Ns], "cost_rel_err_vs_fp64_oracle": (cs - c_ref) / c_ref}
     return out
+
+
+def fp64_comparison_single(Xd, Yd, W, al):
+    """The same input through the exact all-FP64 path (identical to the
+    oracle's path by the parity tests): its time, and the reduced-precision
+    result's cost error and frame deviation against it."""
+    import torch
+
+    from paper_2008_02734_amd import dtw, metrics
+    M, N, d = Xd.shape[0], Yd.shape[0], Xd.shape[1]
+    X64, Y64 = Xd.to(torch.float64), Yd.to(torch.float64)
+    al64 = dtw.Aligner(M, N, d, torch.float64, "fp64", W["m"], device="cuda:0")
+    al64.run(X64, Y64)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = al64.run(X64, Y64, stats=True)
+    s64 = time.perf_counter() - t
+    c64 = float(al64.cost.item())
+    p64 = al64.path[: int(al64.plen.item())].cpu().numpy()
+    plo = al.path[: int(al.plen.item())].cpu().numpy()
+    dv = metrics.summary(plo, p64)
+    return {"ms": s64 * 1e3, "gcups": M * N / s64 / 1e9, "cost": c64, "device_error": st["device_error"],
+            "rel_cost_err": (float(al.cost.item()) - c64) / c64, "path_dev_mean_frames": dv["mean_frames"],
+            "path_dev_max_frames": int(dv["max_frames"]), "frac_within_1_frame": dv["frac_le_1"]}
 
 
 def bench_batched(args):
@@ -202,6 +229,25 @@ def bench_batched(args):
                               ("ms_sweep", "ms_split", "ms_plan", "ms_leaf", "ms_other")},
                 "levels": st["levels"], "leaves": st["leaves"],
                 "roofline": roofline(stats, "fp32", d, "pass_kernel<float,24> (wavefront sweep)")})
+    if not args.no_fp64_comparison:
+        from paper_2008_02734_amd import metrics
+        r64 = dtw.BatchAligner([x.to(torch.float64) for x in Xl], [y.to(torch.float64) for y in Yl],
+                               precision="fp64", min_block=500)
+        r64.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st64 = r64.run()
+        s64 = time.perf_counter() - t
+        c32, c64 = runner.costs.cpu().numpy(), r64.costs.cpu().numpy()
+        rel = (c32 - c64) / c64
+        devs = [metrics.summary(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(runner.path_list(), r64.path_list())]
+        out["fp64_same_input"] = {
+            "ms": s64 * 1e3, "gcups": cells / s64 / 1e9, "device_error": st64["device_error"],
+            "speedup_of_reduced_precision": s64 * 1e3 / ms, "max_rel_cost_err": float(np.max(np.abs(rel))),
+            "mean_rel_cost_err": float(np.mean(np.abs(rel))),
+            "path_dev_mean_frames": float(np.mean([v["mean_frames"] for v in devs])),
+            "path_dev_max_frames": int(max(v["max_frames"] for v in devs)),
+            "pairs_with_identical_path": int(sum(v["max_frames"] == 0 for v in devs))}
     if not args.no_cpu_baseline:
         import oracle
         t = time.perf_counter()
@@ -218,14 +264,48 @@ def bench_batched(args):
     return out
 
 
+def run_stream(dtw, reqs, precs, rng, frac=0.7):
+    """One pass of the request list through a fresh server: a pilot with every
+    request submitted at once (the saturated rate), then a Poisson stream at
+    `frac` of that rate.  Returns throughput, latencies and the results."""
+    cells = sum(q[0].shape[0] * q[1].shape[0] for q in reqs)
+    srv = dtw.Server(pool_bytes=16 << 30, max_slots=8, max_batch=16)
+    try:
+        t0 = time.perf_counter()
+        tk = [srv.submit(q[0], q[1], precision=p) for q, p in zip(reqs, precs)]
+        for t in tk:
+            srv.wait(t)
+        pilot_s = time.perf_counter() - t0
+        lam = frac * len(reqs) / pilot_s
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+        t0 = time.perf_counter()
+        tickets = []
+        for (X, Y, *_), p, at in zip(reqs, precs, arrivals):
+            while time.perf_counter() - t0 < at:
+                time.sleep(50e-6)
+            tickets.append(srv.submit(X, Y, precision=p))
+        res = [srv.wait(t) for t in tickets]
+        makespan = time.perf_counter() - t0
+    finally:
+        srv.close()
+    assert all(r["status"] == 0 and r["device_error"] == 0 for r in res), [r for r in res if r["status"]][:1]
+    lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) / 1e6 for r in res])
+    return {"gcups": cells / makespan / 1e9, "saturated_gcups": cells / pilot_s / 1e9, "lambda_per_s": lam,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "makespan_ms": makespan * 1e3, "max_batch_seen": int(max(r["batch_size"] for r in res)),
+            "costs": [r["cost"] for r in res]}
+
+
 def bench_serving(args):
     """cfg 5, scaled: a Poisson stream of requests through the serving loop.
     M log-uniform in [2000, 40000] (the configuration's upper end, 400000, is
     scaled down so the stream finishes in seconds), N = M x U[0.75, 1.3],
-    half d = 12 chroma-like in FP32, half d = 128 embedding-like in the BF16
-    Gram form.  A pilot run (all requests at once) gives the saturated rate;
-    the stream then arrives at 0.7 of it.  Baseline: the d = 12 requests one
-    at a time through the plain FP64 path."""
+    half d = 12 chroma-like, half d = 128 embedding-like.  Two streams: the
+    configuration's mix (d = 12 in FP32, d = 128 in the BF16 Gram form) and
+    every request in FP32.  A pilot (all requests at once) gives the saturated
+    rate; each stream then arrives at 0.7 of it.  Baseline: every request one
+    at a time through the plain FP64 path, which also gives the FP64 costs
+    the reduced-precision results are measured against."""
     import torch
 
     from paper_2008_02734_amd import dtw, synth
@@ -235,61 +315,39 @@ def bench_serving(args):
     for r in range(args.requests):
         M = int(np.exp(rng.uniform(np.log(2000), np.log(40000))))
         N = int(M * rng.uniform(0.75, 1.3))
-        if r % 2 == 0:
-            X, Y = synth.make_pair(5, r, M, N, 12, "chroma")
-            reqs.append((torch.from_numpy(X.astype(np.float32)).cuda(), torch.from_numpy(Y.astype(np.float32)).cuda(),
-                         "fp32", X, Y))
-        else:
-            X, Y = synth.make_pair(5, r, M, N, 128, "embedding")
-            reqs.append((torch.from_numpy(X.astype(np.float32)).cuda(), torch.from_numpy(Y.astype(np.float32)).cuda(),
-                         "bf16", None, None))
+        d, fam = (12, "chroma") if r % 2 == 0 else (128, "embedding")
+        X, Y = synth.make_pair(5, r, M, N, d, fam)
+        reqs.append((torch.from_numpy(X.astype(np.float32)).cuda(), torch.from_numpy(Y.astype(np.float32)).cuda(),
+                     d, X, Y))
     torch.cuda.synchronize()
     cells = sum(q[0].shape[0] * q[1].shape[0] for q in reqs)
-    srv = dtw.Server(pool_bytes=16 << 30, max_slots=8, max_batch=16)
-    try:
-        # pilot: everything at once
-        t0 = time.perf_counter()
-        tk = [srv.submit(X, Y, precision=p) for X, Y, p, _, _ in reqs]
-        for t in tk:
-            srv.wait(t)
-        pilot_s = time.perf_counter() - t0
-        rate = len(reqs) / pilot_s
-        lam = 0.7 * rate
-        gaps = rng.exponential(1.0 / lam, size=len(reqs))
-        arrivals = np.cumsum(gaps)
-        t0 = time.perf_counter()
-        tickets = []
-        for (X, Y, p, _, _), at in zip(reqs, arrivals):
-            while time.perf_counter() - t0 < at:
-                time.sleep(50e-6)
-            tickets.append(srv.submit(X, Y, precision=p))
-        res = [srv.wait(t) for t in tickets]
-        makespan = time.perf_counter() - t0
-    finally:
-        srv.close()
-    assert all(r["status"] == 0 for r in res), [r for r in res if r["status"] != 0][:1]
-    lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) / 1e6 for r in res])
-    out = base_record(args, cells / makespan / 1e9, makespan * 1e3, "f32+bf16",
+    mixed = run_stream(dtw, reqs, ["fp32" if q[2] == 12 else "bf16" for q in reqs], rng)
+    fp32 = run_stream(dtw, reqs, ["fp32"] * len(reqs), rng)
+    # baseline: one at a time, plain FP64
+    c64, bt = [], 0.0
+    for X, Y, d, Xh, Yh in reqs:
+        Xd, Yd = torch.from_numpy(Xh).cuda(), torch.from_numpy(Yh).cuda()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        c, _, _ = dtw.align(Xd, Yd)
+        bt += time.perf_counter() - s0
+        c64.append(c)
+    c64 = np.array(c64)
+    base = cells / bt / 1e9
+    is12 = np.array([q[2] == 12 for q in reqs])
+    for st in (mixed, fp32):
+        rel = np.abs((np.array(st.pop("costs")) - c64) / c64)
+        st["max_rel_cost_err"] = float(np.max(rel))
+        st["max_rel_cost_err_d12"] = float(np.max(rel[is12]))
+        st["max_rel_cost_err_d128"] = float(np.max(rel[~is12]))
+        st["vs_fp64_one_at_a_time"] = st["gcups"] / base
+        st["saturated_vs_fp64_one_at_a_time"] = st["saturated_gcups"] / base
+    out = base_record(args, mixed["gcups"], mixed["makespan_ms"], "f32+bf16",
                       {"workload": f"Poisson stream of {len(reqs)} requests, M log-uniform in [2000, 40000], half "
                                    "d=12 FP32, half d=128 BF16 Gram cost, at 0.7x the saturated rate",
                        "requests": len(reqs), "seed": [5, "r"]})
-    out.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "lambda_per_s": lam, "saturated_gcups": cells / pilot_s / 1e9,
-                "max_batch_seen": int(max(r["batch_size"] for r in res))})
-    # baseline: the d = 12 requests one at a time in FP64
-    import torch as _t
-    bcells, bt = 0, 0.0
-    for X, Y, p, Xh, Yh in reqs:
-        if Xh is None:
-            continue
-        Xd, Yd = _t.from_numpy(Xh).cuda(), _t.from_numpy(Yh).cuda()
-        _t.cuda.synchronize()
-        s0 = time.perf_counter()
-        dtw.align(Xd, Yd)
-        bt += time.perf_counter() - s0
-        bcells += Xh.shape[0] * Yh.shape[0]
-    served_d12 = sum(q[0].shape[0] * q[1].shape[0] for q in reqs if q[2] == "fp32")
-    out["baseline_fp64_one_at_a_time"] = {"gcups": bcells / bt / 1e9, "requests": "the d=12 half"}
+    out.update({"p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed_stream": mixed,
+                "fp32_stream": fp32, "fp64_one_at_a_time_gcups": base})
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_sample_serving(reqs)
     return out
 
@@ -298,8 +356,8 @@ def cpu_sample_serving(reqs):
     import oracle
     t = time.perf_counter()
     done = 0
-    for X, Y, p, Xh, Yh in reqs:
-        if Xh is None or Xh.shape[0] > 6000:
+    for X, Y, d, Xh, Yh in reqs:
+        if Xh.shape[0] > 6000:
             continue
         oracle.full(Xh, Yh)
         done += Xh.shape[0] * Yh.shape[0]
@@ -307,7 +365,7 @@ def cpu_sample_serving(reqs):
             break
     cpu_s = time.perf_counter() - t
     return {"value": done / cpu_s / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
-            "sample": f"d=12 requests with M <= 6000 ({done / 1e6:.0f} M cells): textbook FP64 full table, "
+            "sample": f"requests with M <= 6000 in stream order ({done / 1e6:.0f} M cells): textbook FP64 full table, "
                       f"single thread, {cpu_s:.1f} s"}
 
 
@@ -320,6 +378,8 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="pairs of the batched workload (config 4)")
     ap.add_argument("--requests", type=int, default=96, help="requests of the serving stream (config 5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-comparison", action="store_true",
+                    help="skip the all-FP64 run of the same input (configs 3 and 4)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (calibration of HBM byte counters) and exit")
     args = ap.parse_args()
