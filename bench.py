@@ -117,7 +117,10 @@ def bench_single(args, cfg):
 
     from paper_2008_02734_amd import dtw, synth
 
-    W = WORKLOADS[cfg]
+    W = dict(WORKLOADS[cfg])
+    if args.precision:
+        W["precision"] = args.precision
+        W["name"] = W["name"].replace("BF16 Gram", args.precision.upper() + " Gram")
     M, N, d, prec = W["M"], W["N"], W["d"], W["precision"]
     X, Y = synth.make_pair(cfg, 0, M, N, d, W["family"])
     tdt = torch.float64 if prec == "fp64" else torch.float32
@@ -130,8 +133,8 @@ def bench_single(args, cfg):
     st = stats[-1]
     assert all(s["device_error"] == 0 for s in stats), st
     kname = {"fp64": f"pass_kernel<double,{d}>", "fp32": f"pass_kernel<float,{d}>",
-             "bf16": "pass_kernel<float,128,Gram>"}[prec] + " (wavefront sweep)"
-    out = base_record(args, M * N / (ms * 1e-3) / 1e9, ms, {"fp64": "f64", "fp32": "f32", "bf16": "bf16/f32"}[prec],
+             "bf16": "pass_kernel<float,128,Gram>", "fp16": "pass_kernel<float,128,GramF16>"}[prec] + " (wavefront sweep)"
+    out = base_record(args, M * N / (ms * 1e-3) / 1e9, ms, {"fp64": "f64", "fp32": "f32", "bf16": "bf16/f32", "fp16": "f16/f32"}[prec],
                       {"workload": W["name"], "M": M, "N": N, "d": d, "min_block": W["m"], "precision": prec,
                        "seed": [cfg, 0]})
     out.update({
@@ -301,8 +304,8 @@ def bench_serving(args):
     M log-uniform in [2000, 40000] (the configuration's upper end, 400000, is
     scaled down so the stream finishes in seconds), N = M x U[0.75, 1.3],
     half d = 12 chroma-like, half d = 128 embedding-like.  Two streams: the
-    configuration's mix (d = 12 in FP32, d = 128 in the BF16 Gram form) and
-    every request in FP32.  A pilot (all requests at once) gives the saturated
+    configuration's mix (d = 12 in FP32, d = 128 in the BF16 Gram form), the
+    same mix with the FP16 Gram form, and every request in FP32.  A pilot (all requests at once) gives the saturated
     rate; each stream then arrives at 0.7 of it.  Baseline: every request one
     at a time through the plain FP64 path, which also gives the FP64 costs
     the reduced-precision results are measured against."""
@@ -322,6 +325,7 @@ def bench_serving(args):
     torch.cuda.synchronize()
     cells = sum(q[0].shape[0] * q[1].shape[0] for q in reqs)
     mixed = run_stream(dtw, reqs, ["fp32" if q[2] == 12 else "bf16" for q in reqs], rng)
+    mixed16 = run_stream(dtw, reqs, ["fp32" if q[2] == 12 else "fp16" for q in reqs], rng)
     fp32 = run_stream(dtw, reqs, ["fp32"] * len(reqs), rng)
     # baseline: one at a time, plain FP64
     c64, bt = [], 0.0
@@ -335,7 +339,7 @@ def bench_serving(args):
     c64 = np.array(c64)
     base = cells / bt / 1e9
     is12 = np.array([q[2] == 12 for q in reqs])
-    for st in (mixed, fp32):
+    for st in (mixed, mixed16, fp32):
         rel = np.abs((np.array(st.pop("costs")) - c64) / c64)
         st["max_rel_cost_err"] = float(np.max(rel))
         st["max_rel_cost_err_d12"] = float(np.max(rel[is12]))
@@ -347,7 +351,7 @@ def bench_serving(args):
                                    "d=12 FP32, half d=128 BF16 Gram cost, at 0.7x the saturated rate",
                        "requests": len(reqs), "seed": [5, "r"]})
     out.update({"p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed_stream": mixed,
-                "fp32_stream": fp32, "fp64_one_at_a_time_gcups": base})
+                "mixed_fp16_stream": mixed16, "fp32_stream": fp32, "fp64_one_at_a_time_gcups": base})
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_sample_serving(reqs)
     return out
 
@@ -378,6 +382,8 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="pairs of the batched workload (config 4)")
     ap.add_argument("--requests", type=int, default=96, help="requests of the serving stream (config 5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
+                    help="override the single-pair workload's arithmetic (e.g. fp16 for config 3)")
     ap.add_argument("--no-fp64-comparison", action="store_true",
                     help="skip the all-FP64 run of the same input (configs 3 and 4)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

@@ -66,7 +66,8 @@ typedef enum { DTW_F64 = 0, DTW_F32 = 1 } dtw_dtype;
 typedef enum {
   DTW_PREC_FP64 = 0,     /* exact method: frame cost and accumulation in FP64          */
   DTW_PREC_FP32 = 1,     /* frame cost and accumulation in FP32 on the vector ALUs     */
-  DTW_PREC_BF16_COST = 2 /* frame cost from a BF16 Gram tile on MFMA, FP32 accumulation */
+  DTW_PREC_BF16_COST = 2, /* frame cost from a BF16 Gram tile on MFMA, FP32 accumulation */
+  DTW_PREC_FP16_COST = 3  /* the same Gram tile from FP16 frames (finer rounding, same rate) */
 } dtw_precision;
 
 typedef struct dtw_opts {
@@ -131,7 +132,8 @@ dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
  *   stream      hipStream_t or NULL
  * Supported feature dimensions: 1 <= d <= 128 for DTW_PREC_FP64 / FP32 (frames
  * zero-padded to 4, 8, 12, 16, 24, 32, 64 or 128),
- * 1 <= d <= 128 for DTW_PREC_BF16_COST (frames zero-padded to 32, 64 or 128);
+ * 1 <= d <= 128 for DTW_PREC_BF16_COST / FP16_COST (frames zero-padded to 32,
+ * 64 or 128);
  * other d give DTW_ERR_UNSUPPORTED. */
 dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t d,
                      int32_t in_dtype, const dtw_opts* opts, void* workspace,

@@ -22,7 +22,8 @@ hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* 
                            int32_t* paths, int grid, hipStream_t st);
 hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
                               hipStream_t st);
-hipError_t launch_bf16_stage(const void* in, int in_f64, int64_t rows, int d, int D, uint16_t* out, float* norms,
+hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
+                             float* norms,
                              hipStream_t st);
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st);
 hipError_t launch_diag(const Work& w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
@@ -108,12 +109,12 @@ void put(Layout& L, Region& r, size_t bytes) {
   L.total = r.off + bytes;
 }
 
-bool valid_precision(int p) { return p == DTW_PREC_FP64 || p == DTW_PREC_FP32 || p == DTW_PREC_BF16_COST; }
+bool valid_precision(int p) { return p == DTW_PREC_FP64 || p == DTW_PREC_FP32 || is_gram_precision(p); }
 
 // Padded frame width of the compute copies for a precision, 0 if unsupported.
 int frame_width(int d, int precision) {
   if (d < 1) return 0;
-  return precision == DTW_PREC_BF16_COST ? pick_dgram(d) : pick_dmax(d);
+  return is_gram_precision(precision) ? pick_dgram(d) : pick_dmax(d);
 }
 
 // Xrows / Yrows: frames of X / Y that the compute copies must cover.
@@ -147,7 +148,7 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   c.leaf_words = (((int64_t)m + kWave) * (K0sum + c.leaf)) / 16 + ((int64_t)m + kWave) * 6 * c.leaf +
                  2 * (K0sum + c.leaf) + 64;
   c.pslots = K0sum;
-  const bool gram = precision == DTW_PREC_BF16_COST;
+  const bool gram = is_gram_precision(precision);
   const bool f32 = precision == DTW_PREC_FP32 || gram;  // compute type of the recurrence
   L.cbytes = f32 ? 4 : 8;
   L.D = frame_width(d, precision);
@@ -237,7 +238,7 @@ Work make_work(const Layout& L, void* ws, int d, int m, int precision) {
 dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
   dtw_default_opts(out);
   if (o) *out = *o;
-  if (!valid_precision(out->precision)) return out->precision == DTW_PREC_BF16_COST ? DTW_ERR_UNSUPPORTED : DTW_ERR_INVALID_ARG;
+  if (!valid_precision(out->precision)) return DTW_ERR_INVALID_ARG;
   if (out->min_block < 3 || out->min_block > kMaxMinBlock) return DTW_ERR_INVALID_ARG;
   for (int i = 0; i < 4; ++i)
     if (out->reserved[i] != 0) return DTW_ERR_INVALID_ARG;
@@ -318,11 +319,12 @@ hipError_t stage_inputs(const Layout& L, void* ws, const void* X, const void* Y,
   void* xc = at<void>(ws, L.xconv);
   void* yc = at<void>(ws, L.yconv);
   hipError_t e;
-  if (precision == DTW_PREC_BF16_COST) {
+  if (is_gram_precision(precision)) {
     float* xn = at<float>(ws, L.xnorm);
     float* yn = at<float>(ws, L.ynorm);
-    e = launch_bf16_stage(X, in_f64, xrows, d, L.D, static_cast<uint16_t*>(xc), xn, st);
-    if (e == hipSuccess) e = launch_bf16_stage(Y, in_f64, yrows, d, L.D, static_cast<uint16_t*>(yc), yn, st);
+    const int bf16 = precision == DTW_PREC_BF16_COST ? 1 : 0;
+    e = launch_gram_stage(X, in_f64, xrows, d, L.D, bf16, static_cast<uint16_t*>(xc), xn, st);
+    if (e == hipSuccess) e = launch_gram_stage(Y, in_f64, yrows, d, L.D, bf16, static_cast<uint16_t*>(yc), yn, st);
     w.Xn = xn;
     w.Yn = yn;
   } else {

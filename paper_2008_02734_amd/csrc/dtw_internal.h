@@ -29,9 +29,12 @@ constexpr int kCostRing = 128;  // LDS cost slots, indexed by step
 constexpr int kPubGroup = 16;   // steps per boundary-row publication
 
 // Frame cost forms: the exact Euclidean cost on the VALU (FP64 or FP32), or
-// the BF16 Gram form on the matrix cores (dtw_gram.h).
+// the Gram form on the matrix cores (dtw_gram.h) from BF16 or FP16 frames.
 constexpr int kCostEuclid = 0;
-constexpr int kCostGram = 1;
+constexpr int kCostGram = 1;     // BF16 frames
+constexpr int kCostGramF16 = 2;  // FP16 frames
+constexpr bool is_gram(int cm) { return cm != kCostEuclid; }
+constexpr bool is_gram_precision(int p) { return p == DTW_PREC_BF16_COST || p == DTW_PREC_FP16_COST; }
 
 // Content of a boundary-ring cell that has not been written: a signalling
 // NaN.  No arithmetic result is a signalling NaN, so a cell holding any other

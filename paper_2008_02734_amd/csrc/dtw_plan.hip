@@ -453,8 +453,8 @@ __global__ void nonfinite_kernel(const TI* in, int64_t n, int32_t* flag) {
     if (!__builtin_isfinite((double)in[u])) atomicOr(flag, 1);
 }
 
-// Input staging of the Gram form: each frame rounded to bf16 (round to
-// nearest even; FP64 inputs are first rounded to FP32), zero-padded to D
+// Input staging of the Gram form: each frame rounded to bf16 or fp16 (round
+// to nearest even; FP64 inputs are first rounded to FP32), zero-padded to D
 // dimensions, and its squared norm from the rounded values in FP32.  One wave
 // per frame: lane l holds dimensions l and l + 64; the norm is reduced over
 // the wave in a fixed order.
@@ -464,9 +464,41 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
-template <typename TI>
-__global__ __launch_bounds__(256) void bf16_stage_kernel(const TI* __restrict__ in, int64_t rows, int d, int D,
+// IEEE binary16 with round to nearest even, subnormals included (written out
+// in integer arithmetic so that it does not depend on the float mode).
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);
+  const uint32_t sign = (u >> 16) & 0x8000u;
+  const uint32_t a = u & 0x7fffffffu;
+  if (a > 0x7f800000u) return (uint16_t)(sign | 0x7e00u);  // NaN
+  if (a >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u); // at or past the rounding point of 65504: infinity
+  if (a >= 0x38800000u) {                                   // normal: |f| >= 2^-14
+    uint32_t h = (a - 0x38000000u) >> 13;                   // exponent rebiased by 112, 10 mantissa bits
+    const uint32_t rem = a & 0x1fffu;
+    h += (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ? 1u : 0u;
+    return (uint16_t)(sign | h);
+  }
+  if (a < 0x33000000u) return (uint16_t)sign;               // below 2^-25: zero
+  const uint32_t e = a >> 23;                               // 102 .. 112
+  const uint32_t m = (a & 0x7fffffu) | 0x800000u;
+  const uint32_t shift = 126u - e;                          // units of 2^-24
+  uint32_t h = m >> shift;
+  const uint32_t rem = m & ((1u << shift) - 1u), halfway = 1u << (shift - 1u);
+  h += (rem > halfway || (rem == halfway && (h & 1u))) ? 1u : 0u;
+  return (uint16_t)(sign | h);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) {
+  const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+  const uint32_t e = (h >> 10) & 0x1fu, m = h & 0x3ffu;
+  if (e == 0) return __builtin_bit_cast(float, sign | __builtin_bit_cast(uint32_t, (float)m * 0x1p-24f));
+  if (e == 31) return __builtin_bit_cast(float, sign | 0x7f800000u | (m << 13));
+  return __builtin_bit_cast(float, sign | ((e + 112u) << 23) | (m << 13));
+}
+
+template <typename TI, bool kBf16>
+__global__ __launch_bounds__(256) void gram_stage_kernel(const TI* __restrict__ in, int64_t rows, int d, int D,
                                                           uint16_t* __restrict__ out, float* __restrict__ norms) {
   const int lane = threadIdx.x % 64;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -474,9 +506,9 @@ __global__ __launch_bounds__(256) void bf16_stage_kernel(const TI* __restrict__ 
     float s = 0.0f;
     for (int k = lane; k < D; k += 64) {
       const float f = (k < d) ? (float)in[r * d + k] : 0.0f;
-      const uint16_t h = f32_to_bf16_rne(f);
+      const uint16_t h = kBf16 ? f32_to_bf16_rne(f) : f32_to_f16_rne(f);
       out[r * D + k] = h;
-      const float g = __builtin_bit_cast(float, (uint32_t)h << 16);
+      const float g = kBf16 ? bf16_to_f32(h) : f16_to_f32(h);
       s = __builtin_fmaf(g, g, s);
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -546,11 +578,13 @@ hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64
     pad_convert_kernel<float, float><<<grid, 256, 0, st>>>((const float*)in, (float*)out, rows, d, D);
   return hipGetLastError();
 }
-hipError_t launch_bf16_stage(const void* in, int in_f64, int64_t rows, int d, int D, uint16_t* out, float* norms,
-                             hipStream_t st) {
+hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
+                             float* norms, hipStream_t st) {
   const int grid = (int)min((int64_t)2048, (rows + 3) / 4 + 1);
-  if (in_f64) bf16_stage_kernel<double><<<grid, 256, 0, st>>>((const double*)in, rows, d, D, out, norms);
-  else bf16_stage_kernel<float><<<grid, 256, 0, st>>>((const float*)in, rows, d, D, out, norms);
+  if (in_f64 && bf16) gram_stage_kernel<double, true><<<grid, 256, 0, st>>>((const double*)in, rows, d, D, out, norms);
+  else if (bf16) gram_stage_kernel<float, true><<<grid, 256, 0, st>>>((const float*)in, rows, d, D, out, norms);
+  else if (in_f64) gram_stage_kernel<double, false><<<grid, 256, 0, st>>>((const double*)in, rows, d, D, out, norms);
+  else gram_stage_kernel<float, false><<<grid, 256, 0, st>>>((const float*)in, rows, d, D, out, norms);
   return hipGetLastError();
 }
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st) {

@@ -225,14 +225,14 @@ __device__ __forceinline__ void publish(int t, int lane, const T* hist, typename
   }
 }
 
-// BF16 Gram-form producer (dtw_gram.h).  At the start of a stripe the eight
-// producer waves copy its 64 bf16 X frames into LDS (rows padded by 16 bytes
+// Gram-form producer (dtw_gram.h), BF16 frames for kBf16, else FP16.  At the
+// start of a stripe the eight producer waves copy its 64 16-bit X frames into LDS (rows padded by 16 bytes
 // so the operand reads of 16 lanes fall in distinct banks) and take one
 // barrier, which the other waves of the group match with gram_stage_barrier.
 // The 64 x 32 cost block of a phase is two 32x32 tiles (stripe rows 0..31 and
 // 32..63); producer wave w (1..8) owns tile (w-1) & 1 of every fourth phase,
 // (w-1) >> 1 being its phase residue.  It issues the loads of its next
-// block's bf16 Y frames right after writing its current block, so they have
+// block's Y frames right after writing its current block, so they have
 // three phases to arrive, and at its phase it runs DP/16 matrix-core
 // operations (X operand read from LDS) and the FP32 epilogue
 // sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring.  The tile is formed
@@ -241,7 +241,7 @@ __device__ __forceinline__ void publish(int t, int lane, const T* hist, typename
 // the ring at once.  Row r of the stripe is frame gi0 + gis*(a0 + r) of Xb,
 // column j is frame gj0 + gjs*j of Yb; rows past Lr reuse row Lr and columns
 // past need_max reuse column need_max.
-template <int DP>
+template <int DP, bool kBf16>
 __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, const uint16_t* __restrict__ Yb,
                                               const float* __restrict__ Xn, const float* __restrict__ Yn, int gi0,
                                               int gis, int gj0, int gjs, int a0, int Lr, int need_max, int n_phases,
@@ -282,7 +282,7 @@ __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, c
       if (c0 <= need_max) {
         f32x16_t acc = f32x16_zero();
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32x32x16(Yo[kb], load_bf16x8(xrow + 16 * kb), acc);
+        for (int kb = 0; kb < KB; ++kb) acc = mfma_16bit_32x32x16<kBf16>(Yo[kb], load_bf16x8(xrow + 16 * kb), acc);
         // register q of this lane holds column 8*(q/4) + 4*half + q%4 of the block
         float* nys = ny_stage[pw];
         if (half == 0) nys[l32] = ny_own;
@@ -311,13 +311,13 @@ __device__ __forceinline__ void stage_barrier() {
 }
 template <int CM>
 __device__ __forceinline__ void gram_stage_barrier() {
-  stage_barrier<CM == kCostGram>();
+  stage_barrier<is_gram(CM)>();
 }
 template <int CM, int D>
-constexpr bool kPassStagesRows = (CM == kCostGram) || (D >= 64);
+constexpr bool kPassStagesRows = is_gram(CM) || (D >= 64);
 
 template <typename T, int D, int CM>
-__global__ __launch_bounds__(kPassThreads, (CM == kCostGram ? 5 : D == 32 ? 4 : (D >= 64 && sizeof(T) == 8) ? 3 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+__global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >= 64 && sizeof(T) == 8) ? 3 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
@@ -462,15 +462,15 @@ __global__ __launch_bounds__(kPassThreads, (CM == kCostGram ? 5 : D == 32 ? 4 : 
         }
         lds_barrier();
       }
-    } else if (wave <= kProducers && CM == kCostGram) {
-      // ------------------------------------------------ frame costs, BF16 Gram form
-      if constexpr (CM == kCostGram)
-        gram_producer<D>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
+    } else if (wave <= kProducers && is_gram(CM)) {
+      // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
+      if constexpr (is_gram(CM))
+        gram_producer<D, CM == kCostGram>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
                          P.dir ? P.i1 : P.i0, P.dir ? -1 : 1, P.dir ? P.j1 : P.j0, P.dir ? -1 : 1, a0, Lr,
                          need_max, n_phases, wave, lane, reinterpret_cast<float*>(cring));
     } else if (wave <= kProducers && D >= 64) {
       // ------------------------------------------------ frame costs, wide frames
-      if constexpr (D >= 64 && CM != kCostGram) {
+      if constexpr (D >= 64 && !is_gram(CM)) {
         // the stripe's frames in LDS, rows padded by 16 bytes (bank spread of the chunk reads)
         constexpr int XS = D + 16 / (int)sizeof(T);
         constexpr int CPR = D * (int)sizeof(T) / 16;  // 16-byte chunks per frame
@@ -701,15 +701,15 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
       gram_stage_barrier<CM>();
       fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane)
                   : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane);
-    } else if (wave <= kProducers && CM == kCostGram) {
-      // ------------------------------------------------ frame costs, BF16 Gram form
-      if constexpr (CM == kCostGram)
-        gram_producer<D>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
+    } else if (wave <= kProducers && is_gram(CM)) {
+      // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
+      if constexpr (is_gram(CM))
+        gram_producer<D, CM == kCostGram>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
                          ColN, S.r0 + sw, 1, S.c0, 1, 0, Lr, S.Cc - 1, n_phases, wave, lane,
                          reinterpret_cast<float*>(cring));
     } else if (wave <= kProducers && D >= 64) {
       // ------------------------------------------------ frame costs, wide frames (read from HBM)
-      if constexpr (D >= 64 && CM != kCostGram) {
+      if constexpr (D >= 64 && !is_gram(CM)) {
         const int pw = wave - 1;
         const T* xl = RowSrc + (int64_t)(S.r0 + sw + min(lane, Lr)) * D;
         for (int k = -1; k < n_phases; ++k) {
@@ -842,9 +842,9 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     S.r0 = S.tr ? Lf.j0 : Lf.i0;
     S.c0 = S.tr ? Lf.i0 : Lf.j0;
     S.Wm = (S.Cc + kWave - 1 + 15) / 16;
-    // in the Gram form X and Y are the bf16 frames, reached through w.X / w.Y
-    const T* __restrict__ Xs = (CM == kCostGram) ? static_cast<const T*>(w.X) : X;
-    const T* __restrict__ Ys = (CM == kCostGram) ? static_cast<const T*>(w.Y) : Y;
+    // in the Gram form X and Y are the 16-bit frames, reached through w.X / w.Y
+    const T* __restrict__ Xs = is_gram(CM) ? static_cast<const T*>(w.X) : X;
+    const T* __restrict__ Ys = is_gram(CM) ? static_cast<const T*>(w.Y) : Y;
     const T* __restrict__ RowSrc = S.tr ? Ys : Xs;
     const T* __restrict__ ColSrc = S.tr ? Xs : Ys;
     const float* __restrict__ RowN = S.tr ? w.Yn : w.Xn;
@@ -930,7 +930,7 @@ int pick_dmax(int d) {
     default: return hipErrorInvalidValue;            \
   }
 
-// Padded frame width of the Gram form's bf16 copies (multiples of 16 for
+// Padded frame width of the Gram form's 16-bit copies (multiples of 16 for
 // the matrix-core K blocks).
 int pick_dgram(int d) {
   if (d <= 32) return 32;
@@ -953,6 +953,9 @@ hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
   if (w.precision == DTW_PREC_BF16_COST) {
     DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGram><<<grid, kPassThreads, 0, st>>>(
                                             nullptr, nullptr, w, level)))
+  } else if (w.precision == DTW_PREC_FP16_COST) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGramF16><<<grid, kPassThreads, 0, st>>>(
+                                            nullptr, nullptr, w, level)))
   } else if (w.precision == DTW_PREC_FP32) {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), (pass_kernel<float, D_, kCostEuclid><<<grid, kPassThreads, 0, st>>>(
                                           static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w, level)))
@@ -968,6 +971,9 @@ hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const vo
   const size_t dyn = (size_t)lds_leaf_bytes;
   if (w.precision == DTW_PREC_BF16_COST) {
     DTW_DISPATCH_DGRAM(pick_dgram(w.d), (leaf_kernel<float, D_, kCostGram><<<grid, kPassThreads, dyn, st>>>(
+                                            nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
+  } else if (w.precision == DTW_PREC_FP16_COST) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (leaf_kernel<float, D_, kCostGramF16><<<grid, kPassThreads, dyn, st>>>(
                                             nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
   } else if (w.precision == DTW_PREC_FP32) {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), (leaf_kernel<float, D_, kCostEuclid><<<grid, kPassThreads, dyn, st>>>(
@@ -1002,7 +1008,8 @@ hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32) {
   M_(float, 4, kCostEuclid, 1) M_(float, 8, kCostEuclid, 1) M_(float, 12, kCostEuclid, 1)                 \
   M_(float, 16, kCostEuclid, 1) M_(float, 24, kCostEuclid, 1) M_(float, 32, kCostEuclid, 1)               \
   M_(float, 64, kCostEuclid, 1) M_(float, 128, kCostEuclid, 1)                                            \
-  M_(float, 32, kCostGram, 1) M_(float, 64, kCostGram, 1) M_(float, 128, kCostGram, 1)
+  M_(float, 32, kCostGram, 1) M_(float, 64, kCostGram, 1) M_(float, 128, kCostGram, 1)                   \
+  M_(float, 32, kCostGramF16, 1) M_(float, 64, kCostGramF16, 1) M_(float, 128, kCostGramF16, 1)
   DTW_LEAF_ALL(DTW_LEAF_STATIC)
 #undef DTW_LEAF_STATIC
   lim[0] &= ~(int64_t)255;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdtw_hip.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "dtw.h")
 
 DTW_F64, DTW_F32 = 0, 1
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 STATUS = {0: "ok", -1: "invalid argument", -2: "path capacity too small", -3: "workspace too small",
           -4: "non-finite input", -5: "HIP runtime error", -6: "not ready", -7: "unknown ticket",
           -8: "unsupported dimension or mode", -9: "device-side consistency check failed"}

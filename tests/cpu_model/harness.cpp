@@ -70,10 +70,18 @@ static float model_bf16(uint16_t h) {
   return f;
 }
 
-// Gram-form cost from the staged bf16 frames and FP32 norms (k-order FP32 sum).
-static float model_gram_cost(const uint16_t* x, const uint16_t* y, float nx, float ny, int D) {
+// fp16 bits to float (normal, subnormal; the staged frames hold no inf/NaN).
+static float model_f16(uint16_t h) {
+  const int e = (h >> 10) & 0x1f, m = h & 0x3ff;
+  const float v = e == 0 ? std::ldexp((float)m, -24) : std::ldexp((float)(m | 0x400), e - 25);
+  return (h & 0x8000) ? -v : v;
+}
+
+// Gram-form cost from the staged 16-bit frames and FP32 norms (k-order FP32 sum).
+static float model_gram_cost(const uint16_t* x, const uint16_t* y, float nx, float ny, int D, bool bf16) {
   float dot = 0.0f;
-  for (int k = 0; k < D; ++k) dot += model_bf16(x[k]) * model_bf16(y[k]);
+  for (int k = 0; k < D; ++k)
+    dot += bf16 ? model_bf16(x[k]) * model_bf16(y[k]) : model_f16(x[k]) * model_f16(y[k]);
   const float v = std::fmax(std::fma(-2.0f, dot, nx + ny), 0.0f);
   return std::sqrt(v);
 }
@@ -81,10 +89,10 @@ static float model_gram_cost(const uint16_t* x, const uint16_t* y, float nx, flo
 // The frame cost of (gi, gj) in the form the Work asks for.
 template <typename T>
 static T model_frame_cost(const Work& w, int64_t gi, int64_t gj) {
-  if (w.precision == DTW_PREC_BF16_COST) {
+  if (is_gram_precision(w.precision)) {
     const int D = pick_dgram(w.d);
     return (T)model_gram_cost(static_cast<const uint16_t*>(w.X) + gi * D, static_cast<const uint16_t*>(w.Y) + gj * D,
-                              w.Xn[gi], w.Yn[gj], D);
+                              w.Xn[gi], w.Yn[gj], D, w.precision == DTW_PREC_BF16_COST);
   }
   const int D = pick_dmax(w.d);
   return model_cost(static_cast<const T*>(w.X) + gi * D, static_cast<const T*>(w.Y) + gj * D, D);
@@ -301,6 +309,8 @@ hipError_t launch_pass(const Work& w, int level, int, hipStream_t) {
   model_check_queue(w);
   if (w.precision == DTW_PREC_BF16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
+  } else if (w.precision == DTW_PREC_FP16_COST) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, level); })))
   } else if (w.precision == DTW_PREC_FP32) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, level); })))
   } else {
@@ -313,6 +323,8 @@ hipError_t launch_leaf(const Work& w, int, int64_t lds_leaf_bytes, const void* X
   model_check_leaves(w);
   if (w.precision == DTW_PREC_BF16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostGram>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  } else if (w.precision == DTW_PREC_FP16_COST) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else if (w.precision == DTW_PREC_FP32) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else {
@@ -373,10 +385,12 @@ hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64
     cpu_launch(2, 64, [&] { pad_convert_kernel<float, float>((const float*)in, (float*)out, rows, d, D); });
   return hipSuccess;
 }
-hipError_t launch_bf16_stage(const void* in, int in_f64, int64_t rows, int d, int D, uint16_t* out, float* norms,
-                             hipStream_t) {
-  if (in_f64) cpu_launch(2, 256, [&] { bf16_stage_kernel<double>((const double*)in, rows, d, D, out, norms); });
-  else cpu_launch(2, 256, [&] { bf16_stage_kernel<float>((const float*)in, rows, d, D, out, norms); });
+hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
+                             float* norms, hipStream_t) {
+  if (in_f64 && bf16) cpu_launch(2, 256, [&] { gram_stage_kernel<double, true>((const double*)in, rows, d, D, out, norms); });
+  else if (bf16) cpu_launch(2, 256, [&] { gram_stage_kernel<float, true>((const float*)in, rows, d, D, out, norms); });
+  else if (in_f64) cpu_launch(2, 256, [&] { gram_stage_kernel<double, false>((const double*)in, rows, d, D, out, norms); });
+  else cpu_launch(2, 256, [&] { gram_stage_kernel<float, false>((const float*)in, rows, d, D, out, norms); });
   return hipSuccess;
 }
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t) {

@@ -182,14 +182,26 @@ def test_model_gram_form(model_exe, M, N, d, m):
     assert -1e-12 <= (cost - c_ref) / c_ref <= BF16_REL_TOL
 
 
-@pytest.mark.parametrize("M,N,d,m", [(90, 70, 64, 16), (100, 60, 128, 500)])
-def test_wave_model_gram_form(model_exe, wave_exe, M, N, d, m):
+@pytest.mark.parametrize("M,N,d,m", [(120, 100, 128, 16), (60, 90, 40, 500)])
+def test_model_fp16_gram_form(model_exe, M, N, d, m):
+    # the FP16 frames: a valid path within 1e-5 of the oracle's optimum
+    X, Y = _gram_case(M, N, d, 3 * M + N)
+    r = run_model(model_exe, [(X, Y)], m, precision=3)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    cost, path = r["results"][0]
+    c_ref, _ = oracle.full(X, Y)
+    assert abs(cost - oracle.path_cost(X, Y, path)) <= 1e-12 * c_ref
+    assert -1e-12 <= (cost - c_ref) / c_ref <= 1e-5
+
+
+@pytest.mark.parametrize("M,N,d,m,prec", [(90, 70, 64, 16, 2), (100, 60, 128, 500, 2), (80, 75, 128, 16, 3)])
+def test_wave_model_gram_form(model_exe, wave_exe, M, N, d, m, prec):
     # the real kernels with the matrix-core operation emulated in the device's
     # lane layout: same path as the plain model (both sum the bf16 products
     # in k order in FP32)
     X, Y = _gram_case(M, N, d, 7 * M + N)
-    r_wave = run_model(wave_exe, [(X, Y)], m, precision=2)
-    r_plain = run_model(model_exe, [(X, Y)], m, precision=2)
+    r_wave = run_model(wave_exe, [(X, Y)], m, precision=prec)
+    r_plain = run_model(model_exe, [(X, Y)], m, precision=prec)
     assert r_wave["rc"] == 0 and r_wave["device_error"] == 0, r_wave
     assert r_wave["results"][0][1].tolist() == r_plain["results"][0][1].tolist()
     # the FP64 path cost: compensated per-leaf sums on the device, a plain sum in the model

@@ -186,3 +186,64 @@ def test_bf16_batched_equals_single(dtw):
         c1, p1, _ = dtw.align(Xs[b], Ys[b], precision="bf16", min_block=500)
         assert costs[b].item() == c1
         assert torch.equal(paths[b], p1)
+
+
+# ------------------------------------------------------------------ FP16 Gram form
+#
+# The same Gram form from frames rounded to fp16 (round to nearest even,
+# subnormals kept): eight times finer than bf16 at the same matrix-core rate;
+# gate: relative cost error <= 1e-5.
+
+FP16_REL_TOL = 1e-5
+
+
+def fp16_round(a):
+    """Round to fp16 (nearest even, subnormals kept) through FP32, as the input staging does."""
+    return np.ascontiguousarray(a, dtype=np.float32).astype(np.float16).astype(np.float64)
+
+
+@pytest.mark.parametrize("M,N", [(3000, 2500), (6000, 4800)])
+def test_fp16_embedding_d128(dtw, M, N):
+    X, Y = synth.make_pair(3, M + 1, M, N, 128, "embedding")
+    cost, path, st = dtw.align(dev(X), dev(Y), precision="fp16", min_block=500)
+    assert st["device_error"] == 0
+    p = path.cpu().numpy()
+    check_path(p, M, N)
+    c_ref, p_ref = oracle.full(X, Y)
+    assert abs(cost - oracle.path_cost(X, Y, p)) <= 1e-12 * c_ref
+    rel = (cost - c_ref) / c_ref
+    assert -1e-12 <= rel <= FP16_REL_TOL, rel
+    dv = metrics.summary(p, p_ref)
+    print(f"fp16 M={M} N={N}: rel cost err {rel:.2e}, frame deviation mean {dv['mean_frames']:.3f} "
+          f"max {dv['max_frames']}")
+
+
+@pytest.mark.parametrize("scale", [1.0, 3e-4])
+def test_fp16_sweep_band_against_gram_reference(dtw, scale):
+    # one sweep in the FP16 Gram form against an FP64 DP on the Gram costs of
+    # the fp16-rounded frames; scale 3e-4 puts most elements in fp16's
+    # subnormal range
+    M, N, d = 260, 300, 128
+    X, Y = synth.make_pair(3, 78, M, N, d, "embedding")
+    X, Y = X * scale, Y * scale
+    Xr, Yr = fp16_round(X), fp16_round(Y)
+    nx = (Xr * Xr).sum(1)
+    ny = (Yr * Yr).sum(1)
+    C = np.sqrt(np.maximum(nx[:, None] + ny[None, :] - 2.0 * Xr @ Yr.T, 0.0))
+    F = np.full((M, N), np.inf)
+    for i in range(M):
+        for j in range(N):
+            if i == 0 and j == 0:
+                F[0, 0] = C[0, 0]
+                continue
+            best = min(F[i - 1, j - 1] if i and j else np.inf, F[i - 1, j] if i else np.inf,
+                       F[i, j - 1] if j else np.inf)
+            F[i, j] = best + C[i, j]
+    K = M + N - 1
+    kstop = (K + 1) // 2
+    got = dtw.diag(dev(X), dev(Y), 0, 0, M - 1, N - 1, 0, kstop, precision="fp16").cpu().numpy()
+    for q in range(3):
+        k = kstop - 2 + q
+        for a in range(max(0, k - N + 1), min(M - 1, k) + 1):
+            ref = F[a, k - a]
+            assert abs(got[q, a] - ref) <= 2e-5 * ref, (q, a, got[q, a], ref)

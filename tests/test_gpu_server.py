@@ -108,8 +108,8 @@ def test_poll_busy_then_done_and_errors(dtw):
         with pytest.raises(dtw.DtwError) as e:
             srv.submit(dev(big[0], torch.float64), dev(big[1], torch.float64))
         assert e.value.status == -3
-        # d beyond the FP64 form
-        Z = torch.zeros((10, 64), dtype=torch.float64, device="cuda")
+        # d beyond the widest frame form
+        Z = torch.zeros((10, 129), dtype=torch.float64, device="cuda")
         with pytest.raises(dtw.DtwError) as e:
             srv.submit(Z, Z)
         assert e.value.status == -8
