@@ -456,6 +456,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >
             up_prev = up;
             if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
               hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
+              __builtin_amdgcn_wave_barrier();  // lane 63's value read by lane 48 + (t & 15), see the leaf
               if (has_succ) publish<T>(t, lane, hist, ring_out, pub_max);
             }
           }
@@ -673,6 +674,10 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
         }
         if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
           hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
+          // at a last step inside a group, lane 48 + (t & 15) reads what lane
+          // 63 has just written: LDS operations of one wave are in order, and
+          // this keeps the compiler from reordering them
+          __builtin_amdgcn_wave_barrier();
           if (has_succ) leaf_publish<T>(t, lane, hist, brow, S.Cc);
         }
       }
