@@ -204,35 +204,38 @@ def bench_batched(args):
     from paper_2008_02734_amd import dtw, synth
 
     shapes = synth.batch_shapes(args.batch)
-    d = 24
+    d = args.batch_d
     Xs, Ys = [], []
     for p, (M, N) in enumerate(shapes):
         X, Y = synth.make_pair(4, p, M, N, d, "chroma")
         Xs.append(X.astype(np.float32))
         Ys.append(Y.astype(np.float32))
-    Xp = torch.from_numpy(np.concatenate(Xs)).to("cuda:0")
-    Yp = torch.from_numpy(np.concatenate(Ys)).to("cuda:0")
+    prec = args.precision or "fp32"
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    Xp = torch.from_numpy(np.concatenate(Xs)).to("cuda:0", tdt)
+    Yp = torch.from_numpy(np.concatenate(Ys)).to("cuda:0", tdt)
     xo = np.concatenate([[0], np.cumsum([s[0] for s in shapes])]).astype(np.int64)
     yo = np.concatenate([[0], np.cumsum([s[1] for s in shapes])]).astype(np.int64)
     Xl = [Xp[xo[i]:xo[i + 1]] for i in range(len(shapes))]
     Yl = [Yp[yo[i]:yo[i + 1]] for i in range(len(shapes))]
-    runner = dtw.BatchAligner(Xl, Yl, precision="fp32", min_block=500, profile=True)
+    runner = dtw.BatchAligner(Xl, Yl, precision=prec, min_block=500, profile=True)
     ms, lat, stats = timed_steps(runner.run, args.steps, args.warmup)
     st = stats[-1]
     assert all(s["device_error"] == 0 for s in stats), st
     cells = sum(M * N for M, N in shapes)
-    out = base_record(args, cells / (ms * 1e-3) / 1e9, ms, "f32",
+    form = "FP32 DP, FP64 split" if prec == "fp32" else prec.upper() + " DP and split"
+    out = base_record(args, cells / (ms * 1e-3) / 1e9, ms, {"fp32": "f32", "fp64": "f64"}[prec],
                       {"workload": f"batch of {len(shapes)} pairs, M,N log-uniform in [1000, 30000], N/M in "
-                                   "[0.7, 1.4], d=24 f32 chroma-like, FP32 DP, FP64 split (m=500)",
-                       "pairs": len(shapes), "d": d, "min_block": 500, "precision": "fp32", "seed": [4, "p"]})
+                                   f"[0.7, 1.4], d={d} f32 chroma-like, {form} (m=500)",
+                       "pairs": len(shapes), "d": d, "min_block": 500, "precision": prec, "seed": [4, "p"]})
     out.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "cells_processed": st["cells_processed"],
                 "processed_gcups": st["cells_processed"] / (ms * 1e-3) / 1e9,
                 "kernel_ms": {k: float(np.mean([s[k] for s in stats])) for k in
                               ("ms_sweep", "ms_split", "ms_plan", "ms_leaf", "ms_other")},
                 "levels": st["levels"], "leaves": st["leaves"],
-                "roofline": roofline(stats, "fp32", d, "pass_kernel<float,24> (wavefront sweep)")})
-    if not args.no_fp64_comparison:
+                "roofline": roofline(stats, prec, d, f"pass_kernel<{'double' if prec == 'fp64' else 'float'},{d}> (wavefront sweep)")})
+    if not args.no_fp64_comparison and prec != "fp64":
         from paper_2008_02734_amd import metrics
         r64 = dtw.BatchAligner([x.to(torch.float64) for x in Xl], [y.to(torch.float64) for y in Yl],
                                precision="fp64", min_block=500)
@@ -380,6 +383,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--batch", type=int, default=512, help="pairs of the batched workload (config 4)")
+    ap.add_argument("--batch-d", type=int, default=24, help="frame width of the batched workload (config 4)")
     ap.add_argument("--requests", type=int, default=96, help="requests of the serving stream (config 5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "fp16"], default=None,

@@ -79,6 +79,37 @@ __device__ __forceinline__ void frame_cost2(const T (&x)[D], const T* __restrict
   c1 = sqrt_t(s1);
 }
 
+// The same two costs with the Y frames in LDS (broadcast reads), KC
+// dimensions at a time: the scheduling barrier keeps the compiler from
+// hoisting every read ahead of the arithmetic, which would hold 2D values in
+// registers; the other producer waves on the SIMD cover the read latency.
+template <typename T, int D>
+__device__ __forceinline__ void frame_cost2_lds(const T (&x)[D], const T* __restrict__ y0, const T* __restrict__ y1,
+                                                T& c0, T& c1) {
+  constexpr int KC = D >= 24 ? 2 : 4;
+  static_assert(D % KC == 0, "narrow frame widths are multiples of 4");
+  T s0 = T(0), s1 = T(0);
+#pragma unroll
+  for (int k0 = 0; k0 < D; k0 += KC) {
+    T a[KC], b[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      a[q] = y0[k0 + q];
+      b[q] = y1[k0 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      const T e0 = x[k0 + q] - a[q];
+      const T e1 = x[k0 + q] - b[q];
+      s0 = fma_t(e0, e0, s0);
+      s1 = fma_t(e1, e1, s1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  c0 = sqrt_t(s0);
+  c1 = sqrt_t(s1);
+}
+
 // Frame widths of 64 and more: the lane's frame xl is read in chunks of 16
 // dimensions (from LDS in the sweep, where the stripe's frames are staged, or
 // from HBM in the leaf) and each chunk serves four wave-uniform Y frames, so
@@ -91,7 +122,7 @@ __device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const
   constexpr int KC = 16;
   static_assert(D % KC == 0, "wide frame widths are multiples of 16");
   T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll 2
+#pragma unroll 1
   for (int kc = 0; kc < D; kc += KC) {
     T xc[KC];
 #pragma unroll
@@ -211,15 +242,16 @@ __device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_
 }
 
 // Publish lane 63's values of the steps g0..t (g0 = t rounded down to a
-// multiple of kPubGroup) from the LDS history: lane 48+u stores step g0+u,
-// i.e. column g0 + u - 63 of the stripe's bottom row.
+// multiple of kPubGroup) from the LDS history of lane 63 (`hist63[step & 15]`,
+// written by lane 63 alone): lane 48+u stores step g0+u, i.e. column
+// g0 + u - 63 of the stripe's bottom row.
 template <typename T>
-__device__ __forceinline__ void publish(int t, int lane, const T* hist, typename RingWord<T>::U* ring_out,
+__device__ __forceinline__ void publish(int t, int lane, const T* hist63, typename RingWord<T>::U* ring_out,
                                         int pub_max) {
   const int st = (t & ~(kPubGroup - 1)) + (lane - (kWave - kPubGroup));
   const int col = st - (kWave - 1);
   if (lane >= kWave - kPubGroup && st <= t && col >= 0 && col <= pub_max) {
-    const T v = hist[(st & (kPubGroup - 1)) * kWave + (kWave - 1)];
+    const T v = hist63[st & (kPubGroup - 1)];
     __hip_atomic_store(ring_out + col, __builtin_bit_cast(typename RingWord<T>::U, v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -313,15 +345,21 @@ template <int CM>
 __device__ __forceinline__ void gram_stage_barrier() {
   stage_barrier<is_gram(CM)>();
 }
-template <int CM, int D>
-constexpr bool kPassStagesRows = is_gram(CM) || (D >= 64);
+// FP64 Euclidean sweeps at frame widths up to 32 stage the Y frames of each
+// phase in LDS, one phase ahead, with vector loads: their scalar loads would
+// wait on L2 once per frame chunk, which is slow when the workgroups of a
+// batch read frames of many different pairs.
+template <typename T, int CM, int D>
+constexpr bool kStageY = (sizeof(T) == 8) && (CM == kCostEuclid) && (D <= 32);
+template <typename T, int CM, int D>
+constexpr bool kPassStagesRows = is_gram(CM) || (D >= 64) || kStageY<T, CM, D>;
 
 template <typename T, int D, int CM>
-__global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >= 64 && sizeof(T) == 8) ? 3 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+__global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
-  __shared__ T hist[kPubGroup * kWave];   // recurrence values of the last steps, [step & 15][lane]
+  __shared__ T hist[kPubGroup];           // lane 63's recurrence values of the last steps, [step & 15]
   __shared__ T bring[2 * kPhase];         // bottom row of the stripe above, [column & 63]
   __shared__ int sh_ticket;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -384,7 +422,8 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >
       const int t_band = min(n_steps, max(0, P.kstop - a0 - 2));
       T f = INF;                                          // own F(a, b-1)
       T up_prev = (s == 0 && lane == 0) ? T(0) : INF;     // F(a-1, b-1)
-      stage_barrier<kPassStagesRows<CM, D>>();
+      T* const h63 = hist + in_vgpr(0);                    // one base register, slot offsets as immediates
+      stage_barrier<kPassStagesRows<T, CM, D>>();
       lds_barrier();  // phase -1: first costs and boundary chunk
       for (int k = 0; k < n_phases; ++k) {
         const int t0 = k * kPhase;
@@ -414,12 +453,12 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >
               // the history takes the previous step's value, off this
               // step's dependency chain; a group's last value is written
               // and the group published at once, ahead of the barrier
-              if ((u & (kPubGroup - 1)) != 0) hist[((u - 1) & (kPubGroup - 1)) * kWave + lane] = f;
+              if ((u & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(u - 1) & (kPubGroup - 1)] = f;
               const T up = wave_shr1(bb[g & 1][i], f);
               f = min_t(min_t(up_prev, f), up) + cb[g & 1][i];
               up_prev = up;
               if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
-                hist[(kPubGroup - 1) * kWave + lane] = f;
+                if (lane == kWave - 1) h63[kPubGroup - 1] = f;
                 if (has_succ) publish<T>(t0 + u, lane, hist, ring_out, pub_max);
               }
             }
@@ -429,7 +468,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >
           for (int t = t0; t < t1; ++t) {
             const int u = t - t0;
             const int b = t - lane;
-            if ((t & (kPubGroup - 1)) != 0) hist[((t - 1) & (kPubGroup - 1)) * kWave + lane] = f;
+            if ((t & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(t - 1) & (kPubGroup - 1)] = f;
             const T c = cp[u * kWave];
             const T up = wave_shr1(bp[u], f);
             if (t < t_band) {
@@ -455,7 +494,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >
             }
             up_prev = up;
             if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
-              hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
+              if (lane == kWave - 1) h63[t & (kPubGroup - 1)] = f;
               __builtin_amdgcn_wave_barrier();  // lane 63's value read by lane 48 + (t & 15), see the leaf
               if (has_succ) publish<T>(t, lane, hist, ring_out, pub_max);
             }
@@ -504,9 +543,62 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >
           lds_barrier();
         }
       }
+    } else if (wave <= kProducers && kStageY<T, CM, D>) {
+      // ------------------------------------------------ frame costs, Y frames staged in LDS
+      if constexpr (kStageY<T, CM, D>) {
+        const int pw = wave - 1;
+        T x[D];
+        {
+          const int r = min(lane, Lr);  // lanes below the stripe's last row reuse it
+          const int gi = P.dir ? P.i1 - (a0 + r) : P.i0 + a0 + r;
+          const T* xr = X + (int64_t)gi * D;
+#pragma unroll
+          for (int q = 0; q < D; ++q) x[q] = xr[q];
+        }
+        // ys[p & 1] holds the frames of phase p's 32 columns (clamped at
+        // need_max), written at iteration p - 2 from loads issued at p - 3
+        constexpr int CPF = D * (int)sizeof(T) / 16;  // 16-byte chunks per frame
+        static_assert(kPhase * CPF <= kProducers * kWave, "one chunk per producer lane");
+        __shared__ __align__(16) T ys[2][kPhase * D];
+        const int pl = pw * kWave + lane;
+        uint4 pend = {0u, 0u, 0u, 0u};
+        auto fetch = [&](int ph) {
+          const int cb = ph * kPhase;
+          if (pl < kPhase * CPF && cb <= need_max) {
+            const int jc = min(cb + pl / CPF, need_max);
+            const int gj = P.dir ? P.j1 - jc : P.j0 + jc;
+            pend = *reinterpret_cast<const uint4*>(Y + (int64_t)gj * D + (pl % CPF) * (16 / (int)sizeof(T)));
+          }
+        };
+        auto stash = [&](int ph) {
+          if (pl < kPhase * CPF && ph * kPhase <= need_max)
+            *reinterpret_cast<uint4*>(&ys[ph & 1][0] + pl * (16 / (int)sizeof(T))) = pend;
+        };
+        fetch(0);
+        stash(0);
+        fetch(1);
+        lds_barrier();  // phase 0's frames visible (matched by stage_barrier in the other waves)
+        for (int k = -1; k < n_phases; ++k) {
+          const int c0 = (k + 1) * kPhase;
+          if (c0 <= need_max) {
+            const T* yb = &ys[(k + 1) & 1][0];
+#pragma unroll
+            for (int i = 0; i < kPhase / kProducers; i += 2) {
+              const int jj0 = pw + i * kProducers, jj1 = jj0 + kProducers;
+              T cv0, cv1;
+              frame_cost2_lds<T, D>(x, yb + jj0 * D, yb + jj1 * D, cv0, cv1);
+              cring[((c0 + jj0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
+              cring[((c0 + jj1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
+            }
+          }
+          stash(k + 2);  // into the buffer of phase k, last read before the previous barrier
+          fetch(k + 3);
+          lds_barrier();
+        }
+      }
     } else if (wave <= kProducers) {
       // ------------------------------------------------ frame costs
-      if constexpr (D < 64) {
+      if constexpr (D < 64 && !kStageY<T, CM, D>) {
         const int pw = wave - 1;
         T x[D];
         {
@@ -538,7 +630,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : D == 32 ? 4 : (D >
       }
     } else {
       // ------------------------------------------------ boundary input
-      stage_barrier<kPassStagesRows<CM, D>>();
+      stage_barrier<kPassStagesRows<T, CM, D>>();
       uint32_t* gen_out = w.gens + P.gen_off + s % kRing;
       uint32_t* gen_in = w.gens + P.gen_off + (s + kRing - 1) % kRing;
       if (has_pred) (void)poll_cell<uint32_t>(gen_in, my_tag - 1u, w, true);
@@ -593,11 +685,11 @@ struct LeafShape {
 // Lane 48+u stores step g0+u's value of lane 63 (column g0+u-63 of the
 // stripe's bottom row), g0 = t rounded down to a multiple of kPubGroup.
 template <typename T>
-__device__ __forceinline__ void leaf_publish(int t, int lane, const T* hist, T* brow, int Cc) {
+__device__ __forceinline__ void leaf_publish(int t, int lane, const T* hist63, T* brow, int Cc) {
   const int st = (t & ~(kPubGroup - 1)) + (lane - (kWave - kPubGroup));
   const int col = st - (kWave - 1);
   if (lane >= kWave - kPubGroup && st <= t && col >= 0 && col < Cc)
-    brow[col] = hist[(st & (kPubGroup - 1)) * kWave + (kWave - 1)];
+    brow[col] = hist63[st & (kPubGroup - 1)];
 }
 
 // One step of the leaf recurrence with its backpointer code.
@@ -624,6 +716,7 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
   T f = INF;
   T up_prev = (sw == 0 && lane == 0) ? T(0) : INF;
   uint32_t word = 0;
+  T* const h63 = hist + in_vgpr(0);  // one base register, slot offsets as immediates
   lds_barrier();  // phase -1
   for (int k = 0; k < n_phases; ++k) {
     const int t0 = k * kPhase;
@@ -651,14 +744,14 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
           const int u = g * G + i;
           // history as in the pass kernel: previous value off the chain,
           // a group's last value written and published at once
-          if ((u & (kPubGroup - 1)) != 0) hist[((u - 1) & (kPubGroup - 1)) * kWave + lane] = f;
+          if ((u & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(u - 1) & (kPubGroup - 1)] = f;
           leaf_step<T, TR>(cb[g & 1][i], bb[g & 1][i], f, up_prev, word, u);
           if ((u & 15) == 15) {
             bpst[((t0 + u) >> 4) * kWave + lane] = word;
             word = 0u;
           }
           if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
-            hist[(kPubGroup - 1) * kWave + lane] = f;
+            if (lane == kWave - 1) h63[kPubGroup - 1] = f;
             if (has_succ) leaf_publish<T>(t0 + u, lane, hist, brow, S.Cc);
           }
         }
@@ -666,14 +759,14 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
     } else {
       for (int t = t0; t < n_steps; ++t) {
         const int u = t - t0;
-        if ((t & (kPubGroup - 1)) != 0) hist[((t - 1) & (kPubGroup - 1)) * kWave + lane] = f;
+        if ((t & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(t - 1) & (kPubGroup - 1)] = f;
         leaf_step<T, TR>(cp[u * kWave], bp[u], f, up_prev, word, t);
         if ((t & 15) == 15 || t == n_steps - 1) {
           bpst[(t >> 4) * kWave + lane] = word;
           word = 0u;
         }
         if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
-          hist[(t & (kPubGroup - 1)) * kWave + lane] = f;
+          if (lane == kWave - 1) h63[t & (kPubGroup - 1)] = f;
           // at a last step inside a group, lane 48 + (t & 15) reads what lane
           // 63 has just written: LDS operations of one wave are in order, and
           // this keeps the compiler from reordering them
@@ -811,7 +904,7 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     const void* Yorig, int in_f64, int d) {
   extern __shared__ __align__(16) unsigned char lds_raw[];  // pointers and bottom row when they fit
   __shared__ T cring[kCostRing * kWave];
-  __shared__ T hist[kPubGroup * kWave];
+  __shared__ T hist[kPubGroup];  // lane 63's recurrence values of the last steps
   __shared__ T bring[2 * kPhase];
   __shared__ int sh_ticket;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));

@@ -48,6 +48,7 @@ inline int cpu_update_dpp(int old, int src, int ctrl) {
 #define __builtin_amdgcn_s_waitcnt(x) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_wave_barrier() cpu_wave_barrier->arrive_and_wait()
 #define __builtin_amdgcn_s_setprio(n) ((void)0)
+#define __builtin_amdgcn_sched_barrier(n) ((void)0)
 
 template <class T> inline T __shfl(T v, int src) { return cpu_wave_exchange(v, src); }
 template <class T> inline T __shfl_xor(T v, int mask) { return cpu_wave_exchange(v, cpu_lane() ^ mask); }
