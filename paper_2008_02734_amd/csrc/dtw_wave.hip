@@ -242,16 +242,18 @@ __device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_
 }
 
 // Publish lane 63's values of the steps g0..t (g0 = t rounded down to a
-// multiple of kPubGroup) from the LDS history of lane 63 (`hist63[step & 15]`,
-// written by lane 63 alone): lane 48+u stores step g0+u, i.e. column
-// g0 + u - 63 of the stripe's bottom row.
+// multiple of kPubGroup): lane 48+u stores step g0+u, i.e. column g0 + u - 63
+// of the stripe's bottom row.  The values are read from the cost ring: after
+// the recurrence has read the cost of step s from slot s it writes its value
+// of step s into that slot, which the producers do not write again before
+// the phase's closing barrier.
 template <typename T>
-__device__ __forceinline__ void publish(int t, int lane, const T* hist63, typename RingWord<T>::U* ring_out,
+__device__ __forceinline__ void publish(int t, int lane, const T* cring, typename RingWord<T>::U* ring_out,
                                         int pub_max) {
   const int st = (t & ~(kPubGroup - 1)) + (lane - (kWave - kPubGroup));
   const int col = st - (kWave - 1);
   if (lane >= kWave - kPubGroup && st <= t && col >= 0 && col <= pub_max) {
-    const T v = hist63[st & (kPubGroup - 1)];
+    const T v = cring[(st & (kCostRing - 1)) * kWave + (kWave - 1)];
     __hip_atomic_store(ring_out + col, __builtin_bit_cast(typename RingWord<T>::U, v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -359,7 +361,6 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
                                                             int level) {
   using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
-  __shared__ T hist[kPubGroup];           // lane 63's recurrence values of the last steps, [step & 15]
   __shared__ T bring[2 * kPhase];         // bottom row of the stripe above, [column & 63]
   __shared__ int sh_ticket;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -422,12 +423,12 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
       const int t_band = min(n_steps, max(0, P.kstop - a0 - 2));
       T f = INF;                                          // own F(a, b-1)
       T up_prev = (s == 0 && lane == 0) ? T(0) : INF;     // F(a-1, b-1)
-      T* const h63 = hist + in_vgpr(0);                    // one base register, slot offsets as immediates
       stage_barrier<kPassStagesRows<T, CM, D>>();
       lds_barrier();  // phase -1: first costs and boundary chunk
       for (int k = 0; k < n_phases; ++k) {
         const int t0 = k * kPhase;
-        const T* cp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
+        T* const hp = cring + (t0 & (kCostRing - 1)) * kWave + lane;  // the phase's slots, also the history
+        const T* cp = hp;
         const T* bp = bring + in_vgpr(t0 & (2 * kPhase - 1));
         if (t0 + kPhase <= t_band) {
           // operands of the next kStepGroup steps are read one group ahead
@@ -453,13 +454,13 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
               // the history takes the previous step's value, off this
               // step's dependency chain; a group's last value is written
               // and the group published at once, ahead of the barrier
-              if ((u & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(u - 1) & (kPubGroup - 1)] = f;
+              if ((u & (kPubGroup - 1)) != 0) hp[(u - 1) * kWave] = f;
               const T up = wave_shr1(bb[g & 1][i], f);
               f = min_t(min_t(up_prev, f), up) + cb[g & 1][i];
               up_prev = up;
               if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
-                if (lane == kWave - 1) h63[kPubGroup - 1] = f;
-                if (has_succ) publish<T>(t0 + u, lane, hist, ring_out, pub_max);
+                hp[u * kWave] = f;
+                if (has_succ) publish<T>(t0 + u, lane, cring, ring_out, pub_max);
               }
             }
           }
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
           for (int t = t0; t < t1; ++t) {
             const int u = t - t0;
             const int b = t - lane;
-            if ((t & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(t - 1) & (kPubGroup - 1)] = f;
+            if ((t & (kPubGroup - 1)) != 0) hp[(u - 1) * kWave] = f;
             const T c = cp[u * kWave];
             const T up = wave_shr1(bp[u], f);
             if (t < t_band) {
@@ -494,9 +495,9 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
             }
             up_prev = up;
             if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
-              if (lane == kWave - 1) h63[t & (kPubGroup - 1)] = f;
+              hp[u * kWave] = f;
               __builtin_amdgcn_wave_barrier();  // lane 63's value read by lane 48 + (t & 15), see the leaf
-              if (has_succ) publish<T>(t, lane, hist, ring_out, pub_max);
+              if (has_succ) publish<T>(t, lane, cring, ring_out, pub_max);
             }
           }
         }
@@ -671,7 +672,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
 // steps 16m..16m+15 (columns 16m-r..16m+15-r) in word ((st*Wm + m)*64 + r),
 // Wm = ceil((Cc+63)/16); all lanes store their word together every 16 steps.
 // The bottom row of a stripe reaches the next stripe through `brow`, written
-// from the recurrence values' LDS history every 16 steps, and the input wave
+// from the recurrence values kept in the cost ring every 16 steps, and the input wave
 // copies it into the boundary ring one phase ahead.  Lane 0 of the
 // recurrence wave then walks the pointers back from the block's last cell.
 // `bp` and `brow` point into LDS when the leaf fits there and into global
@@ -685,11 +686,11 @@ struct LeafShape {
 // Lane 48+u stores step g0+u's value of lane 63 (column g0+u-63 of the
 // stripe's bottom row), g0 = t rounded down to a multiple of kPubGroup.
 template <typename T>
-__device__ __forceinline__ void leaf_publish(int t, int lane, const T* hist63, T* brow, int Cc) {
+__device__ __forceinline__ void leaf_publish(int t, int lane, const T* cring, T* brow, int Cc) {
   const int st = (t & ~(kPubGroup - 1)) + (lane - (kWave - kPubGroup));
   const int col = st - (kWave - 1);
   if (lane >= kWave - kPubGroup && st <= t && col >= 0 && col < Cc)
-    brow[col] = hist63[st & (kPubGroup - 1)];
+    brow[col] = cring[(st & (kCostRing - 1)) * kWave + (kWave - 1)];
 }
 
 // One step of the leaf recurrence with its backpointer code.
@@ -708,19 +709,19 @@ __device__ __forceinline__ void leaf_step(T c, T bv, T& f, T& up_prev, uint32_t&
 
 template <typename T, bool TR>
 __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr, int n_steps, int n_phases,
-                                             bool has_succ, uint32_t* bpst, T* brow, const T* cring,
-                                             const T* bring, T* hist, int lane) {
+                                             bool has_succ, uint32_t* bpst, T* brow, T* cring,
+                                             const T* bring, int lane) {
   const T INF = inf_t<T>();
   // Unpredicated steps as in the pass kernel: +inf before a lane's row
   // starts, DIAG = 0 for the block's first cell.
   T f = INF;
   T up_prev = (sw == 0 && lane == 0) ? T(0) : INF;
   uint32_t word = 0;
-  T* const h63 = hist + in_vgpr(0);  // one base register, slot offsets as immediates
   lds_barrier();  // phase -1
   for (int k = 0; k < n_phases; ++k) {
     const int t0 = k * kPhase;
-    const T* cp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
+    T* const hp = cring + (t0 & (kCostRing - 1)) * kWave + lane;  // the phase's slots, also the history
+    const T* cp = hp;
     const T* bp = bring + in_vgpr(t0 & (2 * kPhase - 1));
     if (t0 + kPhase <= n_steps) {
       constexpr int G = kStepGroup;
@@ -744,34 +745,34 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
           const int u = g * G + i;
           // history as in the pass kernel: previous value off the chain,
           // a group's last value written and published at once
-          if ((u & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(u - 1) & (kPubGroup - 1)] = f;
+          if ((u & (kPubGroup - 1)) != 0) hp[(u - 1) * kWave] = f;
           leaf_step<T, TR>(cb[g & 1][i], bb[g & 1][i], f, up_prev, word, u);
           if ((u & 15) == 15) {
             bpst[((t0 + u) >> 4) * kWave + lane] = word;
             word = 0u;
           }
           if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
-            if (lane == kWave - 1) h63[kPubGroup - 1] = f;
-            if (has_succ) leaf_publish<T>(t0 + u, lane, hist, brow, S.Cc);
+            hp[u * kWave] = f;
+            if (has_succ) leaf_publish<T>(t0 + u, lane, cring, brow, S.Cc);
           }
         }
       }
     } else {
       for (int t = t0; t < n_steps; ++t) {
         const int u = t - t0;
-        if ((t & (kPubGroup - 1)) != 0 && lane == kWave - 1) h63[(t - 1) & (kPubGroup - 1)] = f;
+        if ((t & (kPubGroup - 1)) != 0) hp[(u - 1) * kWave] = f;
         leaf_step<T, TR>(cp[u * kWave], bp[u], f, up_prev, word, t);
         if ((t & 15) == 15 || t == n_steps - 1) {
           bpst[(t >> 4) * kWave + lane] = word;
           word = 0u;
         }
         if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
-          if (lane == kWave - 1) h63[t & (kPubGroup - 1)] = f;
+          hp[u * kWave] = f;
           // at a last step inside a group, lane 48 + (t & 15) reads what lane
           // 63 has just written: LDS operations of one wave are in order, and
           // this keeps the compiler from reordering them
           __builtin_amdgcn_wave_barrier();
-          if (has_succ) leaf_publish<T>(t, lane, hist, brow, S.Cc);
+          if (has_succ) leaf_publish<T>(t, lane, cring, brow, S.Cc);
         }
       }
     }
@@ -784,7 +785,7 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
 template <typename T, int D, int CM>
 __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* __restrict__ ColSrc,
                                         const float* __restrict__ RowN, const float* __restrict__ ColN,
-                                        const LeafShape& S, uint32_t* bp, T* brow, T* cring, T* bring, T* hist,
+                                        const LeafShape& S, uint32_t* bp, T* brow, T* cring, T* bring,
                                         int wave, int lane) {
   const T INF = inf_t<T>();
   T fend = T(0);
@@ -797,8 +798,8 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     if (wave == 0) {
       uint32_t* bpst = bp + (int64_t)(sw / kWave) * S.Wm * kWave;
       gram_stage_barrier<CM>();
-      fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane)
-                  : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, hist, lane);
+      fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, lane)
+                  : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, lane);
     } else if (wave <= kProducers && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
@@ -904,7 +905,6 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     const void* Yorig, int in_f64, int d) {
   extern __shared__ __align__(16) unsigned char lds_raw[];  // pointers and bottom row when they fit
   __shared__ T cring[kCostRing * kWave];
-  __shared__ T hist[kPubGroup];  // lane 63's recurrence values of the last steps
   __shared__ T bring[2 * kPhase];
   __shared__ int sh_ticket;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -955,12 +955,12 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
     if (Lf.scratch_off < 0) {
       uint32_t* bp = reinterpret_cast<uint32_t*>(lds_raw);
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
-                                  hist, wave, lane);
+                                  wave, lane);
       if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
     } else {
       uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
-                                  hist, wave, lane);
+                                  wave, lane);
       if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
     }
 
