@@ -260,14 +260,15 @@ __device__ __forceinline__ void publish(int t, int lane, const T* cring, typenam
 }
 
 // Gram-form producer (dtw_gram.h), BF16 frames for kBf16, else FP16.  At the
-// start of a stripe the eight producer waves copy its 64 16-bit X frames into LDS (rows padded by 16 bytes
-// so the operand reads of 16 lanes fall in distinct banks) and take one
-// barrier, which the other waves of the group match with gram_stage_barrier.
+// start of a stripe the NPW producer waves copy its 64 16-bit X frames into
+// LDS (rows padded by 16 bytes so the operand reads of 16 lanes fall in
+// distinct banks) and take one barrier, which the other waves of the group
+// match with stage_barrier.
 // The 64 x 32 cost block of a phase is two 32x32 tiles (stripe rows 0..31 and
-// 32..63); producer wave w (1..8) owns tile (w-1) & 1 of every fourth phase,
-// (w-1) >> 1 being its phase residue.  It issues the loads of its next
-// block's Y frames right after writing its current block, so they have
-// three phases to arrive, and at its phase it runs DP/16 matrix-core
+// 32..63); of the NPW producer waves, wave w owns tile (w-1) & 1 of every
+// (NPW/2)-th phase, (w-1) >> 1 being its phase residue.  It issues the loads
+// of its next block's Y frames right after writing its current block, so they
+// have NPW/2 - 1 phases to arrive, and at its phase it runs DP/16 matrix-core
 // operations (X operand read from LDS) and the FP32 epilogue
 // sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring.  The tile is formed
 // transposed (Y frames as the first operand): each lane's results then share
@@ -275,7 +276,7 @@ __device__ __forceinline__ void publish(int t, int lane, const T* cring, typenam
 // the ring at once.  Row r of the stripe is frame gi0 + gis*(a0 + r) of Xb,
 // column j is frame gj0 + gjs*j of Yb; rows past Lr reuse row Lr and columns
 // past need_max reuse column need_max.
-template <int DP, bool kBf16>
+template <int DP, bool kBf16, int NPW>
 __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, const uint16_t* __restrict__ Yb,
                                               const float* __restrict__ Xn, const float* __restrict__ Yn, int gi0,
                                               int gis, int gj0, int gjs, int a0, int Lr, int need_max, int n_phases,
@@ -283,9 +284,11 @@ __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, c
   constexpr int KB = DP / 16;
   constexpr int XS = DP + 8;  // LDS row stride of the staged frames, in bf16
   __shared__ __align__(16) uint16_t xs[kWave * XS];
-  __shared__ float ny_stage[kProducers][32];  // |y|^2 of a block's columns, per producer wave
+  static_assert(NPW % 2 == 0, "producer waves come in tile pairs");
+  constexpr int kRot = NPW / 2;                // a wave writes every kRot-th phase
+  __shared__ float ny_stage[NPW][32];          // |y|^2 of a block's columns, per producer wave
   const int pw = wave - 1;
-  for (int idx = pw * kWave + lane; idx < kWave * (DP / 8); idx += kProducers * kWave) {
+  for (int idx = pw * kWave + lane; idx < kWave * (DP / 8); idx += NPW * kWave) {
     const int r = idx / (DP / 8), c = idx % (DP / 8);
     const uint4 v = *reinterpret_cast<const uint4*>(Xb + (int64_t)(gi0 + gis * (a0 + min(r, Lr))) * DP + 8 * c);
     *reinterpret_cast<uint4*>(xs + r * XS + 8 * c) = v;
@@ -329,7 +332,7 @@ __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, c
         }
         __builtin_amdgcn_wave_barrier();
       }
-      kw += 4;
+      kw += kRot;
       issue(kw);
     }
     lds_barrier();
@@ -357,7 +360,7 @@ template <typename T, int CM, int D>
 constexpr bool kPassStagesRows = is_gram(CM) || (D >= 64) || kStageY<T, CM, D>;
 
 template <typename T, int D, int CM>
-__global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+__global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 5 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
@@ -503,13 +506,13 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
         }
         lds_barrier();
       }
-    } else if (wave <= kProducers && is_gram(CM)) {
+    } else if (wave <= pass_producers(CM) && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
-        gram_producer<D, CM == kCostGram>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
+        gram_producer<D, CM == kCostGram, pass_producers(CM)>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
                          P.dir ? P.i1 : P.i0, P.dir ? -1 : 1, P.dir ? P.j1 : P.j0, P.dir ? -1 : 1, a0, Lr,
                          need_max, n_phases, wave, lane, reinterpret_cast<float*>(cring));
-    } else if (wave <= kProducers && D >= 64) {
+    } else if (wave <= pass_producers(CM) && D >= 64) {
       // ------------------------------------------------ frame costs, wide frames
       if constexpr (D >= 64 && !is_gram(CM)) {
         // the stripe's frames in LDS, rows padded by 16 bytes (bank spread of the chunk reads)
@@ -544,7 +547,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
           lds_barrier();
         }
       }
-    } else if (wave <= kProducers && kStageY<T, CM, D>) {
+    } else if (wave <= pass_producers(CM) && kStageY<T, CM, D>) {
       // ------------------------------------------------ frame costs, Y frames staged in LDS
       if constexpr (kStageY<T, CM, D>) {
         const int pw = wave - 1;
@@ -597,7 +600,7 @@ __global__ __launch_bounds__(kPassThreads, (is_gram(CM) ? 5 : (D >= 32 && sizeof
           lds_barrier();
         }
       }
-    } else if (wave <= kProducers) {
+    } else if (wave <= pass_producers(CM)) {
       // ------------------------------------------------ frame costs
       if constexpr (D < 64 && !kStageY<T, CM, D>) {
         const int pw = wave - 1;
@@ -803,7 +806,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     } else if (wave <= kProducers && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
-        gram_producer<D, CM == kCostGram>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
+        gram_producer<D, CM == kCostGram, kProducers>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
                          ColN, S.r0 + sw, 1, S.c0, 1, 0, Lr, S.Cc - 1, n_phases, wave, lane,
                          reinterpret_cast<float*>(cring));
     } else if (wave <= kProducers && D >= 64) {
@@ -1049,10 +1052,10 @@ int pick_dgram(int d) {
 // VALU, or BF16 Gram costs on the matrix cores with the FP32 recurrence.
 hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
   if (w.precision == DTW_PREC_BF16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGram><<<grid, kPassThreads, 0, st>>>(
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGram><<<grid, pass_threads(kCostGram), 0, st>>>(
                                             nullptr, nullptr, w, level)))
   } else if (w.precision == DTW_PREC_FP16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGramF16><<<grid, kPassThreads, 0, st>>>(
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGramF16><<<grid, pass_threads(kCostGramF16), 0, st>>>(
                                             nullptr, nullptr, w, level)))
   } else if (w.precision == DTW_PREC_FP32) {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), (pass_kernel<float, D_, kCostEuclid><<<grid, kPassThreads, 0, st>>>(

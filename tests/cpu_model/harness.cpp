@@ -308,9 +308,9 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
 hipError_t launch_pass(const Work& w, int level, int, hipStream_t) {
   model_check_queue(w);
   if (w.precision == DTW_PREC_BF16_COST) {
-    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGram), [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
   } else if (w.precision == DTW_PREC_FP16_COST) {
-    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, level); })))
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGramF16), [&] { pass_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, level); })))
   } else if (w.precision == DTW_PREC_FP32) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, level); })))
   } else {
