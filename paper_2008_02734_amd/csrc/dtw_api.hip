@@ -404,8 +404,8 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
   PROF_TRY(prof, kProfOther, launch_init(w, st));
 
-  // resident sweep workgroups per CU: two of 10 waves, or three of the Gram form's 6
-  const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WG_PER_CU", is_gram_precision(opts.precision) ? 3 : 2));
+  // resident sweep workgroups per CU: two of 10 waves, or four of the Gram form's 4
+  const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WG_PER_CU", is_gram_precision(opts.precision) ? 4 : 2));
   const int comb_grid = I.cus * 4;
   const int64_t lds_leaf_bytes = I.leaf_dyn[f32 ? 1 : 0];
   for (int lvl = 0; lvl <= L.lmax; ++lvl) {
@@ -586,7 +586,7 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype, i
   DevInfo& I = dev_info();
   w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
   HIP_TRY(launch_diag(w, (int32_t)i0, (int32_t)j0, (int32_t)i1, (int32_t)j1, reverse ? 1 : 0, (int32_t)kstop,
-                      I.cus * (is_gram_precision(precision) ? 3 : 2), out, st));
+                      I.cus * (is_gram_precision(precision) ? 4 : 2), out, st));
   return DTW_OK;
 }
 

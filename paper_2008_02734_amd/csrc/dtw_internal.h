@@ -34,10 +34,10 @@ constexpr int kCostEuclid = 0;
 constexpr int kCostGram = 1;     // BF16 frames
 constexpr int kCostGramF16 = 2;  // FP16 frames
 constexpr bool is_gram(int cm) { return cm != kCostEuclid; }
-// Producer waves of a sweep workgroup: the Gram form needs only four (its
-// matrix-core tiles are cheap), which makes its workgroup 6 waves and lets
-// three workgroups share a CU; the Euclidean forms use eight.
-constexpr int pass_producers(int cm) { return is_gram(cm) ? 4 : kProducers; }
+// Producer waves of a sweep workgroup: the Gram form needs only two (its
+// matrix-core tiles are cheap), which makes its workgroup 4 waves and lets
+// four workgroups share a CU; the Euclidean forms use eight.
+constexpr int pass_producers(int cm) { return is_gram(cm) ? 2 : kProducers; }
 constexpr int pass_threads(int cm) { return kWave * (pass_producers(cm) + 2); }
 constexpr bool is_gram_precision(int p) { return p == DTW_PREC_BF16_COST || p == DTW_PREC_FP16_COST; }
 

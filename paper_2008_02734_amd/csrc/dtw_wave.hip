@@ -259,44 +259,57 @@ __device__ __forceinline__ void publish(int t, int lane, const T* cring, typenam
   }
 }
 
-// Gram-form producer (dtw_gram.h), BF16 frames for kBf16, else FP16.  At the
-// start of a stripe the NPW producer waves copy its 64 16-bit X frames into
-// LDS (rows padded by 16 bytes so the operand reads of 16 lanes fall in
-// distinct banks) and take one barrier, which the other waves of the group
-// match with stage_barrier.
-// The 64 x 32 cost block of a phase is two 32x32 tiles (stripe rows 0..31 and
-// 32..63); of the NPW producer waves, wave w owns tile (w-1) & 1 of every
-// (NPW/2)-th phase, (w-1) >> 1 being its phase residue.  It issues the loads
-// of its next block's Y frames right after writing its current block, so they
-// have NPW/2 - 1 phases to arrive, and at its phase it runs DP/16 matrix-core
-// operations (X operand read from LDS) and the FP32 epilogue
+// Gram-form producer (dtw_gram.h), BF16 frames for kBf16, else FP16.  The
+// X operand is either held in registers (kXRegs: each lane's slices of its
+// row's frame) or staged in LDS at the start of a stripe by the NPW producer
+// waves (rows padded by 16 bytes so the operand reads of 16 lanes fall in
+// distinct banks), behind one barrier that the other waves of the group
+// match with stage_barrier.  The 64 x 32 cost block of a phase is two 32x32
+// tiles (stripe rows 0..31 and 32..63); of the NPW producer waves, wave w
+// owns tile (w-1) & 1 of every (NPW/2)-th phase, (w-1) >> 1 being its phase
+// residue.  It issues the loads of its next block's Y frames right after
+// writing its current block, so they have the NPW/2 - 1 phases in between
+// plus the rest of the current one to arrive, and at its phase it runs
+// DP/16 matrix-core operations and the FP32 epilogue
 // sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring.  The tile is formed
 // transposed (Y frames as the first operand): each lane's results then share
 // one stripe row, and the 32 lanes of a half-wave write 32 distinct rows of
 // the ring at once.  Row r of the stripe is frame gi0 + gis*(a0 + r) of Xb,
 // column j is frame gj0 + gjs*j of Yb; rows past Lr reuse row Lr and columns
 // past need_max reuse column need_max.
-template <int DP, bool kBf16, int NPW>
+template <int DP, bool kBf16, int NPW, bool kXRegs>
 __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, const uint16_t* __restrict__ Yb,
                                               const float* __restrict__ Xn, const float* __restrict__ Yn, int gi0,
                                               int gis, int gj0, int gjs, int a0, int Lr, int need_max, int n_phases,
                                               int wave, int lane, float* cring) {
   constexpr int KB = DP / 16;
   constexpr int XS = DP + 8;  // LDS row stride of the staged frames, in bf16
-  __shared__ __align__(16) uint16_t xs[kWave * XS];
   static_assert(NPW % 2 == 0, "producer waves come in tile pairs");
   constexpr int kRot = NPW / 2;                // a wave writes every kRot-th phase
   __shared__ float ny_stage[NPW][32];          // |y|^2 of a block's columns, per producer wave
   const int pw = wave - 1;
-  for (int idx = pw * kWave + lane; idx < kWave * (DP / 8); idx += NPW * kWave) {
-    const int r = idx / (DP / 8), c = idx % (DP / 8);
-    const uint4 v = *reinterpret_cast<const uint4*>(Xb + (int64_t)(gi0 + gis * (a0 + min(r, Lr))) * DP + 8 * c);
-    *reinterpret_cast<uint4*>(xs + r * XS + 8 * c) = v;
-  }
   const int tile = pw & 1, res = pw >> 1;
   const int half = lane >> 5, l32 = lane & 31;
   const int row = tile * 32 + l32;  // stripe row of all of this lane's results
-  const float nx = Xn[gi0 + gis * (a0 + min(row, Lr))];
+  const int gi = gi0 + gis * (a0 + min(row, Lr));
+  const float nx = Xn[gi];
+  // the X operand: this lane's slices of its row's frame, in registers, or
+  // the stripe's frames staged in LDS by all producer waves
+  bf16x8_t Xo[kXRegs ? KB : 1];
+  const uint16_t* xrow = nullptr;
+  if constexpr (kXRegs) {
+    const uint16_t* xr = Xb + (int64_t)gi * DP + 8 * half;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) Xo[kb] = load_bf16x8(xr + 16 * kb);
+  } else {
+    __shared__ __align__(16) uint16_t xs[kWave * XS];
+    for (int idx = pw * kWave + lane; idx < kWave * (DP / 8); idx += NPW * kWave) {
+      const int r = idx / (DP / 8), c = idx % (DP / 8);
+      const uint4 v = *reinterpret_cast<const uint4*>(Xb + (int64_t)(gi0 + gis * (a0 + min(r, Lr))) * DP + 8 * c);
+      *reinterpret_cast<uint4*>(xs + r * XS + 8 * c) = v;
+    }
+    xrow = xs + row * XS + 8 * half;
+  }
   bf16x8_t Yo[KB];
   float ny_own = 0.0f;
   auto issue = [&](int kw) {  // loads of the block written at iteration kw
@@ -311,15 +324,17 @@ __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, c
   };
   int kw = res - 1;
   issue(kw);
-  lds_barrier();  // the staged frames are visible (matched by gram_stage_barrier)
-  const uint16_t* xrow = xs + row * XS + 8 * half;
+  if constexpr (!kXRegs) lds_barrier();  // the staged frames are visible (matched by stage_barrier)
   for (int k = -1; k < n_phases; ++k) {
     if (k == kw) {
       const int c0 = (k + 1) * kPhase;
       if (c0 <= need_max) {
         f32x16_t acc = f32x16_zero();
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) acc = mfma_16bit_32x32x16<kBf16>(Yo[kb], load_bf16x8(xrow + 16 * kb), acc);
+        for (int kb = 0; kb < KB; ++kb) {
+          if constexpr (kXRegs) acc = mfma_16bit_32x32x16<kBf16>(Yo[kb], Xo[kb], acc);
+          else acc = mfma_16bit_32x32x16<kBf16>(Yo[kb], load_bf16x8(xrow + 16 * kb), acc);
+        }
         // register q of this lane holds column 8*(q/4) + 4*half + q%4 of the block
         float* nys = ny_stage[pw];
         if (half == 0) nys[l32] = ny_own;
@@ -357,10 +372,10 @@ __device__ __forceinline__ void gram_stage_barrier() {
 template <typename T, int CM, int D>
 constexpr bool kStageY = (sizeof(T) == 8) && (CM == kCostEuclid) && (D <= 32);
 template <typename T, int CM, int D>
-constexpr bool kPassStagesRows = is_gram(CM) || (D >= 64) || kStageY<T, CM, D>;
+constexpr bool kPassStagesRows = (!is_gram(CM) && D >= 64) || kStageY<T, CM, D>;
 
 template <typename T, int D, int CM>
-__global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 5 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+__global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
@@ -509,7 +524,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 5 : (D >= 32 && si
     } else if (wave <= pass_producers(CM) && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
-        gram_producer<D, CM == kCostGram, pass_producers(CM)>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
+        gram_producer<D, CM == kCostGram, pass_producers(CM), true>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
                          P.dir ? P.i1 : P.i0, P.dir ? -1 : 1, P.dir ? P.j1 : P.j0, P.dir ? -1 : 1, a0, Lr,
                          need_max, n_phases, wave, lane, reinterpret_cast<float*>(cring));
     } else if (wave <= pass_producers(CM) && D >= 64) {
@@ -806,7 +821,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     } else if (wave <= kProducers && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
-        gram_producer<D, CM == kCostGram, kProducers>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
+        gram_producer<D, CM == kCostGram, kProducers, false>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
                          ColN, S.r0 + sw, 1, S.c0, 1, 0, Lr, S.Cc - 1, n_phases, wave, lane,
                          reinterpret_cast<float*>(cring));
     } else if (wave <= kProducers && D >= 64) {
