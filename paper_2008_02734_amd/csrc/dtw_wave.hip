@@ -114,15 +114,16 @@ __device__ __forceinline__ void frame_cost2_lds(const T (&x)[D], const T* __rest
 // dimensions (from LDS in the sweep, where the stripe's frames are staged, or
 // from HBM in the leaf) and each chunk serves four wave-uniform Y frames, so
 // register use stays bounded and every cost keeps the dimension order of
-// frame_cost.
-template <typename T, int D>
+// frame_cost.  kUnroll chunks are unrolled (the leaf, with more live state,
+// takes 1 to stay within its registers).
+template <typename T, int D, int kUnroll>
 __device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const T* __restrict__ y0,
                                                  const T* __restrict__ y1, const T* __restrict__ y2,
                                                  const T* __restrict__ y3, T (&c)[4]) {
   constexpr int KC = 16;
   static_assert(D % KC == 0, "wide frame widths are multiples of 16");
   T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll 1
+#pragma unroll kUnroll
   for (int kc = 0; kc < D; kc += KC) {
     T xc[KC];
 #pragma unroll
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
               gj[i] = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc : P.j0 + jc);
             }
             T cv[4];
-            frame_cost4_wide<T, D>(xl, Y + (int64_t)gj[0] * D, Y + (int64_t)gj[1] * D, Y + (int64_t)gj[2] * D,
+            frame_cost4_wide<T, D, 2>(xl, Y + (int64_t)gj[0] * D, Y + (int64_t)gj[1] * D, Y + (int64_t)gj[2] * D,
                                    Y + (int64_t)gj[3] * D, cv);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -836,7 +837,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
 #pragma unroll
             for (int i = 0; i < 4; ++i) gj[i] = __builtin_amdgcn_readfirstlane(S.c0 + min(cb0 + pw + i * kProducers, S.Cc - 1));
             T cv[4];
-            frame_cost4_wide<T, D>(xl, ColSrc + (int64_t)gj[0] * D, ColSrc + (int64_t)gj[1] * D,
+            frame_cost4_wide<T, D, 1>(xl, ColSrc + (int64_t)gj[0] * D, ColSrc + (int64_t)gj[1] * D,
                                    ColSrc + (int64_t)gj[2] * D, ColSrc + (int64_t)gj[3] * D, cv);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
