@@ -27,9 +27,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = full-rate VALU lane-slots/s
-# (FP64 and unpacked FP32 alike).
-VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# MI355X vector peaks: FP64 78.6 TFLOP/s = 256 CUs x 4 SIMD x 16 FMA lanes x
+# 2.4 GHz x 2 flop; FP32 157.3 TFLOP/s = 32 lanes per SIMD per cycle (the FP32
+# batch sweep retires 4.7e13 VALU lane-instructions/s, above the 16-lane rate,
+# so unpacked FP32 runs at that rate too).  Lane-slots/s per arithmetic type:
+VALU_SLOTS_PER_S = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 256 * 4 * 32 * 2.4e9}
 # Algorithmic VALU slots per DP cell (from the gfx950 ISA of the sweep kernel):
 #  FP64, d = 12: 12 subtract + 12 fma, 21 for the correctly rounded square root
 #    (18 instructions, v_rsq_f64 counted 4 as a quarter-rate transcendental),
@@ -90,7 +92,7 @@ def roofline(stats, precision, d, kernel, traffic=None):
     sweep_ms = float(np.mean([s["ms_sweep"] for s in stats]))
     st = stats[-1]
     achieved = st["sweep_cells"] / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
-    peak = VALU_SLOTS_PER_S / slots_per_cell(precision, d) / 1e9
+    peak = VALU_SLOTS_PER_S["f64" if precision == "fp64" else "f32"] / slots_per_cell(precision, d) / 1e9
     return {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak, "unit": "Gcells/s",
             "frac": (achieved / peak) if achieved else None, "traffic": traffic,
             "launches_per_step": st["levels"], "sweep_cells_per_step": st["sweep_cells"],

@@ -86,7 +86,7 @@ __device__ __forceinline__ void frame_cost2(const T (&x)[D], const T* __restrict
 template <typename T, int D>
 __device__ __forceinline__ void frame_cost2_lds(const T (&x)[D], const T* __restrict__ y0, const T* __restrict__ y1,
                                                 T& c0, T& c1) {
-  constexpr int KC = D >= 24 ? 2 : 4;
+  constexpr int KC = (sizeof(T) == 8 && D >= 24) ? 2 : 4;
   static_assert(D % KC == 0, "narrow frame widths are multiples of 4");
   T s0 = T(0), s1 = T(0);
 #pragma unroll
@@ -366,12 +366,12 @@ template <int CM>
 __device__ __forceinline__ void gram_stage_barrier() {
   stage_barrier<is_gram(CM)>();
 }
-// FP64 Euclidean sweeps at frame widths up to 32 stage the Y frames of each
-// phase in LDS, one phase ahead, with vector loads: their scalar loads would
-// wait on L2 once per frame chunk, which is slow when the workgroups of a
-// batch read frames of many different pairs.
+// Euclidean sweeps at frame widths up to 32 stage the Y frames of each phase
+// in LDS, one phase ahead, with vector loads: scalar loads would wait on L2
+// once per frame chunk, which is slow when the workgroups of a batch read
+// frames of many different pairs.
 template <typename T, int CM, int D>
-constexpr bool kStageY = (sizeof(T) == 8) && (CM == kCostEuclid) && (D <= 32);
+constexpr bool kStageY = (CM == kCostEuclid) && (D <= 32);
 template <typename T, int CM, int D>
 constexpr bool kPassStagesRows = (!is_gram(CM) && D >= 64) || kStageY<T, CM, D>;
 

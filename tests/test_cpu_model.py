@@ -159,6 +159,19 @@ def test_wave_model_matches_oracle(wave_exe, M, N, d, m):
     assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
+@pytest.mark.parametrize("M,N,d,m", [(70, 50, 12, 16), (90, 75, 24, 500), (80, 60, 4, 3), (60, 70, 100, 16)])
+def test_wave_model_fp32_form(model_exe, wave_exe, M, N, d, m):
+    # the real kernels in FP32 (staged Y frames for d <= 32, wide frames
+    # above): the same path as the plain model, which evaluates the same FP32
+    # costs and recurrence cell by cell
+    X, Y = synth.random_pair(8100 + M + N + d, M, N, d, "normal")
+    r_wave = run_model(wave_exe, [(X, Y)], m, precision=1)
+    r_plain = run_model(model_exe, [(X, Y)], m, precision=1)
+    assert r_wave["rc"] == 0 and r_wave["device_error"] == 0, r_wave
+    assert r_wave["results"][0][1].tolist() == r_plain["results"][0][1].tolist()
+    assert abs(r_wave["results"][0][0] - r_plain["results"][0][0]) <= 1e-12 * r_plain["results"][0][0]
+
+
 # ------------------------------------------------------------ BF16 Gram form
 
 BF16_REL_TOL = 1e-2
