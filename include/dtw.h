@@ -77,8 +77,10 @@ typedef struct dtw_opts {
                               valid range [3, 1024]: below 3 the recursion would not
                               terminate, above 1024 a leaf no longer fits one workgroup */
   int32_t validate_finite; /* nonzero: scan X and Y for NaN/Inf first (synchronises)    */
-  int32_t profile;         /* nonzero (with stats): time each kernel class with HIP events
-                              recorded on `stream` and report the sums in dtw_stats       */
+  int32_t profile;         /* with stats: 1 = time each kernel class with HIP events
+                              recorded on `stream` and report the sums in dtw_stats;
+                              2 = time the sweep launches only (ms_sweep; fewer events
+                              in the stream); 0 = no timing                              */
   int32_t reserved[4];     /* must be zero                                                */
 } dtw_opts;
 

@@ -251,13 +251,16 @@ constexpr int kProfEvents = 1024;
 
 struct Profiler {
   bool on = false;
+  bool sweep_only = false;  // profile = 2: the sweep launches only (fewer events in the stream)
+  bool rec = false;         // the current launch is being timed
   hipStream_t st = nullptr;
   hipEvent_t* ev = nullptr;
   int used = 0;
   int cls[kProfEvents / 2];
 
-  hipError_t init(bool enable, hipStream_t s) {
+  hipError_t init(bool enable, bool sweeps, hipStream_t s) {
     on = enable;
+    sweep_only = sweeps;
     st = s;
     if (!on) return hipSuccess;
     static hipEvent_t pools[64][kProfEvents];
@@ -275,12 +278,14 @@ struct Profiler {
     return hipSuccess;
   }
   hipError_t begin(int c) {
-    if (!on || used + 2 > kProfEvents) return hipSuccess;
+    rec = on && used + 2 <= kProfEvents && (!sweep_only || c == kProfSweep);
+    if (!rec) return hipSuccess;
     cls[used / 2] = c;
     return hipEventRecord(ev[used], st);
   }
   hipError_t end() {
-    if (!on || used + 2 > kProfEvents) return hipSuccess;
+    if (!rec) return hipSuccess;
+    rec = false;
     hipError_t e = hipEventRecord(ev[used + 1], st);
     used += 2;
     return e;
@@ -393,7 +398,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   }
 
   Profiler prof;
-  HIP_TRY(prof.init(opts.profile != 0 && stats != nullptr, st));
+  HIP_TRY(prof.init(opts.profile != 0 && stats != nullptr, opts.profile == 2, st));
   Work w = make_work(L, ws, d, m, opts.precision);
   if (device_error_word) *device_error_word = &w.ctl->error;
   w.X = X;

@@ -95,7 +95,7 @@ def make_opts(precision="fp64", min_block=500, validate_finite=False, profile=Fa
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.min_block = int(min_block)
     o.validate_finite = 1 if validate_finite else 0
-    o.profile = 1 if profile else 0
+    o.profile = int(profile) if not isinstance(profile, bool) else (1 if profile else 0)
     return o
 
 
