@@ -888,20 +888,27 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
   return fend;
 }
 
-// Backtrace by one lane from the block's last cell; cells are written
-// backwards from slot_end of the diagonal-indexed path scratch.  Returns the
-// number of cells written (the block's first cell only for the pair's first
-// leaf: otherwise it is the previous leaf's last cell).
+// Backtrace from the block's last cell by the whole recurrence wave in
+// lockstep: the walk's position and every pointer word are wave-uniform
+// (readfirstlane), so its arithmetic runs on the scalar unit and a step costs
+// about one load latency; lane 0 writes the cells, backwards from slot_end of
+// the diagonal-indexed path scratch.  Returns the number of cells written (the
+// block's first cell only for the pair's first leaf: otherwise it is the
+// previous leaf's last cell).
 __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShape& S, const LeafDesc& Lf,
-                                              const PairDesc& pd, int64_t slot_end, int2* tpath) {
+                                              const PairDesc& pd, int64_t slot_end, int2* tpath, int lane) {
+  const int R = __builtin_amdgcn_readfirstlane(S.R), Cc = __builtin_amdgcn_readfirstlane(S.Cc);
+  const int Wm = __builtin_amdgcn_readfirstlane(S.Wm);
+  const bool tr = __builtin_amdgcn_readfirstlane(S.tr ? 1 : 0) != 0;
+  const bool first = __builtin_amdgcn_readfirstlane(Lf.first) != 0;
+  const int oi = __builtin_amdgcn_readfirstlane((int)(Lf.i0 - pd.x_off));  // block origin in the pair
+  const int oj = __builtin_amdgcn_readfirstlane((int)(Lf.j0 - pd.y_off));
   int cnt = 0;
-  int ri = S.R - 1, cj = S.Cc - 1;
-  for (int guard = 0; guard < S.R + S.Cc; ++guard) {  // every step decrements ri or cj
+  int ri = R - 1, cj = Cc - 1;
+  for (int guard = 0; guard < R + Cc; ++guard) {  // every step decrements ri or cj
     const bool at_start = (ri == 0 && cj == 0);
-    if (!at_start || Lf.first) {
-      const int gi = S.tr ? (Lf.i0 + cj) : (Lf.i0 + ri);
-      const int gj = S.tr ? (Lf.j0 + ri) : (Lf.j0 + cj);
-      tpath[slot_end - cnt] = make_int2((int)(gi - pd.x_off), (int)(gj - pd.y_off));
+    if (!at_start || first) {
+      if (lane == 0) tpath[slot_end - cnt] = tr ? make_int2(oi + cj, oj + ri) : make_int2(oi + ri, oj + cj);
       ++cnt;
     }
     if (at_start) break;
@@ -909,11 +916,12 @@ __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShap
     if (cj == 0) { --ri; continue; }
     const int r = ri & (kWave - 1);
     const int t = cj + r;
-    const uint32_t wd = bp[((int64_t)(ri >> 6) * S.Wm + (t >> 4)) * kWave + r];
+    const uint32_t wd = (uint32_t)__builtin_amdgcn_readfirstlane((int)bp[((ri >> 6) * Wm + (t >> 4)) * kWave + r]);
     const uint32_t code = (wd >> (2 * (t & 15))) & 3u;
+    // code 0 DIAG; 1 UP and 2 LEFT in the block's own orientation, swapped when transposed
     if (code == 0u) { --ri; --cj; }
-    else if (code == 1u) { if (S.tr) --cj; else --ri; }
-    else { if (S.tr) --ri; else --cj; }
+    else if ((code == 1u) != tr) --ri;
+    else --cj;
   }
   return cnt;
 }
@@ -975,12 +983,12 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
       uint32_t* bp = reinterpret_cast<uint32_t*>(lds_raw);
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
                                   wave, lane);
-      if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
+      if (wave == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath, lane);
     } else {
       uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
                                   wave, lane);
-      if (wave == 0 && lane == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath);
+      if (wave == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath, lane);
     }
 
     if (wave == 0) {

@@ -193,6 +193,25 @@ def test_deterministic_repeats(dtw):
     assert torch.equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("profile", [1, 2])
+def test_profiling_modes_leave_results_unchanged(dtw, profile):
+    # HIP events around every launch (1) or around the sweep launches only (2)
+    X, Y = synth.make_pair(2, 6, 2000, 1700, 12, "chroma")
+    Xd, Yd = dev(X), dev(Y)
+    al = dtw.Aligner(2000, 1700, 12, torch.float64, "fp64", 64, device="cuda")
+    al.run(Xd, Yd)
+    c0, p0 = float(al.cost.item()), al.path[: int(al.plen.item())].clone()
+    al.opts.profile = profile
+    st = al.run(Xd, Yd, stats=True)
+    assert float(al.cost.item()) == c0 and torch.equal(al.path[: int(al.plen.item())], p0)
+    assert st["ms_sweep"] > 0.0
+    others = [st[k] for k in ("ms_split", "ms_plan", "ms_leaf", "ms_other")]
+    if profile == 2:
+        assert all(v == 0.0 for v in others), st
+    else:
+        assert all(v > 0.0 for v in others), st
+
+
 def test_batched_equals_single(dtw):
     shapes = [(300, 250), (64, 700), (1000, 900), (5, 5), (777, 600)]
     Xs, Ys = [], []

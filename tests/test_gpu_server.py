@@ -28,13 +28,13 @@ def dev(a, dtype):
 
 
 def mixed_requests(n, seed=5):
-    """Uneven lengths and the three precision forms, from the generators."""
+    """Uneven lengths and the four precision forms, from the generators."""
     rng = np.random.default_rng([5, 999, seed])
     reqs = []
     for r in range(n):
         M = int(np.exp(rng.uniform(np.log(200), np.log(4000))))
         N = int(M * rng.uniform(0.75, 1.3))
-        kind = r % 3
+        kind = r % 4
         if kind == 0:
             X, Y = synth.make_pair(5, r, M, N, 12, "chroma")
             reqs.append((dev(X, torch.float64), dev(Y, torch.float64), "fp64"))
@@ -43,12 +43,12 @@ def mixed_requests(n, seed=5):
             reqs.append((dev(X, torch.float32), dev(Y, torch.float32), "fp32"))
         else:
             X, Y = synth.make_pair(5, r, M, N, 128, "embedding")
-            reqs.append((dev(X, torch.float32), dev(Y, torch.float32), "bf16"))
+            reqs.append((dev(X, torch.float32), dev(Y, torch.float32), "bf16" if kind == 2 else "fp16"))
     return reqs
 
 
 def test_results_same_alone_and_in_the_mix(dtw):
-    reqs = mixed_requests(18)
+    reqs = mixed_requests(20)
     srv = dtw.Server(pool_bytes=256 << 20, max_slots=3, max_batch=4)
     try:
         tickets = [srv.submit(X, Y, precision=p, min_block=128) for X, Y, p in reqs]
