@@ -31,6 +31,22 @@ __device__ __forceinline__ float min_t(float a, float b) {
   return r;
 }
 
+// One unpredicated recurrence step, min(min(diag, left), up) + c, as a single
+// assembly group: v_min keeps its IEEE-mode NaN rule (the other operand), and
+// the compiler pads around one inline-assembly statement instead of three.
+__device__ __forceinline__ double step_t(double diag, double left, double up, double c) {
+  double r;
+  asm volatile("v_min_f64 %0, %1, %2\n\tv_min_f64 %0, %0, %3\n\tv_add_f64 %0, %0, %4"
+               : "=&v"(r) : "v"(diag), "v"(left), "v"(up), "v"(c));
+  return r;
+}
+__device__ __forceinline__ float step_t(float diag, float left, float up, float c) {
+  float r;
+  asm volatile("v_min_f32 %0, %1, %2\n\tv_min_f32 %0, %0, %3\n\tv_add_f32 %0, %0, %4"
+               : "=&v"(r) : "v"(diag), "v"(left), "v"(up), "v"(c));
+  return r;
+}
+
 template <typename T> __device__ __forceinline__ T inf_t();
 template <> __device__ __forceinline__ double inf_t<double>() { return __builtin_inf(); }
 template <> __device__ __forceinline__ float inf_t<float>() { return __builtin_inff(); }
@@ -475,7 +491,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
               // and the group published at once, ahead of the barrier
               if ((u & (kPubGroup - 1)) != 0) hp[(u - 1) * kWave] = f;
               const T up = wave_shr1(bb[g & 1][i], f);
-              f = min_t(min_t(up_prev, f), up) + cb[g & 1][i];
+              f = step_t(up_prev, f, up, cb[g & 1][i]);
               up_prev = up;
               if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
                 hp[u * kWave] = f;
@@ -492,7 +508,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
             const T c = cp[u * kWave];
             const T up = wave_shr1(bp[u], f);
             if (t < t_band) {
-              f = min_t(min_t(up_prev, f), up) + c;
+              f = step_t(up_prev, f, up, c);
             } else if (b >= 0 && b <= bmax) {
               const T diag = (b == 0) ? INF : up_prev;
               const T left = (b == 0) ? INF : f;

@@ -36,6 +36,14 @@ WAVE_EDITS = [
     ('asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));',
      "r = (a != a) ? b : ((b != b) ? a : ((b < a) ? b : a));"),
     ('asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));', "r = x;"),
+    ('asm volatile("v_min_f64 %0, %1, %2\\n\\tv_min_f64 %0, %0, %3\\n\\tv_add_f64 %0, %0, %4"\n'
+     '               : "=&v"(r) : "v"(diag), "v"(left), "v"(up), "v"(c));',
+     "{ const double m1 = (diag != diag) ? left : ((left != left) ? diag : ((left < diag) ? left : diag));"
+     " const double m2 = (m1 != m1) ? up : ((up != up) ? m1 : ((up < m1) ? up : m1)); r = m2 + c; }"),
+    ('asm volatile("v_min_f32 %0, %1, %2\\n\\tv_min_f32 %0, %0, %3\\n\\tv_add_f32 %0, %0, %4"\n'
+     '               : "=&v"(r) : "v"(diag), "v"(left), "v"(up), "v"(c));',
+     "{ const float m1 = (diag != diag) ? left : ((left != left) ? diag : ((left < diag) ? left : diag));"
+     " const float m2 = (m1 != m1) ? up : ((up != up) ? m1 : ((up < m1) ? up : m1)); r = m2 + c; }"),
     ('asm volatile("s_waitcnt lgkmcnt(0)\\n\\ts_barrier" ::: "memory");', "__syncthreads();"),
     ('asm volatile("s_waitcnt vmcnt(0)" ::: "memory");', "std::atomic_thread_fence(std::memory_order_seq_cst);"),
     ("extern __shared__ __align__(16) unsigned char lds_raw[];", "unsigned char* lds_raw = cpu_dynamic_lds;"),
