@@ -151,8 +151,8 @@ def test_model_batched(model_exe):
         assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
-WAVE_CASES = [(37, 29, 3, 3), (70, 50, 12, 16), (130, 90, 5, 3), (20, 300, 4, 16), (9, 9, 2, 500),
-              (90, 75, 64, 16), (70, 100, 100, 500), (80, 60, 128, 3)]
+WAVE_CASES = [(37, 29, 3, 3), (70, 50, 12, 16), (130, 90, 5, 8), (20, 300, 4, 16), (9, 9, 2, 500),
+              (90, 75, 64, 16), (70, 100, 100, 500), (80, 60, 128, 16)]
 
 
 @pytest.mark.parametrize("M,N,d,m", WAVE_CASES)
@@ -167,7 +167,7 @@ def test_wave_model_matches_oracle(wave_exe, M, N, d, m):
     assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
-@pytest.mark.parametrize("M,N,d,m", [(70, 50, 12, 16), (90, 75, 24, 500), (80, 60, 4, 3), (60, 70, 100, 16)])
+@pytest.mark.parametrize("M,N,d,m", [(70, 50, 12, 16), (90, 75, 24, 500), (80, 60, 4, 8), (60, 70, 100, 16)])
 def test_wave_model_fp32_form(model_exe, wave_exe, M, N, d, m):
     # the real kernels in FP32 (staged Y frames for d <= 32, wide frames
     # above): the same path as the plain model, which evaluates the same FP32

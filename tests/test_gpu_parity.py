@@ -98,7 +98,8 @@ ALIGN_CASES = [(s, M, N, d, m) for s, (M, N, d) in enumerate(
 HUNG_ON_GPU = {(0, 37, 29, 3, 3)}
 
 
-WIDE_CASES = [(700, 560, 64, 500), (650, 900, 100, 16), (1200, 1000, 128, 500), (129, 70, 128, 3)]
+WIDE_CASES = [(700, 560, 64, 500), (650, 900, 100, 16), (1200, 1000, 128, 500), (129, 70, 128, 3),
+              (2500, 2100, 12, 1024)]  # the largest cutoff the API accepts
 
 
 @pytest.mark.parametrize("M,N,d,m", WIDE_CASES)

@@ -247,3 +247,55 @@ def test_fp16_sweep_band_against_gram_reference(dtw, scale):
         for a in range(max(0, k - N + 1), min(M - 1, k) + 1):
             ref = F[a, k - a]
             assert abs(got[q, a] - ref) <= 2e-5 * ref, (q, a, got[q, a], ref)
+
+
+# ------------------------------------------------------------------ full-size workloads
+#
+# At the benchmark's sizes the oracle's full table is out of reach for the
+# 200000 x 160000 pair, so these check what holds at any size: a valid path,
+# its reported cost equal to the oracle's FP64 cost of that path, the exact
+# FP64 GPU path no more costly, and the precision form within its bound of
+# it.  The batch is checked pair by pair on the pairs the oracle can solve in
+# seconds.
+
+
+def test_long_pair_full_size_precision_forms(dtw):
+    X, Y = synth.make_pair(3, 0, 200000, 160000, 128, "embedding")
+    M, N = X.shape[0], Y.shape[0]
+    Xd, Yd = dev(X), dev(Y)  # FP64 inputs: every form's reported cost is on the same frames
+    c64, p64, st64 = dtw.align(Xd, Yd)
+    assert st64["device_error"] == 0
+    p64 = p64.cpu().numpy()
+    check_path(p64, M, N)
+    assert abs(c64 - oracle.path_cost(X, Y, p64)) <= 1e-12 * c64
+    for prec, tol in (("bf16", BF16_REL_TOL), ("fp16", FP16_REL_TOL)):
+        c, p, st = dtw.align(Xd, Yd, precision=prec)
+        assert st["device_error"] == 0
+        p = p.cpu().numpy()
+        check_path(p, M, N)
+        assert abs(c - oracle.path_cost(X, Y, p)) <= 1e-12 * c64
+        rel = (c - c64) / c64
+        assert -1e-12 <= rel <= tol, (prec, rel)
+        print(f"{prec} 200000x160000 d=128: rel cost err vs the FP64 path {rel:.2e}")
+
+
+def test_batch_full_size_fp32_sampled_against_oracle(dtw):
+    shapes = synth.batch_shapes(512)
+    Xs, Ys = [], []
+    for p, (M, N) in enumerate(shapes):
+        X, Y = synth.make_pair(4, p, M, N, 24, "chroma")
+        Xs.append(X)
+        Ys.append(Y)
+    costs, paths, st = dtw.align_batched([dev(X.astype(np.float32), torch.float32) for X in Xs],
+                                         [dev(Y.astype(np.float32), torch.float32) for Y in Ys], precision="fp32")
+    assert st["device_error"] == 0
+    costs = costs.cpu().numpy()
+    order = np.argsort([M * N for M, N in shapes])
+    for b in order[:12]:  # the smallest pairs: the oracle's table in well under a second each
+        Xr = Xs[b].astype(np.float32).astype(np.float64)
+        Yr = Ys[b].astype(np.float32).astype(np.float64)
+        c_ref, _ = oracle.full(Xr, Yr)
+        p = paths[b].cpu().numpy()
+        check_path(p, *shapes[b])
+        assert abs(costs[b] - oracle.path_cost(Xr, Yr, p)) <= 1e-12 * c_ref
+        assert -1e-12 <= (costs[b] - c_ref) / c_ref <= FP32_REL_TOL
