@@ -67,19 +67,9 @@ __device__ __forceinline__ float wave_shr1(float old, float v) {
 // Euclidean frame cost (Sec. 4.1): sum over t of fma(e, e, s), e = x_t - y_t,
 // in dimension order, then the square root.  Frames are zero-padded to D
 // dimensions; a padded dimension contributes fma(0, 0, s) = s exactly.  x is
-// the lane's own frame in registers; y is a wave-uniform frame (scalar loads).
-template <typename T, int D>
-__device__ __forceinline__ T frame_cost(const T (&x)[D], const T* __restrict__ y) {
-  T s = T(0);
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const T e = x[k] - y[k];
-    s = fma_t(e, e, s);
-  }
-  return sqrt_t(s);
-}
-
-// The same cost for two Y frames at once (each in the order above).
+// the lane's own frame in registers; y0 and y1 are wave-uniform frames (the
+// leaf reads them with scalar loads).  Two Y frames at once give two
+// independent fma chains.
 template <typename T, int D>
 __device__ __forceinline__ void frame_cost2(const T (&x)[D], const T* __restrict__ y0, const T* __restrict__ y1,
                                             T& c0, T& c1) {
@@ -130,7 +120,7 @@ __device__ __forceinline__ void frame_cost2_lds(const T (&x)[D], const T* __rest
 // dimensions (from LDS in the sweep, where the stripe's frames are staged, or
 // from HBM in the leaf) and each chunk serves four wave-uniform Y frames, so
 // register use stays bounded and every cost keeps the dimension order of
-// frame_cost.  kUnroll chunks are unrolled (the leaf, with more live state,
+// frame_cost2.  kUnroll chunks are unrolled (the leaf, with more live state,
 // takes 1 to stay within its registers).
 template <typename T, int D, int kUnroll>
 __device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const T* __restrict__ y0,
@@ -172,13 +162,16 @@ __device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const
 //               per step.  UP comes from lane r-1 through a DPP lane shift
 //               (lane 0: the bottom row of the stripe above), DIAG is the
 //               previous step's UP and LEFT the lane's own previous value.
-//   waves 1..8  frame costs (Sec. 4.1) of whole columns, one phase ahead of
-//               the recurrence, into an LDS ring.  A column's Y frame is
-//               wave-uniform and arrives through scalar loads; the lane's X
-//               frame stays in registers.
-//   wave 9      boundary input: the bottom row of the stripe above, read from
+//   producers   waves 1..pass_producers(CM): frame costs (Sec. 4.1) of whole
+//               columns, one phase ahead of the recurrence, into an LDS ring
+//               (Euclidean forms: eight waves, Y frames staged in LDS or read
+//               wave-uniformly, X frames in registers or LDS; Gram form: two
+//               waves with matrix-core tiles).
+//   last wave   boundary input: the bottom row of the stripe above, read from
 //               HBM one phase ahead into LDS.
-// Phases of kPhase steps are separated by workgroup barriers.
+// Phases of kPhase steps are separated by workgroup barriers.  The
+// recurrence also writes its value of step t into slot t of the cost ring
+// once it has read that slot's cost; the bottom row is published from there.
 //
 // Cost ring: lane r's cost for column j sits in slot (j + r) mod kCostRing,
 // so the recurrence reads slot t at step t (one address per step for the
@@ -629,38 +622,6 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
           }
           stash(k + 2);  // into the buffer of phase k, last read before the previous barrier
           fetch(k + 3);
-          lds_barrier();
-        }
-      }
-    } else if (wave <= pass_producers(CM)) {
-      // ------------------------------------------------ frame costs
-      if constexpr (D < 64 && !kStageY<T, CM, D>) {
-        const int pw = wave - 1;
-        T x[D];
-        {
-          const int r = min(lane, Lr);  // lanes below the stripe's last row reuse it
-          const int gi = P.dir ? P.i1 - (a0 + r) : P.i0 + a0 + r;
-          const T* xr = X + (int64_t)gi * D;
-  #pragma unroll
-          for (int q = 0; q < D; ++q) x[q] = xr[q];
-        }
-        for (int k = -1; k < n_phases; ++k) {
-          const int c0 = (k + 1) * kPhase;
-          if (c0 <= need_max) {
-            // two columns at a time: two independent fma chains per lane
-  #pragma unroll
-            for (int i = 0; i < kPhase / kProducers; i += 2) {
-              const int j0 = c0 + pw + i * kProducers, j1 = j0 + kProducers;
-              const int jc0 = min(j0, need_max), jc1 = min(j1, need_max);
-              const int gj0 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc0 : P.j0 + jc0);
-              const int gj1 = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc1 : P.j0 + jc1);
-              T cv0, cv1;
-              frame_cost2<T, D>(x, Y + (int64_t)gj0 * D, Y + (int64_t)gj1 * D, cv0, cv1);
-              // columns past need_max hold a clamped column's cost; nothing reads them
-              cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
-              cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
-            }
-          }
           lds_barrier();
         }
       }
