@@ -48,20 +48,29 @@ __device__ __forceinline__ double2 dd_add(double2 a, double2 b) {
 
 // ----------------------------------------------------------------- block scan
 
+// Exclusive prefix sum over the workgroup in thread order; *total = the sum.
+// Inclusive scan inside each wave by lane shuffles, wave totals through
+// tmp[0 .. waves-1], two workgroup barriers. Every thread of the workgroup
+// must call it; tmp may be reused as soon as it returns.
 __device__ int64_t block_excl_scan(int64_t v, int64_t* tmp, int64_t* total) {
   const int t = threadIdx.x, n = blockDim.x;
-  tmp[t] = v;
-  __syncthreads();
-  for (int off = 1; off < n; off <<= 1) {
-    const int64_t u = (t >= off) ? tmp[t - off] : 0;
-    __syncthreads();
-    tmp[t] += u;
-    __syncthreads();
+  const int lane = t & (kWave - 1), wv = t / kWave, nw = (n + kWave - 1) / kWave;
+  int64_t x = v;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int64_t u = __shfl(x, lane >= off ? lane - off : lane);
+    if (lane >= off) x += u;
   }
-  const int64_t incl = tmp[t];
-  *total = tmp[n - 1];
+  if (lane == kWave - 1 || t == n - 1) tmp[wv] = x;
   __syncthreads();
-  return incl - v;
+  int64_t before = 0, all = 0;
+  for (int k = 0; k < nw; ++k) {
+    const int64_t s = tmp[k];
+    if (k < wv) before += s;
+    all += s;
+  }
+  *total = all;
+  __syncthreads();
+  return before + x - v;
 }
 
 }  // namespace dtw

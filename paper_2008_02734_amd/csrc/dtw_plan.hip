@@ -262,10 +262,21 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
     if (n_tickets > w.caps.ticket) {
       if (tid == 0) set_error(ctl, kErrTicketCap);
     } else {
+      // a pass's stripes are written by one thread; the start offsets are
+      // read kTicketBatch at a time so that one load latency covers a batch
+      // (a long pass at the top level has hundreds of stripes)
+      constexpr int kTicketBatch = 16;
       for (int p = tid; p < n_pass; p += nt) {
         const int ns = w.passes[p].n_stripes;
         const int r = gt[ns] + atomicAdd(&eqc[ns], 1);
-        for (int s = 0; s < ns; ++s) w.tickets[start[s] + r] = make_int2(p, s);
+        for (int s0 = 0; s0 < ns; s0 += kTicketBatch) {
+          int32_t so[kTicketBatch];
+#pragma unroll
+          for (int k = 0; k < kTicketBatch; ++k) so[k] = (s0 + k < ns) ? start[s0 + k] : 0;
+#pragma unroll
+          for (int k = 0; k < kTicketBatch; ++k)
+            if (s0 + k < ns) w.tickets[so[k] + r] = make_int2(p, s0 + k);
+        }
       }
     }
     __syncthreads();
@@ -376,23 +387,38 @@ __global__ __launch_bounds__(1024) void scan_kernel(Work w, int32_t* poff, int32
   const PairDesc pd = w.pairs[p];
   const int64_t n = pd.M + pd.N - 1;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t per = (n + nt - 1) / nt;
-  const int64_t lo = min(n, tid * per), hi = min(n, lo + per);
-  int64_t local = 0;
+  // chunks of nt * kV diagonals; a thread owns kV consecutive ones, loaded
+  // together, and the block scan carries from chunk to chunk
+  constexpr int kV = 8;
   double2 acc = make_double2(0.0, 0.0);
   const int n_leaf = clamp_count(w.ctl, w.ctl->n_leaf, w.caps.leaf);
-  for (int64_t e = lo; e < hi; ++e) {
-    const int c = w.cnt[pd.pbase + e];
-    local += c;
-    const int l = lidx[pd.pbase + e];
-    if (c > 0 && l >= 0 && l < n_leaf) acc = dd_add(acc, w.leaf_cost[l]);
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)nt * kV) {
+    const int64_t lo = base + (int64_t)tid * kV;
+    int c[kV];
+    int64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      c[k] = (lo + k < n) ? w.cnt[pd.pbase + lo + k] : 0;
+      local += c[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      if (c[k] > 0) {
+        const int l = lidx[pd.pbase + lo + k];
+        if (l >= 0 && l < n_leaf) acc = dd_add(acc, w.leaf_cost[l]);
+      }
+    }
+    int64_t tot;
+    int64_t run = carry + block_excl_scan(local, tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      if (lo + k < n) poff[pd.pbase + lo + k] = (int32_t)run;
+      run += c[k];
+    }
+    carry += tot;
   }
-  int64_t total;
-  int64_t run = block_excl_scan(local, tmp, &total);
-  for (int64_t e = lo; e < hi; ++e) {
-    poff[pd.pbase + e] = (int32_t)run;
-    run += w.cnt[pd.pbase + e];
-  }
+  const int64_t total = carry;
   red[tid] = acc;
   __syncthreads();
   for (int off = nt / 2; off > 0; off >>= 1) {
