@@ -866,12 +866,14 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
 }
 
 // Backtrace from the block's last cell by the whole recurrence wave in
-// lockstep: the walk's position and every pointer word are wave-uniform
-// (readfirstlane), so its arithmetic runs on the scalar unit and a step costs
-// about one load latency; lane 0 writes the cells, backwards from slot_end of
-// the diagonal-indexed path scratch.  Returns the number of cells written (the
-// block's first cell only for the pair's first leaf: otherwise it is the
-// previous leaf's last cell).
+// lockstep, one row per iteration. The position is wave-uniform, so the
+// arithmetic runs on the scalar unit. In a row, the walk keeps moving along
+// the row up to the first cell (from the right) whose pointer is DIAG or
+// vertical: a bit scan over the row's packed 2-bit codes finds it, one word
+// of 16 steps at a time. The row's run of cells is then stored by the lanes
+// at once, backwards from slot_end of the diagonal-indexed path scratch.
+// Returns the number of cells written (the block's first cell only for the
+// pair's first leaf: otherwise it is the previous leaf's last cell).
 __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShape& S, const LeafDesc& Lf,
                                               const PairDesc& pd, int64_t slot_end, int2* tpath, int lane) {
   const int R = __builtin_amdgcn_readfirstlane(S.R), Cc = __builtin_amdgcn_readfirstlane(S.Cc);
@@ -880,26 +882,51 @@ __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShap
   const bool first = __builtin_amdgcn_readfirstlane(Lf.first) != 0;
   const int oi = __builtin_amdgcn_readfirstlane((int)(Lf.i0 - pd.x_off));  // block origin in the pair
   const int oj = __builtin_amdgcn_readfirstlane((int)(Lf.j0 - pd.y_off));
+  constexpr uint32_t kLo = 0x55555555u;  // bit 0 of every 2-bit field
   int cnt = 0;
   int ri = R - 1, cj = Cc - 1;
-  for (int guard = 0; guard < R + Cc; ++guard) {  // every step decrements ri or cj
-    const bool at_start = (ri == 0 && cj == 0);
-    if (!at_start || first) {
-      if (lane == 0) tpath[slot_end - cnt] = tr ? make_int2(oi + cj, oj + ri) : make_int2(oi + ri, oj + cj);
-      ++cnt;
+  // code 0 DIAG; 1 UP and 2 LEFT in the block's own orientation, swapped
+  // when transposed. A move along the row (cj - 1) is code 2 or 3, or code 1
+  // when transposed; field mask of the other codes:
+  //   not transposed: hi bit clear;  transposed: hi bit set or lo bit clear.
+  for (int guard = 0; guard < R && ri > 0; ++guard) {
+    const int r = ri & (kWave - 1), s = ri >> 6;
+    int t = cj + r;  // step of (ri, cj) in lane r's pointer words
+    int tx = r;      // step where the row is left (column 0 when no other code is found)
+    uint32_t v = 1u; // the code there
+    for (int g = 0; g < Wm; ++g) {
+      const int b = t >> 4, p = t & 15;
+      const uint32_t wd = (uint32_t)__builtin_amdgcn_readfirstlane((int)bp[(s * Wm + b) * kWave + r]);
+      const uint32_t lo = wd & kLo, hi = (wd >> 1) & kLo;
+      uint32_t m = tr ? (hi | (~lo & kLo)) : (~hi & kLo);
+      if (p < 15) m &= (1u << (2 * p + 2)) - 1u;  // steps b*16 .. t
+      if (m != 0u) {
+        const int f = (31 - __builtin_clz(m)) >> 1;
+        tx = (b << 4) + f;
+        v = (wd >> (2 * f)) & 3u;
+        break;
+      }
+      if ((b << 4) <= r) break;  // this word holds column 0: the run reaches it
+      t = (b << 4) - 1;
     }
-    if (at_start) break;
-    if (ri == 0) { --cj; continue; }  // first row / column: the only move
-    if (cj == 0) { --ri; continue; }
-    const int r = ri & (kWave - 1);
-    const int t = cj + r;
-    const uint32_t wd = (uint32_t)__builtin_amdgcn_readfirstlane((int)bp[((ri >> 6) * Wm + (t >> 4)) * kWave + r]);
-    const uint32_t code = (wd >> (2 * (t & 15))) & 3u;
-    // code 0 DIAG; 1 UP and 2 LEFT in the block's own orientation, swapped when transposed
-    if (code == 0u) { --ri; --cj; }
-    else if ((code == 1u) != tr) --ri;
-    else --cj;
+    const int cx = max(tx - r, 0);  // a code found left of column 0 is not the row's
+    const int n = cj - cx + 1;      // cells (ri, cj) .. (ri, cx)
+    for (int q0 = 0; q0 < n; q0 += kWave) {
+      const int q = q0 + lane;
+      if (q < n) tpath[slot_end - cnt - q] = tr ? make_int2(oi + cj - q, oj + ri) : make_int2(oi + ri, oj + cj - q);
+    }
+    cnt += n;
+    // leave the row: straight up at column 0 (the only move), DIAG for code 0, else up
+    cj = (cx == 0) ? 0 : ((v == 0u) ? cx - 1 : cx);
+    --ri;
   }
+  // row 0: cells (0, cj) .. (0, 1), and (0, 0) for the pair's first leaf
+  const int n0 = cj + (first ? 1 : 0);
+  for (int q0 = 0; q0 < n0; q0 += kWave) {
+    const int q = q0 + lane;
+    if (q < n0) tpath[slot_end - cnt - q] = tr ? make_int2(oi + cj - q, oj) : make_int2(oi, oj + cj - q);
+  }
+  cnt += n0;
   return cnt;
 }
 
