@@ -411,7 +411,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method is measured on one "
-              f"MI355X and the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+              f"MI355X, and splitting a batch or a pair over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.config in WORKLOADS:
         out = bench_single(args, args.config)

@@ -1,4 +1,4 @@
-"""Reduced-precision forms against the FP64 oracle (the benchmark spec precision form).
+"""Reduced-precision forms (FP32 Euclidean, BF16 and FP16 Gram cost) against the FP64 oracle.
 
 FP32 form: frame costs and the accumulated-cost recurrence in FP32 on the
 VALU; band sums S = F + B - C and the argmin in FP64 (the FP32 values
