@@ -168,6 +168,19 @@ def test_wave_model_matches_oracle(wave_exe, M, N, d, m):
     assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
+@pytest.mark.parametrize("M,N", [(130, 90), (90, 130)])
+def test_wave_model_leaf_ties(wave_exe, M, N):
+    # one leaf of two stripes (transposed or not) on integer frames with many
+    # exact ties: the leaf's walk gives the textbook path and exact cost
+    X, Y = synth.random_pair(9200 + M + N, M, N, 1, "int3")
+    r = run_model(wave_exe, [(X, Y)], 500)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    cost, path = r["results"][0]
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.tolist() == p_ref.tolist()
+    assert cost == c_ref
+
+
 @pytest.mark.parametrize("M,N,d,m", [(70, 50, 12, 16), (90, 75, 24, 500), (80, 60, 4, 8), (60, 70, 100, 16)])
 def test_wave_model_fp32_form(model_exe, wave_exe, M, N, d, m):
     # the real kernels in FP32 (staged Y frames for d <= 32, wide frames

@@ -165,6 +165,23 @@ def test_align_equals_linmdtw_port_on_ties(dtw, seed, m):
     assert cost == c_ref
 
 
+@pytest.mark.parametrize("M,N", [(480, 800), (800, 480), (200, 300), (300, 130), (64, 65), (65, 64), (1, 700)])
+def test_leaf_backtrace_on_ties(dtw, M, N):
+    # One leaf per pair (m above both sides) on integer frames, where exact
+    # ties are common: the leaf's walk over its pointer words (rows of several
+    # stripes, runs crossing 16-step words, transposed blocks, pointers in LDS
+    # or, for 480x800, in global scratch) must give the textbook path with the
+    # DIAG, UP, LEFT tie order and the exact optimal cost.
+    X, Y = synth.random_pair(9100 + M + N, M, N, 1, "int3")
+    cost, path, st = dtw.align(dev(X), dev(Y), min_block=1000)
+    assert st["leaves"] == 1
+    r = oracle.linmdtw(X, Y, min_block=1000)
+    assert path.cpu().numpy().tolist() == r["path"].tolist()
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.cpu().numpy().tolist() == p_ref.tolist()
+    assert cost == c_ref
+
+
 def test_config1_exact(dtw):
     # 500 x 400, d = 12 FP64 Gaussian walk: a single leaf at m = 500, and the
     # divide-and-conquer path at smaller m.
