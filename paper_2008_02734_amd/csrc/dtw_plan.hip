@@ -67,6 +67,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
                                                     int64_t lds_leaf_bytes) {
   __shared__ int64_t tmp[1024];
   __shared__ int32_t s_max_stripes;
+  __shared__ int32_t s_rank[1024];
   Ctl* ctl = w.ctl;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n_prev = (level == 0) ? 0 : clamp_count(ctl, ctl->n_sub, w.caps.sub);
@@ -262,20 +263,37 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
     if (n_tickets > w.caps.ticket) {
       if (tid == 0) set_error(ctl, kErrTicketCap);
     } else {
-      // a pass's stripes are written by one thread; the start offsets are
-      // read kTicketBatch at a time so that one load latency covers a batch
-      // (a long pass at the top level has hundreds of stripes)
+      // Either a pass's stripes are written by one thread, the start offsets
+      // read kTicketBatch at a time so that one load latency covers a batch,
+      // or (few passes with many stripes, as at the top levels) the passes are
+      // taken one after another with the stripes spread over the threads;
+      // the choice compares the rounds of dependent loads of the two.
       constexpr int kTicketBatch = 16;
-      for (int p = tid; p < n_pass; p += nt) {
-        const int ns = w.passes[p].n_stripes;
-        const int r = gt[ns] + atomicAdd(&eqc[ns], 1);
-        for (int s0 = 0; s0 < ns; s0 += kTicketBatch) {
-          int32_t so[kTicketBatch];
+      const int64_t rounds_strided = (int64_t)n_pass * ((max_s + nt - 1) / nt);
+      const int64_t rounds_serial = (max_s + kTicketBatch - 1) / kTicketBatch;
+      if (n_pass <= (int)(sizeof(s_rank) / sizeof(s_rank[0])) && rounds_strided < rounds_serial) {
+        for (int p = tid; p < n_pass; p += nt) {
+          const int ns = w.passes[p].n_stripes;
+          s_rank[p] = gt[ns] + atomicAdd(&eqc[ns], 1);
+        }
+        __syncthreads();
+        for (int p = 0; p < n_pass; ++p) {
+          const int ns = w.passes[p].n_stripes;
+          const int r = s_rank[p];
+          for (int s = tid; s < ns; s += nt) w.tickets[start[s] + r] = make_int2(p, s);
+        }
+      } else {
+        for (int p = tid; p < n_pass; p += nt) {
+          const int ns = w.passes[p].n_stripes;
+          const int r = gt[ns] + atomicAdd(&eqc[ns], 1);
+          for (int s0 = 0; s0 < ns; s0 += kTicketBatch) {
+            int32_t so[kTicketBatch];
 #pragma unroll
-          for (int k = 0; k < kTicketBatch; ++k) so[k] = (s0 + k < ns) ? start[s0 + k] : 0;
+            for (int k = 0; k < kTicketBatch; ++k) so[k] = (s0 + k < ns) ? start[s0 + k] : 0;
 #pragma unroll
-          for (int k = 0; k < kTicketBatch; ++k)
-            if (s0 + k < ns) w.tickets[so[k] + r] = make_int2(p, s0 + k);
+            for (int k = 0; k < kTicketBatch; ++k)
+              if (s0 + k < ns) w.tickets[so[k] + r] = make_int2(p, s0 + k);
+          }
         }
       }
     }

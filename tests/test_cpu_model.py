@@ -116,7 +116,8 @@ def run_model(exe, pairs, m, precision=0):
 
 CASES = [(37, 29, 3, 3), (100, 80, 12, 3), (129, 257, 5, 16), (300, 240, 12, 16), (70, 70, 4, 64),
          (2, 300, 4, 3), (300, 1, 4, 3), (1, 1, 2, 3), (200, 130, 1, 5), (64, 65, 32, 3),
-         (2200, 300, 2, 100)]  # several scan chunks, > 16 stripes per top-level sweep
+         (2200, 300, 2, 100),  # several scan chunks, > 16 stripes per top-level sweep
+         (5000, 300, 2, 200)]  # few passes with many stripes: tickets spread over the threads
 
 
 @pytest.mark.parametrize("M,N,d,m", CASES)
