@@ -399,40 +399,51 @@ __global__ __launch_bounds__(kBandChunk) void combine_argmin_kernel(Work w) {
 // compensated sum of the leaf costs in path order.
 __global__ __launch_bounds__(1024) void scan_kernel(Work w, int32_t* poff, int32_t* lidx,
                                                      double* costs_out, int64_t* lens_out) {
+  constexpr int kV = 8;
   __shared__ int64_t tmp[1024];
   __shared__ double2 red[1024];
+  __shared__ int32_t tile[kV * 1024];  // one chunk, for coalesced loads and stores
   const int p = blockIdx.x;
   const PairDesc pd = w.pairs[p];
   const int64_t n = pd.M + pd.N - 1;
   const int tid = threadIdx.x, nt = blockDim.x;
-  // chunks of nt * kV diagonals; a thread owns kV consecutive ones, loaded
-  // together, and the block scan carries from chunk to chunk
-  constexpr int kV = 8;
+  // chunks of nt * kV diagonals, read and written coalesced through an LDS
+  // tile; for the scan a thread owns kV consecutive diagonals of the tile,
+  // and the block scan carries from chunk to chunk
   double2 acc = make_double2(0.0, 0.0);
   const int n_leaf = clamp_count(w.ctl, w.ctl->n_leaf, w.caps.leaf);
   int64_t carry = 0;
   for (int64_t base = 0; base < n; base += (int64_t)nt * kV) {
-    const int64_t lo = base + (int64_t)tid * kV;
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+      const int64_t e = base + (int64_t)i * nt + tid;
+      const int c = (e < n) ? w.cnt[pd.pbase + e] : 0;
+      tile[i * nt + tid] = c;
+      if (c > 0) {
+        const int l = lidx[pd.pbase + e];
+        if (l >= 0 && l < n_leaf) acc = dd_add(acc, w.leaf_cost[l]);
+      }
+    }
+    __syncthreads();
     int c[kV];
     int64_t local = 0;
 #pragma unroll
     for (int k = 0; k < kV; ++k) {
-      c[k] = (lo + k < n) ? w.cnt[pd.pbase + lo + k] : 0;
+      c[k] = tile[tid * kV + k];
       local += c[k];
     }
-#pragma unroll
-    for (int k = 0; k < kV; ++k) {
-      if (c[k] > 0) {
-        const int l = lidx[pd.pbase + lo + k];
-        if (l >= 0 && l < n_leaf) acc = dd_add(acc, w.leaf_cost[l]);
-      }
-    }
     int64_t tot;
-    int64_t run = carry + block_excl_scan(local, tmp, &tot);
+    int64_t run = carry + block_excl_scan(local, tmp, &tot);  // its barriers end every read above
 #pragma unroll
     for (int k = 0; k < kV; ++k) {
-      if (lo + k < n) poff[pd.pbase + lo + k] = (int32_t)run;
+      tile[tid * kV + k] = (int32_t)run;
       run += c[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+      const int64_t e = base + (int64_t)i * nt + tid;
+      if (e < n) poff[pd.pbase + e] = tile[i * nt + tid];
     }
     carry += tot;
   }
