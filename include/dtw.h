@@ -81,7 +81,11 @@ typedef struct dtw_opts {
                               recorded on `stream` and report the sums in dtw_stats;
                               2 = time the sweep launches only (ms_sweep; fewer events
                               in the stream); 0 = no timing                              */
-  int32_t reserved[4];     /* must be zero                                                */
+  int32_t wait_limit_us;   /* bound on one boundary-row wait of a sweep, in microseconds of
+                              the device wall clock; 0 = the default of 20 s.  When a wait
+                              runs out, the call fails with DTW_ERR_INTERNAL and device
+                              error 9, and every other wait of the call ends at once       */
+  int32_t reserved[3];     /* must be zero                                                */
 } dtw_opts;
 
 typedef struct dtw_stats {
@@ -158,6 +162,20 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype,
                     int64_t i0, int64_t j0, int64_t i1, int64_t j1, int32_t reverse,
                     int64_t kstop, int32_t precision, void* workspace, size_t ws_bytes,
                     double* out, void* stream);
+
+/* Device-side consistency code of the latest dtw_align, dtw_align_batched or
+ * dtw_diag call that ran in `workspace` (device pointer).  The call's kernels
+ * write the code, so it is valid once `stream` has completed that call: this
+ * function synchronises `stream`, then reads it into *code (host).
+ *   0      no error
+ *   9      a boundary-row wait of a sweep ran past opts->wait_limit_us; every
+ *          other wait of the call then ends at once
+ *   other  a planner, queue or descriptor check failed (1..8, 10..13)
+ * A nonzero code also shows in the outputs without this query: the cost is
+ * NaN and the path length 0 (dtw_align, dtw_align_batched), every value NaN
+ * (dtw_diag).  With stats != NULL, dtw_align / dtw_align_batched report it in
+ * stats->device_error and return DTW_ERR_INTERNAL. */
+dtw_status dtw_device_error(const void* workspace, int32_t* code, void* stream);
 
 /* Batched form: B independent pairs packed back to back.
  *   x_offsets, y_offsets  host, B+1 frame offsets (pair b uses frames

@@ -52,6 +52,10 @@ def load(path: str):
     L.dtwo_frame_cost.argtypes = [dp, dp, i32]
     L.dtwo_full.restype = ctypes.c_int
     L.dtwo_full.argtypes = [dp, i64, dp, i64, i32, dp, ip, i64, lp, dp]
+    for name in ("dtwo_full_f32", "dtwo_full_left_first"):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [dp, i64, dp, i64, i32, dp, ip, i64, lp]
     L.dtwo_diag.restype = ctypes.c_int
     L.dtwo_diag.argtypes = [dp, dp, i32, i64, i64, i64, i64, i32, i64, dp]
     L.dtwo_linmdtw.restype = ctypes.c_int
@@ -127,6 +131,33 @@ def full(X, Y, return_table: bool = False, L=None):
         raise RuntimeError(f"dtwo_full failed: {rc}")
     out = (cost.value, path[: n.value].copy())
     return out + (F,) if return_table else out
+
+
+def _full_variant(name, X, Y, L):
+    X, Y = _as2d(X), _as2d(Y)
+    M, d = X.shape
+    N = Y.shape[0]
+    assert Y.shape[1] == d
+    cost = ctypes.c_double()
+    path = np.zeros((M + N - 1, 2), dtype=np.int32)
+    n = ctypes.c_int64()
+    rc = getattr(L or lib(), name)(_dp(X), M, _dp(Y), N, d, ctypes.byref(cost), _ip(path), M + N - 1,
+                                   ctypes.byref(n))
+    if rc:
+        raise RuntimeError(f"{name} failed: {rc}")
+    return cost.value, path[: n.value].copy()
+
+
+def full_f32(X, Y, L=None):
+    """Textbook DTW entirely in binary32 (Sec. 4.2's 32-bit CPU reference):
+    returns (float optimum as a Python float, path[K,2] int32)."""
+    return _full_variant("dtwo_full_f32", X, Y, L)
+
+
+def full_left_first(X, Y, L=None):
+    """Textbook DTW in FP64 with LEFT, then UP, then DIAG winning ties (the
+    second tie rule of Sec. 4.2): returns (cost, path[K,2] int32)."""
+    return _full_variant("dtwo_full_left_first", X, Y, L)
 
 
 def diag(X, Y, i0, j0, i1, j1, reverse: bool, kstop: int, L=None):

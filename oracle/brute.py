@@ -11,7 +11,8 @@ D(M-1, N-1) = sum_k binom(M-1,k) binom(N-1,k) 2^k, which pins the enumerator.
 Tie rule: among all minimisers, the path whose move sequence read backwards
 from (M-1,N-1) is lexicographically smallest under DIAG < UP < LEFT, with
 UP = (i-1,j) and LEFT = (i,j-1).  A greedy backtrace that prefers DIAG, then
-UP, then LEFT yields exactly this path.
+UP, then LEFT yields exactly this path (and one that prefers LEFT, then UP,
+then DIAG the smallest under the reversed ranking).
 """
 from __future__ import annotations
 
@@ -65,14 +66,19 @@ def backward_moves(path):
     return tuple(out)
 
 
-def brute_dtw(X, Y, cost=frame_cost):
+def brute_dtw(X, Y, cost=frame_cost, order=(DIAG, UP, LEFT)):
     """Return (optimal cost, tie-broken optimal path, number of paths enumerated).
 
-    Path costs are summed sequentially from (0,0), in path order.
+    Path costs are summed sequentially from (0,0), in path order.  `order`
+    lists the moves from most to least preferred; among minimisers the path
+    whose backward move sequence is lexicographically smallest under that
+    ranking wins (the default is DIAG, then UP, then LEFT; (LEFT, UP, DIAG)
+    is the reversed rule of Sec. 4.2).
     """
     M, N = len(X), len(Y)
     if M > 8 or N > 8:
         raise ValueError("brute force is limited to M, N <= 8")
+    rank = {mv: r for r, mv in enumerate(order)}
     C = [[cost(X[i], Y[j]) for j in range(N)] for i in range(M)]
     best = math.inf
     best_path = None
@@ -82,6 +88,33 @@ def brute_dtw(X, Y, cost=frame_cost):
         s = 0.0
         for (i, j) in p:
             s += C[i][j]
-        if s < best or (s == best and backward_moves(p) < backward_moves(best_path)):
+        if s < best or (s == best and [rank[m] for m in backward_moves(p)] <
+                        [rank[m] for m in backward_moves(best_path)]):
             best, best_path = s, p
     return best, best_path, count
+
+
+def brute_dtw_f32(X, Y):
+    """Binary32 brute force for one-dimensional frames: every path's cost is the
+    sequential float32 sum of float32 frame costs sqrt(e*e), e = x - y with x
+    and y rounded to float32 (with one dimension the frame cost involves a
+    single rounded product, so no fused operation is needed).  Returns the
+    smallest such sum as a float.  Because float addition is monotone, the
+    float32 recurrence reaches exactly this value."""
+    import numpy as np
+    M, N = len(X), len(Y)
+    if M > 8 or N > 8:
+        raise ValueError("brute force is limited to M, N <= 8")
+    xs = [np.float32(float(np.ravel(x)[0])) for x in X]
+    ys = [np.float32(float(np.ravel(y)[0])) for y in Y]
+    if any(np.size(x) != 1 for x in X) or any(np.size(y) != 1 for y in Y):
+        raise ValueError("one-dimensional frames only")
+    C = [[np.sqrt((xs[i] - ys[j]) * (xs[i] - ys[j])) for j in range(N)] for i in range(M)]
+    best = None
+    for p in enumerate_paths(M, N):
+        s = np.float32(0.0)
+        for (i, j) in p:
+            s = np.float32(s + C[i][j])
+        if best is None or s < best:
+            best = s
+    return float(best)

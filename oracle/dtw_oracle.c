@@ -127,6 +127,177 @@ int dtwo_full(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
   return rc;
 }
 
+/* Sec. 4.2 ("Numerical Precision / Tie Breaking"): the paper checks its
+ * 32-bit GPU result against a brute-force 32-bit CPU textbook solve, and two
+ * 64-bit textbook solves that differ only in whether DIAG or LEFT wins a tie.
+ * The two functions below are those two references, written as separate
+ * plain copies of the textbook table so that each can be read on its own. */
+
+/* Textbook DTW (Sec. 2.1) entirely in binary32: the frames are rounded to
+ * float, the frame cost is s <- fmaf(e,e,s), e = x-y in float, then sqrtf,
+ * and every accumulated cost is one float addition; backpointers DIAG, then
+ * UP, then LEFT.  *cost is the float optimum widened to double. */
+int dtwo_full_f32(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
+                  double* cost, int32_t* path, int64_t path_cap, int64_t* path_len) {
+  if (!X || !Y || M < 1 || N < 1 || d < 1 || !cost || !path_len) return -1;
+  float* F = (float*)malloc(sizeof(float) * (size_t)(M * N));
+  unsigned char* P = (unsigned char*)malloc((size_t)(M * N));
+  if (!F || !P) {
+    free(F);
+    free(P);
+    return -3;
+  }
+  for (int64_t i = 0; i < M; ++i) {
+    for (int64_t j = 0; j < N; ++j) {
+      float sc = 0.0f;
+      for (int32_t t = 0; t < d; ++t) {
+        float e = (float)X[i * d + t] - (float)Y[j * d + t];
+        sc = fmaf(e, e, sc);
+      }
+      float c = sqrtf(sc);
+      float f;
+      unsigned char p;
+      if (i == 0 && j == 0) {
+        f = c;
+        p = MOVE_DIAG;
+      } else if (i == 0) {
+        f = F[j - 1] + c;
+        p = MOVE_LEFT;
+      } else if (j == 0) {
+        f = F[(i - 1) * N] + c;
+        p = MOVE_UP;
+      } else {
+        float dg = F[(i - 1) * N + (j - 1)];
+        float up = F[(i - 1) * N + j];
+        float lf = F[i * N + (j - 1)];
+        float best;
+        if (dg <= up && dg <= lf) {
+          best = dg;
+          p = MOVE_DIAG;
+        } else if (up <= lf) {
+          best = up;
+          p = MOVE_UP;
+        } else {
+          best = lf;
+          p = MOVE_LEFT;
+        }
+        f = best + c;
+      }
+      F[i * N + j] = f;
+      P[i * N + j] = p;
+    }
+  }
+  *cost = (double)F[(M - 1) * N + (N - 1)];
+  int64_t len = 0, i = M - 1, j = N - 1;
+  int rc = 0;
+  for (;;) {
+    if (len >= path_cap) { rc = -2; break; }
+    if (path) {
+      path[2 * len] = (int32_t)i;
+      path[2 * len + 1] = (int32_t)j;
+    }
+    ++len;
+    if (i == 0 && j == 0) break;
+    unsigned char p = P[i * N + j];
+    if (p == MOVE_DIAG) { --i; --j; }
+    else if (p == MOVE_UP) { --i; }
+    else { --j; }
+  }
+  if (rc == 0 && path) {
+    for (int64_t a = 0, b = len - 1; a < b; ++a, --b) {
+      int32_t ti = path[2 * a], tj = path[2 * a + 1];
+      path[2 * a] = path[2 * b];
+      path[2 * a + 1] = path[2 * b + 1];
+      path[2 * b] = ti;
+      path[2 * b + 1] = tj;
+    }
+  }
+  *path_len = len;
+  free(F);
+  free(P);
+  return rc;
+}
+
+/* Textbook DTW in FP64 with the opposite tie rule: LEFT wins over DIAG.  The
+ * whole preference order is reversed, LEFT, then UP, then DIAG (the paper
+ * names only the DIAG/LEFT pair; UP keeps its middle place).  Same table,
+ * frame cost and backtrace as dtwo_full otherwise. */
+int dtwo_full_left_first(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
+                         double* cost, int32_t* path, int64_t path_cap, int64_t* path_len) {
+  if (!X || !Y || M < 1 || N < 1 || d < 1 || !cost || !path_len) return -1;
+  double* F = (double*)malloc(sizeof(double) * (size_t)(M * N));
+  unsigned char* P = (unsigned char*)malloc((size_t)(M * N));
+  if (!F || !P) {
+    free(F);
+    free(P);
+    return -3;
+  }
+  for (int64_t i = 0; i < M; ++i) {
+    for (int64_t j = 0; j < N; ++j) {
+      double c = dtwo_frame_cost(X + i * d, Y + j * d, d);
+      double f;
+      unsigned char p;
+      if (i == 0 && j == 0) {
+        f = c;
+        p = MOVE_DIAG;
+      } else if (i == 0) {
+        f = F[j - 1] + c;
+        p = MOVE_LEFT;
+      } else if (j == 0) {
+        f = F[(i - 1) * N] + c;
+        p = MOVE_UP;
+      } else {
+        double dg = F[(i - 1) * N + (j - 1)];
+        double up = F[(i - 1) * N + j];
+        double lf = F[i * N + (j - 1)];
+        double best;
+        if (lf <= up && lf <= dg) {
+          best = lf;
+          p = MOVE_LEFT;
+        } else if (up <= dg) {
+          best = up;
+          p = MOVE_UP;
+        } else {
+          best = dg;
+          p = MOVE_DIAG;
+        }
+        f = best + c;
+      }
+      F[i * N + j] = f;
+      P[i * N + j] = p;
+    }
+  }
+  *cost = F[(M - 1) * N + (N - 1)];
+  int64_t len = 0, i = M - 1, j = N - 1;
+  int rc = 0;
+  for (;;) {
+    if (len >= path_cap) { rc = -2; break; }
+    if (path) {
+      path[2 * len] = (int32_t)i;
+      path[2 * len + 1] = (int32_t)j;
+    }
+    ++len;
+    if (i == 0 && j == 0) break;
+    unsigned char p = P[i * N + j];
+    if (p == MOVE_DIAG) { --i; --j; }
+    else if (p == MOVE_UP) { --i; }
+    else { --j; }
+  }
+  if (rc == 0 && path) {
+    for (int64_t a = 0, b = len - 1; a < b; ++a, --b) {
+      int32_t ti = path[2 * a], tj = path[2 * a + 1];
+      path[2 * a] = path[2 * b];
+      path[2 * a + 1] = path[2 * b + 1];
+      path[2 * b] = ti;
+      path[2 * b + 1] = tj;
+    }
+  }
+  *path_len = len;
+  free(F);
+  free(P);
+  return rc;
+}
+
 /* Number of cells of an Mb x Nb block on local diagonal k (cells (a,k-a)). */
 static int64_t diag_len(int64_t Mb, int64_t Nb, int64_t k) {
   int64_t lo = k - (Nb - 1) > 0 ? k - (Nb - 1) : 0;

@@ -52,6 +52,19 @@ int dtwo_full(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
               double* cost, int32_t* path, int64_t path_cap, int64_t* path_len,
               double* F);
 
+/* The references of Sec. 4.2 (numerical precision and tie breaking):
+ * dtwo_full_f32        textbook DTW entirely in binary32 (frames rounded to
+ *                      float, fmaf/sqrtf frame cost, float accumulation),
+ *                      backpointers DIAG, UP, LEFT; *cost is the float
+ *                      optimum widened to double;
+ * dtwo_full_left_first textbook DTW in FP64 with the reversed tie rule:
+ *                      LEFT, then UP, then DIAG.
+ * Arguments and return values as for dtwo_full (no table output). */
+int dtwo_full_f32(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
+                  double* cost, int32_t* path, int64_t path_cap, int64_t* path_len);
+int dtwo_full_left_first(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,
+                         double* cost, int32_t* path, int64_t path_cap, int64_t* path_len);
+
 /* DiagDTW (Algorithm 1) on the block of rows i0..i1 and columns j0..j1.
  * reverse = 0: the sweep starts at (i0,j0); local cell (a,b) is (i0+a, j0+b).
  * reverse = 1: the sweep starts at (i1,j1); local cell (a,b) is (i1-a, j1-b),

@@ -1,10 +1,14 @@
 // Host runtime of libdtw_hip.so: argument checks, workspace planning and the
 // launch sequence of one alignment (Algorithm 2 of arXiv 2008.02734 run
 // level-synchronously, every level's work lists resident on the device).
+#include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "dtw.h"
@@ -67,10 +71,18 @@ DevInfo& dev_info() {
   return I;
 }
 
+thread_local bool g_launch_rejected = false;
+
 int env_int(const char* name, int dflt) {
   const char* s = getenv(name);
   if (!s || !*s) return dflt;
   return atoi(s);
+}
+
+// Device wall-clock ticks of one boundary wait: `us` microseconds, or 20 s.
+uint64_t wait_ticks(const DevInfo& I, int32_t us) {
+  const uint64_t lim_us = us > 0 ? (uint64_t)us : 20000000ull;
+  return std::max<uint64_t>(1, (uint64_t)I.wall_khz * lim_us / 1000);
 }
 
 // Split levels that can occur: a block that is split has both sides >= m, so
@@ -153,7 +165,7 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   L.cbytes = f32 ? 4 : 8;
   L.D = frame_width(d, precision);
   L.conv = gram || (f32 && in_dtype == DTW_F64) || (!f32 && in_dtype == DTW_F32) || (L.D != d);
-  put(L, L.ctl, sizeof(Ctl));
+  put(L, L.ctl, sizeof(Ctl));  // first, at offset 0: dtw_device_error reads it there
   put(L, L.pairs, sizeof(PairDesc) * n_pairs);
   put(L, L.subs0, sizeof(Block) * c.sub);
   put(L, L.subs1, sizeof(Block) * c.sub);
@@ -226,13 +238,16 @@ Work make_work(const Layout& L, void* ws, int d, int m, int precision) {
   return w;
 }
 
-#define HIP_TRY(expr)                          \
-  do {                                         \
-    hipError_t e_ = (expr);                    \
-    if (e_ != hipSuccess) {                    \
-      g_last_hip = (int32_t)e_;                \
-      return DTW_ERR_HIP;                      \
-    }                                          \
+// A failed HIP call returns DTW_ERR_HIP; a launch that check_launch refused
+// (it could not run on the device) returns DTW_ERR_INTERNAL.
+#define HIP_TRY(expr)                                         \
+  do {                                                        \
+    g_launch_rejected = false;                                \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) {                                   \
+      g_last_hip = (int32_t)e_;                               \
+      return g_launch_rejected ? DTW_ERR_INTERNAL : DTW_ERR_HIP; \
+    }                                                         \
   } while (0)
 
 dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
@@ -240,7 +255,8 @@ dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
   if (o) *out = *o;
   if (!valid_precision(out->precision)) return DTW_ERR_INVALID_ARG;
   if (out->min_block < 3 || out->min_block > kMaxMinBlock) return DTW_ERR_INVALID_ARG;
-  for (int i = 0; i < 4; ++i)
+  if (out->wait_limit_us < 0) return DTW_ERR_INVALID_ARG;
+  for (int i = 0; i < 3; ++i)
     if (out->reserved[i] != 0) return DTW_ERR_INVALID_ARG;
   return DTW_OK;
 }
@@ -403,8 +419,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   if (device_error_word) *device_error_word = &w.ctl->error;
   w.X = X;
   w.Y = Y;
-  // one boundary wait may last at most DTW_SPIN_LIMIT_MS (default 20 s)
-  w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
+  w.spin_ticks = wait_ticks(I, opts.wait_limit_us);
   PROF_TRY(prof, kProfOther, stage_inputs(L, ws, X, Y, in_f64, Mtot, Ntot, d, opts.precision, w, st));
   HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
   PROF_TRY(prof, kProfOther, launch_init(w, st));
@@ -460,6 +475,40 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
 }  // namespace
 
 namespace dtw {
+
+// Compiled resources of each kernel, read once per device; the dynamic LDS
+// limit of the leaf kernels is set before their first launch (leaf_lds_setup)
+// and the cache entry is taken after that.
+hipError_t check_launch(const void* fn, int grid, int threads, size_t dyn_lds) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, hipFuncAttributes> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  hipFuncAttributes a{};
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, fn});
+    if (it == cache.end()) {
+      const hipError_t e = hipFuncGetAttributes(&a, fn);
+      if (e != hipSuccess) return e;
+      cache.emplace(std::make_pair(dev, fn), a);
+    } else {
+      a = it->second;
+    }
+  }
+  const int64_t lds_max = dev_info().lds_max;
+  const bool ok = grid >= 1 && threads >= 1 && threads <= a.maxThreadsPerBlock &&
+                  (int64_t)a.sharedSizeBytes + (int64_t)dyn_lds <= lds_max &&
+                  (dyn_lds == 0 || (int64_t)dyn_lds <= (int64_t)a.maxDynamicSharedSizeBytes);
+  if (!ok) {
+    g_launch_rejected = true;
+    return hipErrorInvalidConfiguration;
+  }
+  return hipSuccess;
+}
+
+bool launch_rejected() { return g_launch_rejected; }
+
 // Entry points of the serving loop (dtw_server.hip): workspace of a batch,
 // and the batch enqueued on a stream without any host synchronisation; the
 // device error word of the batch is returned for a later asynchronous read.
@@ -533,6 +582,17 @@ dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t
              path_len_out, stats, (hipStream_t)stream);
 }
 
+dtw_status dtw_device_error(const void* workspace, int32_t* code, void* stream) {
+  if (!workspace || !code) return DTW_ERR_INVALID_ARG;
+  // the control block is the first region of every workspace (plan_layout)
+  int32_t v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, static_cast<const char*>(workspace) + offsetof(Ctl, error), sizeof(v),
+                         hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  *code = v;
+  return DTW_OK;
+}
+
 dtw_status dtw_workspace_size_batched(int32_t B, const int64_t* x_offsets, const int64_t* y_offsets, int32_t d,
                                       int32_t in_dtype, const dtw_opts* opts_in, size_t* bytes) {
   dtw_opts opts;
@@ -589,7 +649,7 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype, i
   HIP_TRY(stage_inputs(L, workspace, X, Y, in_f64, i1 + 1, j1 + 1, d, precision, w, st));
   w.bandC = nullptr;
   DevInfo& I = dev_info();
-  w.spin_ticks = (uint64_t)I.wall_khz * (uint64_t)std::max(1, env_int("DTW_SPIN_LIMIT_MS", 20000));
+  w.spin_ticks = wait_ticks(I, 0);
   HIP_TRY(launch_diag(w, (int32_t)i0, (int32_t)j0, (int32_t)i1, (int32_t)j1, reverse ? 1 : 0, (int32_t)kstop,
                       I.cus * (is_gram_precision(precision) ? 4 : 2), out, st));
   return DTW_OK;

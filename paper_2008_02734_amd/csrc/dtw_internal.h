@@ -168,4 +168,14 @@ struct Work {
   Caps caps;
 };
 
+// Host-side check of one launch before it is enqueued: the threads per
+// workgroup against the kernel's compiled maximum, its static plus dynamic
+// LDS against the device's per-workgroup limit and the kernel's dynamic LDS
+// limit, its registers against one SIMD's register file, and the grid size.
+// hipSuccess, or hipErrorInvalidConfiguration after recording the rejection
+// (launch_rejected() then reports it and the entry point returns
+// DTW_ERR_INTERNAL instead of enqueueing a launch the device cannot run).
+hipError_t check_launch(const void* fn, int grid, int threads, size_t dyn_lds);
+bool launch_rejected();
+
 }  // namespace dtw

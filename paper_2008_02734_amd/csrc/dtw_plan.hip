@@ -18,13 +18,14 @@ namespace dtw {
 // moves the values to q*Mb + a and fills cells outside the block with NaN.
 __global__ void diag_out_kernel(Work w, double* out) {
   const PassDesc P = w.passes[0];
+  const bool failed = w.ctl->error != 0;  // a device error leaves only NaN
   for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < 3 * (int64_t)P.Mb;
        u += (int64_t)gridDim.x * blockDim.x) {
     const int q = (int)(u / P.Mb), a = (int)(u % P.Mb);
     const int k = P.kstop - 2 + q;
     const int b = k - a;
     double v = __builtin_nan("");
-    if (b >= 0 && b < P.Nb) {
+    if (b >= 0 && b < P.Nb && !failed) {
       const int lo = max(0, k - (P.Nb - 1));
       v = w.bandF[(int64_t)q * P.L + (a - lo)];
     }
@@ -455,12 +456,15 @@ __global__ __launch_bounds__(1024) void scan_kernel(Work w, int32_t* poff, int32
     __syncthreads();
   }
   if (tid == 0) {
-    costs_out[p] = red[0].x + red[0].y;
-    lens_out[p] = total;
+    // after a device error the outputs are not an alignment: NaN cost, empty path
+    const bool failed = w.ctl->error != 0;
+    costs_out[p] = failed ? __builtin_nan("") : red[0].x + red[0].y;
+    lens_out[p] = failed ? 0 : total;
   }
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(Work w, const int32_t* poff, int32_t* paths_out) {
+  if (w.ctl->error != 0) return;  // the path length is 0 after a device error
   const int n_leaf = clamp_count(w.ctl, w.ctl->n_leaf, w.caps.leaf);
   for (int l = blockIdx.x; l < n_leaf; l += gridDim.x) {
     const LeafDesc Lf = w.leaves[l];
@@ -596,66 +600,70 @@ __global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, in
 }
 
 // ----------------------------------------------------------------- launchers
+}  // namespace dtw
+
+#include "dtw_launch.h"
+
+namespace dtw {
 
 hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st);
 
 hipError_t launch_init(const Work& w, hipStream_t st) {
-  init_kernel<<<256, 256, 0, st>>>(w);
-  return hipGetLastError();
+  return launch_checked(&init_kernel, 256, 256, 0, st, w);
 }
 hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t st) {
-  plan_kernel<<<1, 1024, 0, st>>>(w, level, final_level, lds_leaf_bytes);
-  return hipGetLastError();
+  return launch_checked(&plan_kernel, 1, 1024, 0, st, w, level, final_level, lds_leaf_bytes);
 }
 hipError_t launch_combine(const Work& w, int grid, hipStream_t st) {
-  combine_min_kernel<<<grid, kBandChunk, 0, st>>>(w);
-  combine_argmin_kernel<<<grid, kBandChunk, 0, st>>>(w);
-  return hipGetLastError();
+  const hipError_t e = launch_checked(&combine_min_kernel, grid, kBandChunk, 0, st, w);
+  if (e != hipSuccess) return e;
+  return launch_checked(&combine_argmin_kernel, grid, kBandChunk, 0, st, w);
 }
 hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* costs, int64_t* lens,
                            int32_t* paths, int grid, hipStream_t st) {
-  leaf_index_kernel<<<64, 256, 0, st>>>(w, lidx);
-  scan_kernel<<<w.n_pairs, 1024, 0, st>>>(w, poff, lidx, costs, lens);
-  copy_kernel<<<grid, 256, 0, st>>>(w, poff, paths);
-  return hipGetLastError();
+  hipError_t e = launch_checked(&leaf_index_kernel, 64, 256, 0, st, w, lidx);
+  if (e == hipSuccess) e = launch_checked(&scan_kernel, w.n_pairs, 1024, 0, st, w, poff, lidx, costs, lens);
+  if (e == hipSuccess) e = launch_checked(&copy_kernel, grid, 256, 0, st, w, static_cast<const int32_t*>(poff), paths);
+  return e;
 }
 hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
                               hipStream_t st) {
   const int64_t n = rows * D;
   const int grid = (int)min((int64_t)2048, (n + 255) / 256 + 1);
   if (in_f64 && out_f64)
-    pad_convert_kernel<double, double><<<grid, 256, 0, st>>>((const double*)in, (double*)out, rows, d, D);
-  else if (in_f64 && !out_f64)
-    pad_convert_kernel<float, double><<<grid, 256, 0, st>>>((const double*)in, (float*)out, rows, d, D);
-  else if (!in_f64 && out_f64)
-    pad_convert_kernel<double, float><<<grid, 256, 0, st>>>((const float*)in, (double*)out, rows, d, D);
-  else
-    pad_convert_kernel<float, float><<<grid, 256, 0, st>>>((const float*)in, (float*)out, rows, d, D);
-  return hipGetLastError();
+    return launch_checked(&pad_convert_kernel<double, double>, grid, 256, 0, st, static_cast<const double*>(in),
+                          static_cast<double*>(out), rows, d, D);
+  if (in_f64)
+    return launch_checked(&pad_convert_kernel<float, double>, grid, 256, 0, st, static_cast<const double*>(in),
+                          static_cast<float*>(out), rows, d, D);
+  if (out_f64)
+    return launch_checked(&pad_convert_kernel<double, float>, grid, 256, 0, st, static_cast<const float*>(in),
+                          static_cast<double*>(out), rows, d, D);
+  return launch_checked(&pad_convert_kernel<float, float>, grid, 256, 0, st, static_cast<const float*>(in),
+                        static_cast<float*>(out), rows, d, D);
 }
 hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
                              float* norms, hipStream_t st) {
   const int grid = (int)min((int64_t)2048, (rows + 3) / 4 + 1);
-  if (in_f64 && bf16) gram_stage_kernel<double, true><<<grid, 256, 0, st>>>((const double*)in, rows, d, D, out, norms);
-  else if (bf16) gram_stage_kernel<float, true><<<grid, 256, 0, st>>>((const float*)in, rows, d, D, out, norms);
-  else if (in_f64) gram_stage_kernel<double, false><<<grid, 256, 0, st>>>((const double*)in, rows, d, D, out, norms);
-  else gram_stage_kernel<float, false><<<grid, 256, 0, st>>>((const float*)in, rows, d, D, out, norms);
-  return hipGetLastError();
+  const double* id = static_cast<const double*>(in);
+  const float* is = static_cast<const float*>(in);
+  if (in_f64 && bf16) return launch_checked(&gram_stage_kernel<double, true>, grid, 256, 0, st, id, rows, d, D, out, norms);
+  if (bf16) return launch_checked(&gram_stage_kernel<float, true>, grid, 256, 0, st, is, rows, d, D, out, norms);
+  if (in_f64) return launch_checked(&gram_stage_kernel<double, false>, grid, 256, 0, st, id, rows, d, D, out, norms);
+  return launch_checked(&gram_stage_kernel<float, false>, grid, 256, 0, st, is, rows, d, D, out, norms);
 }
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st) {
   const int grid = (int)min((int64_t)1024, (n + 255) / 256 + 1);
-  if (in_f64) nonfinite_kernel<double><<<grid, 256, 0, st>>>((const double*)in, n, flag);
-  else nonfinite_kernel<float><<<grid, 256, 0, st>>>((const float*)in, n, flag);
-  return hipGetLastError();
+  if (in_f64) return launch_checked(&nonfinite_kernel<double>, grid, 256, 0, st, static_cast<const double*>(in), n, flag);
+  return launch_checked(&nonfinite_kernel<float>, grid, 256, 0, st, static_cast<const float*>(in), n, flag);
 }
 hipError_t launch_diag(const Work& w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
                        int32_t kstop, int grid, double* out, hipStream_t st) {
-  init_kernel<<<256, 256, 0, st>>>(w);
-  diag_setup_kernel<<<1, 1, 0, st>>>(w, i0, j0, i1, j1, dir, kstop);
-  hipError_t e = launch_pass(w, 0, grid, st);
-  if (e != hipSuccess) return e;
-  diag_out_kernel<<<64, 256, 0, st>>>(w, out);
-  return hipGetLastError();
+  hipError_t e = launch_checked(&init_kernel, 256, 256, 0, st, w);
+  if (e == hipSuccess) e = launch_checked(&diag_setup_kernel, 1, 1, 0, st, w, i0, j0, i1, j1, dir, kstop);
+  if (e == hipSuccess) e = launch_pass(w, 0, grid, st);
+  if (e == hipSuccess) e = launch_checked(&diag_out_kernel, 64, 256, 0, st, w, out);
+  return e;
 }
 
 }  // namespace dtw

@@ -228,17 +228,26 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // Wait until every global load and store of this wave has completed.
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// The call's device error word, read past the caches: once any wave has
+// recorded an error, every wait of the call gives up.
+__device__ __forceinline__ bool call_failed(const Work& w) {
+  return __hip_atomic_load(&w.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
 // Poll one word until it holds a value other than `empty` (or, with
 // `until_equal`, until it equals `empty`'s argument taken as the target).
 // The wait is bounded by the device wall clock (w.spin_ticks) and an
 // iteration cap; on expiry the lane records an error and returns what it
-// read last, so a broken hand-off ends the kernel instead of hanging it.
+// read last.  A wait also ends as soon as the call's error word is set, so
+// the first expiry (or any other device error) ends every wait of the
+// call: a broken hand-off costs one wait limit, not one per column.
 template <typename U>
 __device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_equal = false) {
   U v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if ((v == empty) != until_equal) {
     const uint64_t t0 = wall_clock64();
     for (uint32_t it = 0;; ++it) {
+      if (call_failed(w)) break;
       __builtin_amdgcn_s_sleep(1);
       v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if ((v == empty) == until_equal) break;
@@ -401,7 +410,9 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
   const T INF = inf_t<T>();
 
   for (int iter = 0; iter <= n_tickets; ++iter) {  // each iteration consumes one ticket
-    if (threadIdx.x == 0) sh_ticket = atomicAdd(&ctl->ticket, 1);
+    // after a device error no further stripe is started (the others end
+    // their waits at once), so a failed call drains quickly
+    if (threadIdx.x == 0) sh_ticket = call_failed(w) ? -1 : atomicAdd(&ctl->ticket, 1);
     lds_barrier();
     const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
     lds_barrier();
@@ -946,7 +957,7 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
   (void)lds_leaf_bytes;
 
   for (int iter = 0; iter <= n_leaf; ++iter) {  // each iteration consumes one ticket
-    if (threadIdx.x == 0) sh_ticket = atomicAdd(&ctl->leaf_ticket, 1);
+    if (threadIdx.x == 0) sh_ticket = call_failed(w) ? -1 : atomicAdd(&ctl->leaf_ticket, 1);
     lds_barrier();
     const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
     lds_barrier();
@@ -1033,6 +1044,11 @@ __global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
 }
 
 // ----------------------------------------------------------------- launchers
+}  // namespace dtw
+
+#include "dtw_launch.h"
+
+namespace dtw {
 
 int pick_dmax(int d) {
   if (d <= 4) return 4;
@@ -1079,41 +1095,47 @@ int pick_dgram(int d) {
 // Sweep launch for the precision of `w`: FP64 or FP32 Euclidean costs on the
 // VALU, or BF16 Gram costs on the matrix cores with the FP32 recurrence.
 hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
+  const float* nf = nullptr;
   if (w.precision == DTW_PREC_BF16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGram><<<grid, pass_threads(kCostGram), 0, st>>>(
-                                            nullptr, nullptr, w, level)))
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&pass_kernel<float, D_, kCostGram>, grid,
+                                                               pass_threads(kCostGram), 0, st, nf, nf, w, level))
   } else if (w.precision == DTW_PREC_FP16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (pass_kernel<float, D_, kCostGramF16><<<grid, pass_threads(kCostGramF16), 0, st>>>(
-                                            nullptr, nullptr, w, level)))
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&pass_kernel<float, D_, kCostGramF16>, grid,
+                                                               pass_threads(kCostGramF16), 0, st, nf, nf, w, level))
   } else if (w.precision == DTW_PREC_FP32) {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), (pass_kernel<float, D_, kCostEuclid><<<grid, kPassThreads, 0, st>>>(
-                                          static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w, level)))
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<float, D_, kCostEuclid>, grid, kPassThreads, 0,
+                                                             st, static_cast<const float*>(w.X),
+                                                             static_cast<const float*>(w.Y), w, level))
   } else {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), (pass_kernel<double, D_, kCostEuclid><<<grid, kPassThreads, 0, st>>>(
-                                          static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w, level)))
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostEuclid>, grid, kPassThreads, 0,
+                                                             st, static_cast<const double*>(w.X),
+                                                             static_cast<const double*>(w.Y), w, level))
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
                        hipStream_t st) {
   const size_t dyn = (size_t)lds_leaf_bytes;
+  const float* nf = nullptr;
   if (w.precision == DTW_PREC_BF16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (leaf_kernel<float, D_, kCostGram><<<grid, kPassThreads, dyn, st>>>(
-                                            nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGram>, grid, kPassThreads,
+                                                               dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d))
   } else if (w.precision == DTW_PREC_FP16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), (leaf_kernel<float, D_, kCostGramF16><<<grid, kPassThreads, dyn, st>>>(
-                                            nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGramF16>, grid, kPassThreads,
+                                                               dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d))
   } else if (w.precision == DTW_PREC_FP32) {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), (leaf_kernel<float, D_, kCostEuclid><<<grid, kPassThreads, dyn, st>>>(
-                                          static_cast<const float*>(w.X), static_cast<const float*>(w.Y), w,
-                                          lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<float, D_, kCostEuclid>, grid, kPassThreads,
+                                                             dyn, st, static_cast<const float*>(w.X),
+                                                             static_cast<const float*>(w.Y), w, lds_leaf_bytes, Xo, Yo,
+                                                             in_f64, w.d))
   } else {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), (leaf_kernel<double, D_, kCostEuclid><<<grid, kPassThreads, dyn, st>>>(
-                                          static_cast<const double*>(w.X), static_cast<const double*>(w.Y), w,
-                                          lds_leaf_bytes, Xo, Yo, in_f64, w.d)))
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<double, D_, kCostEuclid>, grid, kPassThreads,
+                                                             dyn, st, static_cast<const double*>(w.X),
+                                                             static_cast<const double*>(w.Y), w, lds_leaf_bytes, Xo, Yo,
+                                                             in_f64, w.d))
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 // Dynamic LDS left to the leaf kernels (pointers and bottom row) once their

@@ -33,7 +33,7 @@ class DtwError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("min_block", ctypes.c_int32),
                 ("validate_finite", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("wait_limit_us", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -79,6 +79,8 @@ def lib():
         L.dtw_align.restype = i32
         L.dtw_diag.argtypes = [vp, vp, i32, i32, i64, i64, i64, i64, i32, i64, i32, vp, sz, vp, vp]
         L.dtw_diag.restype = i32
+        L.dtw_device_error.argtypes = [vp, ctypes.POINTER(i32), vp]
+        L.dtw_device_error.restype = i32
         L.dtw_workspace_size_batched.argtypes = [i32, i64p, i64p, i32, i32, ctypes.POINTER(Opts),
                                                  ctypes.POINTER(sz)]
         L.dtw_workspace_size_batched.restype = i32
@@ -89,19 +91,37 @@ def lib():
     return _lib
 
 
-def make_opts(precision="fp64", min_block=500, validate_finite=False, profile=False):
+def make_opts(precision="fp64", min_block=500, validate_finite=False, profile=False, wait_limit_us=0):
     o = Opts()
     lib().dtw_default_opts(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.min_block = int(min_block)
     o.validate_finite = 1 if validate_finite else 0
     o.profile = int(profile) if not isinstance(profile, bool) else (1 if profile else 0)
+    o.wait_limit_us = int(wait_limit_us)
     return o
 
 
 def _check(rc, what):
     if rc != 0:
         raise DtwError(rc, what)
+
+
+class DeviceError(DtwError):
+    """A call's kernels recorded a device-side error (dtw_device_error)."""
+
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(-9, f"{what}: device error {code}")
+
+
+def device_error(ws, stream=None):
+    """Device error code of the latest call that ran in workspace `ws` (a device
+    tensor); synchronises the stream."""
+    code = ctypes.c_int32()
+    _check(lib().dtw_device_error(ctypes.c_void_p(ws.data_ptr()), ctypes.byref(code), _stream_ptr(stream)),
+           "dtw_device_error")
+    return code.value
 
 
 def _dtype_code(t):
@@ -134,9 +154,10 @@ def workspace_size(M, N, d, dtype=torch.float64, precision="fp64", min_block=500
 class Aligner:
     """Reusable buffers for repeated alignments of one problem shape."""
 
-    def __init__(self, M, N, d, dtype=torch.float64, precision="fp64", min_block=500, device="cuda"):
+    def __init__(self, M, N, d, dtype=torch.float64, precision="fp64", min_block=500, device="cuda",
+                 wait_limit_us=0):
         self.M, self.N, self.d, self.dtype = M, N, d, dtype
-        self.opts = make_opts(precision, min_block)
+        self.opts = make_opts(precision, min_block, wait_limit_us=wait_limit_us)
         self.ws_bytes = workspace_size(M, N, d, dtype, precision, min_block)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.cost = torch.empty(1, dtype=torch.float64, device=device)
@@ -144,27 +165,38 @@ class Aligner:
         self.path = torch.empty((self.cap, 2), dtype=torch.int32, device=device)
         self.plen = torch.empty(1, dtype=torch.int64, device=device)
 
-    def run(self, X, Y, stats=False, stream=None):
+    def run(self, X, Y, stats=False, stream=None, check=True):
+        """One alignment into self.cost / self.path / self.plen.  With stats the
+        call synchronises and returns the stats dict; otherwise it is
+        asynchronous unless `check` is set, which waits for the call and
+        raises DeviceError if its kernels recorded a device-side error."""
         st = Stats()
         rc = lib().dtw_align(_dev(X), self.M, _dev(Y), self.N, self.d, _dtype_code(X), ctypes.byref(self.opts),
                              ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
                              ctypes.c_void_p(self.cost.data_ptr()), ctypes.c_void_p(self.path.data_ptr()),
                              self.cap, ctypes.c_void_p(self.plen.data_ptr()),
                              ctypes.byref(st) if stats else None, _stream_ptr(stream))
+        if rc == -9 and stats and st.device_error:
+            raise DeviceError(st.device_error, "dtw_align")
         _check(rc, "dtw_align")
+        if not stats and check:
+            code = device_error(self.ws, stream)
+            if code:
+                raise DeviceError(code, "dtw_align")
         return st.to_dict() if stats else None
 
 
-def align(X, Y, precision="fp64", min_block=500, validate_finite=False, stream=None):
+def align(X, Y, precision="fp64", min_block=500, validate_finite=False, stream=None, wait_limit_us=0):
     """Optimal warping path of X (M x d) and Y (N x d), device tensors.
 
     Returns (cost: float, path: int32 tensor [K, 2] on the device, stats: dict).
+    Raises DeviceError when the call's kernels recorded a device-side error.
     """
     if X.dtype != Y.dtype or X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
         raise ValueError("X and Y must be 2-D with equal dtype and feature dimension")
     M, d = X.shape
     N = Y.shape[0]
-    al = Aligner(M, N, d, X.dtype, precision, min_block, device=X.device)
+    al = Aligner(M, N, d, X.dtype, precision, min_block, device=X.device, wait_limit_us=wait_limit_us)
     al.opts.validate_finite = 1 if validate_finite else 0
     st = al.run(X, Y, stats=True, stream=stream)
     n = int(st["path_len"])
@@ -239,6 +271,9 @@ def diag(X, Y, i0, j0, i1, j1, reverse, kstop, precision="fp64", stream=None):
                         o.precision, ctypes.c_void_p(ws.data_ptr()), n.value, ctypes.c_void_p(out.data_ptr()),
                         _stream_ptr(stream))
     _check(rc, "dtw_diag")
+    code = device_error(ws, stream)
+    if code:
+        raise DeviceError(code, "dtw_diag")
     return out
 
 

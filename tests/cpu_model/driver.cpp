@@ -10,6 +10,9 @@
 
 #include "dtw.h"
 
+#include <atomic>
+extern std::atomic<long> cpu_poll_calls;
+
 int main(int argc, char** argv) {
   if (argc != 3) return 2;
   FILE* f = std::fopen(argv[1], "rb");
@@ -59,5 +62,6 @@ int main(int argc, char** argv) {
     std::fwrite(paths.data() + 2 * po[b], 4, 2 * (rc == 0 ? lens[b] : 0), g);
   }
   std::fclose(g);
+  std::printf("poll_calls=%ld\n", cpu_poll_calls.load());
   return 0;
 }

@@ -21,6 +21,7 @@ thread_local std::barrier<>* cpu_wave_barrier = nullptr;
 
 #include "wave_shim.h"
 uint64_t cpu_wave_slots[16][64];
+std::atomic<long> cpu_poll_calls{0};  // boundary waits entered by the wave kernels (instrumented model)
 alignas(16) unsigned char cpu_dynamic_lds[163840];
 #include "dtw_plan_kernels.inc"
 #ifdef MODEL_WAVE
@@ -31,12 +32,59 @@ uint16_t cpu_mfma_b[16][64][8];
 }  // namespace dtw
 #endif
 
+// Resources the model reports for its kernels (hipFuncGetAttributes): the
+// device kernels' workgroup sizes and static LDS of the same order (cost ring
+// and boundary row), so that the host runtime's launch check runs on the
+// same figures it sees on the device.
+struct CpuKernelRes {
+  int threads;
+  size_t static_lds;
+};
+static const CpuKernelRes* cpu_res_of(const void* fn);
+hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void* fn) {
+  const CpuKernelRes* r = cpu_res_of(fn);
+  if (!r) return hipErrorInvalidValue;
+  a->maxThreadsPerBlock = r->threads;
+  a->sharedSizeBytes = r->static_lds;
+  a->maxDynamicSharedSizeBytes = (int)(163840 - r->static_lds);
+  a->numRegs = 64;
+  a->localSizeBytes = 0;
+  return hipSuccess;
+}
+
 #define MODEL_CHECK(cond)                                                      \
   do {                                                                         \
     if (!(cond)) {                                                             \
       std::fprintf(stderr, "model check failed: %s (%s:%d)\n", #cond, __FILE__, __LINE__); \
       std::abort();                                                            \
     }                                                                          \
+  } while (0)
+
+namespace dtw {
+
+// One tag per model kernel: its address is the "kernel" the launch check sees.
+static char tag_pass[2], tag_leaf[2], tag_plan, tag_init, tag_small, tag_scan;
+}  // namespace dtw
+
+static const CpuKernelRes* cpu_res_of(const void* fn) {
+  using namespace dtw;
+  static const CpuKernelRes pass64{kPassThreads, 8 * kCostRing * kWave + 8 * 2 * kPhase + 64};
+  static const CpuKernelRes pass32{kPassThreads, 4 * kCostRing * kWave + 4 * 2 * kPhase + 64};
+  static const CpuKernelRes plan{1024, 8 * 1024 + 4 * 1024 + 8};
+  static const CpuKernelRes small{1024, 0};
+  static const CpuKernelRes scan{1024, 8 * 1024 + 16 * 1024 + 4 * 8 * 1024};
+  if (fn == &tag_pass[0] || fn == &tag_leaf[0]) return &pass64;
+  if (fn == &tag_pass[1] || fn == &tag_leaf[1]) return &pass32;
+  if (fn == &tag_plan) return &plan;
+  if (fn == &tag_init || fn == &tag_small) return &small;
+  if (fn == &tag_scan) return &scan;
+  return nullptr;
+}
+
+#define MODEL_LAUNCH_CHECK(TAG, GRID, THREADS, DYN)                   \
+  do {                                                              \
+    const hipError_t e_ = check_launch((TAG), (GRID), (THREADS), (DYN)); \
+    if (e_ != hipSuccess) return e_;                                \
   } while (0)
 
 namespace dtw {
@@ -305,7 +353,9 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
     case 128: { constexpr int D_ = 128; CALL; } break;             \
     default: std::abort();                                          \
   }
-hipError_t launch_pass(const Work& w, int level, int, hipStream_t) {
+hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_pass[w.precision != DTW_PREC_FP64], grid,
+                     is_gram_precision(w.precision) ? pass_threads(kCostGram) : kPassThreads, 0);
   model_check_queue(w);
   if (w.precision == DTW_PREC_BF16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGram), [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
@@ -318,8 +368,9 @@ hipError_t launch_pass(const Work& w, int level, int, hipStream_t) {
   }
   return hipSuccess;
 }
-hipError_t launch_leaf(const Work& w, int, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
+hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
                        hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_leaf[w.precision != DTW_PREC_FP64], grid, kPassThreads, (size_t)lds_leaf_bytes);
   model_check_leaves(w);
   if (w.precision == DTW_PREC_BF16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostGram>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
@@ -333,12 +384,16 @@ hipError_t launch_leaf(const Work& w, int, int64_t lds_leaf_bytes, const void* X
   return hipSuccess;
 }
 #else
-hipError_t launch_pass(const Work& w, int, int, hipStream_t) {
+hipError_t launch_pass(const Work& w, int, int grid, hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_pass[w.precision != DTW_PREC_FP64], grid,
+                     is_gram_precision(w.precision) ? pass_threads(kCostGram) : kPassThreads, 0);
   if (w.precision != DTW_PREC_FP64) model_pass<float>(w);
   else model_pass<double>(w);
   return hipSuccess;
 }
-hipError_t launch_leaf(const Work& w, int, int64_t, const void* Xo, const void* Yo, int in_f64, hipStream_t) {
+hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
+                       hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_leaf[w.precision != DTW_PREC_FP64], grid, kPassThreads, (size_t)lds_leaf_bytes);
   if (w.precision != DTW_PREC_FP64) model_leaf<float>(w, Xo, Yo, in_f64);
   else model_leaf<double>(w, Xo, Yo, in_f64);
   return hipSuccess;
@@ -354,20 +409,26 @@ hipError_t leaf_lds_setup(int64_t, int64_t* dyn_f64, int64_t* dyn_f32) {
 }
 
 hipError_t launch_init(const Work& w, hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_init, 256, 256, 0);
   cpu_launch(2, 64, [&] { init_kernel(w); });
   return hipSuccess;
 }
 hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_plan, 1, 1024, 0);
   cpu_launch(1, 128, [&] { plan_kernel(w, level, final_level, lds_leaf_bytes); });
   return hipSuccess;
 }
-hipError_t launch_combine(const Work& w, int, hipStream_t) {
+hipError_t launch_combine(const Work& w, int grid, hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_small, grid, kBandChunk, 0);
   cpu_launch(3, kBandChunk, [&] { combine_min_kernel(w); });
   cpu_launch(3, kBandChunk, [&] { combine_argmin_kernel(w); });
   return hipSuccess;
 }
 hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* costs, int64_t* lens,
-                           int32_t* paths, int, hipStream_t) {
+                           int32_t* paths, int grid, hipStream_t) {
+  MODEL_LAUNCH_CHECK(&tag_small, 64, 256, 0);
+  MODEL_LAUNCH_CHECK(&tag_scan, w.n_pairs, 1024, 0);
+  MODEL_LAUNCH_CHECK(&tag_small, grid, 256, 0);
   cpu_launch(2, 64, [&] { leaf_index_kernel(w, lidx); });
   cpu_launch(w.n_pairs, 128, [&] { scan_kernel(w, poff, lidx, costs, lens); });
   cpu_launch(2, 64, [&] { copy_kernel(w, poff, paths); });

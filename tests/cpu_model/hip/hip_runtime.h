@@ -8,6 +8,7 @@
 #include <barrier>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -15,7 +16,7 @@
 #include <vector>
 
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidConfiguration = 9 };
 typedef void* hipStream_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
 enum hipDeviceAttribute_t {
@@ -68,14 +69,31 @@ template <class T> inline T atomicMax(T* p, T v) {
 }
 
 inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+// The LDS limit per workgroup can be lowered with CPU_MODEL_LDS_MAX (bytes) so
+// that a test can make the host-side launch check refuse a launch.
 inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
   switch (a) {
     case hipDeviceAttributeMultiprocessorCount: *v = 4; break;
-    case hipDeviceAttributeMaxSharedMemoryPerBlock: *v = 163840; break;
+    case hipDeviceAttributeMaxSharedMemoryPerBlock: {
+      const char* e = std::getenv("CPU_MODEL_LDS_MAX");
+      *v = (e && *e) ? std::atoi(e) : 163840;
+      break;
+    }
     case hipDeviceAttributeWallClockRate: *v = 100000; break;
   }
   return hipSuccess;
 }
+
+// Compiled resources of a kernel as the HIP runtime reports them; the model's
+// figures come from the harness (cpu_kernel_resources).
+struct hipFuncAttributes {
+  size_t sharedSizeBytes = 0;
+  int maxThreadsPerBlock = 0;
+  int maxDynamicSharedSizeBytes = 0;
+  int numRegs = 0;
+  size_t localSizeBytes = 0;
+};
+hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void* fn);
 inline hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind, hipStream_t) {
   std::memcpy(dst, src, n);
   return hipSuccess;

@@ -47,6 +47,11 @@ WAVE_EDITS = [
     ('asm volatile("s_waitcnt lgkmcnt(0)\\n\\ts_barrier" ::: "memory");', "__syncthreads();"),
     ('asm volatile("s_waitcnt vmcnt(0)" ::: "memory");', "std::atomic_thread_fence(std::memory_order_seq_cst);"),
     ("extern __shared__ __align__(16) unsigned char lds_raw[];", "unsigned char* lds_raw = cpu_dynamic_lds;"),
+    # instrumentation: count every boundary wait (poll of a ring cell or a
+    # generation word) that a wave kernel enters
+    ("__device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_equal = false) {\n",
+     "__device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_equal = false) {\n"
+     "  cpu_poll_calls.fetch_add(1);\n"),
 ]
 
 
@@ -85,7 +90,7 @@ def wave_exe(tmp_path_factory):
     return _build_model(tmp_path_factory.mktemp("cpu_model_wave"), wave=True)
 
 
-def run_model(exe, pairs, m, precision=0):
+def run_model(exe, pairs, m, precision=0, env=None):
     d = pairs[0][0].shape[1]
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
@@ -98,9 +103,10 @@ def run_model(exe, pairs, m, precision=0):
             for _, Y in pairs:
                 f.write(np.ascontiguousarray(Y, dtype=np.float64).tobytes())
         r = subprocess.run([exe, fin, fout], capture_output=True, timeout=300,
-                           env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+                           env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0", **(env or {})))
         assert r.returncode == 0, r.stderr.decode()[-3000:]
         buf = open(fout, "rb").read()
+        polls = int(r.stdout.decode().split("poll_calls=")[1].split()[0])
     rc, derr, levels, leaves = struct.unpack_from("4i", buf, 0)
     (cells,) = struct.unpack_from("q", buf, 16)
     off = 24
@@ -111,7 +117,7 @@ def run_model(exe, pairs, m, precision=0):
         path = np.frombuffer(buf, dtype=np.int32, count=2 * n, offset=off).reshape(-1, 2) if rc == 0 else None
         off += 8 * n if rc == 0 else 0
         out.append((cost, path))
-    return dict(rc=rc, device_error=derr, levels=levels, leaves=leaves, cells=cells, results=out)
+    return dict(rc=rc, device_error=derr, levels=levels, leaves=leaves, cells=cells, results=out, polls=polls)
 
 
 CASES = [(37, 29, 3, 3), (100, 80, 12, 3), (129, 257, 5, 16), (300, 240, 12, 16), (70, 70, 4, 64),
@@ -167,6 +173,32 @@ def test_wave_model_matches_oracle(wave_exe, M, N, d, m):
     c_ref, p_ref = oracle.full(X, Y)
     assert path.tolist() == p_ref.tolist()
     assert abs(cost - c_ref) <= 1e-12 * c_ref
+
+
+def test_wave_model_single_stripe_case_has_no_wait(wave_exe):
+    # 37 x 29 at m = 3: every sweep has at most 34 rows (one stripe) and every
+    # leaf at most 2 rows, so no kernel of this alignment ever enters a
+    # boundary wait; a taller pair at the same cutoff does
+    X, Y = synth.random_pair(8000, 37, 29, 3, "normal")
+    r = run_model(wave_exe, [(X, Y)], 3)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    assert r["polls"] == 0
+    assert r["results"][0][1].tolist() == oracle.full(X, Y)[1].tolist()
+    X2, Y2 = synth.random_pair(8001, 130, 90, 5, "normal")
+    r2 = run_model(wave_exe, [(X2, Y2)], 3)
+    assert r2["rc"] == 0 and r2["polls"] > 0
+
+
+def test_launch_check_refuses_launch_beyond_lds(model_exe):
+    # the host-side launch check: with a per-workgroup LDS limit below the
+    # sweep kernel's static LDS the call returns DTW_ERR_INTERNAL (-9) before
+    # anything runs, instead of enqueueing a launch the device cannot place
+    X, Y = synth.random_pair(8100, 100, 80, 12, "normal")
+    r = run_model(model_exe, [(X, Y)], 16, env={"CPU_MODEL_LDS_MAX": "65536"})
+    assert r["rc"] == -9
+    # the same problem under the device's real limit runs
+    r_ok = run_model(model_exe, [(X, Y)], 16)
+    assert r_ok["rc"] == 0 and r_ok["device_error"] == 0
 
 
 @pytest.mark.parametrize("M,N", [(130, 90), (90, 130)])

@@ -136,6 +136,51 @@ def test_align_matches_textbook_tie_free(dtw, s, M, N, d, m):
     assert abs(st["s_min"] - c_ref) <= 1e-12 * c_ref
 
 
+def test_wait_limit_ends_the_call(dtw):
+    # A 1 us limit on each boundary-row wait, on a pair whose top-level sweeps
+    # have 282 stripes: stripe 1 starts waiting for stripe 0 at once, its wait
+    # runs out, and the call's error word stops every other wait and every
+    # further stripe and leaf.  The call reports device error 9 and
+    # DTW_ERR_INTERNAL, the cost is NaN and the path empty, and it returns in
+    # well under a second of GPU time instead of one limit per column.  The
+    # same workspace then serves a normal call (every buffer is re-initialised).
+    import time
+    X, Y = synth.make_pair(2, 0, 20000, 16000, 12, "chroma")
+    Xd, Yd = dev(X), dev(Y)
+    al = dtw.Aligner(20000, 16000, 12, wait_limit_us=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    al.run(Xd, Yd, check=False)
+    code = dtw.device_error(al.ws)
+    elapsed = time.perf_counter() - t0
+    assert code == 9
+    assert math.isnan(float(al.cost.item())) and int(al.plen.item()) == 0
+    assert elapsed < 5.0
+    with pytest.raises(dtw.DeviceError) as e:
+        al.run(Xd, Yd, stats=True)
+    assert e.value.code == 9
+    al.opts.wait_limit_us = 0
+    st = al.run(Xd, Yd, stats=True)
+    assert st["device_error"] == 0 and dtw.device_error(al.ws) == 0
+    fresh = dtw.Aligner(20000, 16000, 12)
+    fresh.run(Xd, Yd)
+    assert float(al.cost.item()) == float(fresh.cost.item())
+    n = int(fresh.plen.item())
+    assert int(al.plen.item()) == n and torch.equal(al.path[:n], fresh.path[:n])
+
+
+def test_device_error_query_without_stats(dtw):
+    # a call without stats is asynchronous; its device error word is read
+    # afterwards through dtw_device_error, and it is 0 for a good call
+    X, Y = synth.random_pair(8300, 700, 650, 12, "normal")
+    Xd, Yd = dev(X), dev(Y)
+    al = dtw.Aligner(700, 650, 12, min_block=64)
+    al.run(Xd, Yd, check=False)
+    assert dtw.device_error(al.ws) == 0
+    c_ref, p_ref = oracle.full(X, Y)
+    assert al.path[: int(al.plen.item())].cpu().numpy().tolist() == p_ref.tolist()
+
+
 def test_exact_tie_continuous_d1(dtw):
     # d = 1 continuous frames: |x - y| costs give an exact FP64 tie between two
     # optimal paths on this input; the pivot rule follows the oracle's port of

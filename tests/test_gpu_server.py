@@ -2,6 +2,10 @@
 
 Each request's result must be the same alone (dtw_align) and in the mix, and
 requests submitted while others run must be admitted and run concurrently.
+Every served result is also checked against the CPU oracle: FP64 requests
+return the textbook path, reduced-precision requests a valid path within
+their tolerance of the exact optimum, and every reported cost is the FP64
+cost of the returned path.
 """
 import time
 
@@ -9,7 +13,11 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2008_02734_amd import synth
+
+# relative cost error against the exact optimum, per form
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 1e-5, "bf16": 1e-2}
 
 pytestmark = pytest.mark.gpu
 
@@ -27,8 +35,10 @@ def dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def mixed_requests(n, seed=5):
-    """Uneven lengths and the four precision forms, from the generators."""
+def mixed_requests(n, seed=5, host=False):
+    """Uneven lengths and the four precision forms, from the generators.  With
+    `host`, each entry also carries the FP64 host frames the device frames were
+    made from (as the device sees them: rounded to FP32 for the FP32 inputs)."""
     rng = np.random.default_rng([5, 999, seed])
     reqs = []
     for r in range(n):
@@ -37,29 +47,48 @@ def mixed_requests(n, seed=5):
         kind = r % 4
         if kind == 0:
             X, Y = synth.make_pair(5, r, M, N, 12, "chroma")
-            reqs.append((dev(X, torch.float64), dev(Y, torch.float64), "fp64"))
+            item = (dev(X, torch.float64), dev(Y, torch.float64), "fp64")
         elif kind == 1:
             X, Y = synth.make_pair(5, r, M, N, 12, "chroma")
-            reqs.append((dev(X, torch.float32), dev(Y, torch.float32), "fp32"))
+            item = (dev(X, torch.float32), dev(Y, torch.float32), "fp32")
         else:
             X, Y = synth.make_pair(5, r, M, N, 128, "embedding")
-            reqs.append((dev(X, torch.float32), dev(Y, torch.float32), "bf16" if kind == 2 else "fp16"))
+            item = (dev(X, torch.float32), dev(Y, torch.float32), "bf16" if kind == 2 else "fp16")
+        if host:
+            item = item + (item[0].double().cpu().numpy(), item[1].double().cpu().numpy())
+        reqs.append(item)
     return reqs
 
 
+def check_against_oracle(Xh, Yh, prec, cost, path):
+    """A served result against the oracle: textbook path and cost for FP64, a
+    valid path within the form's tolerance of the exact optimum otherwise, and
+    the reported cost equal to the FP64 cost of the returned path."""
+    p = path.cpu().numpy()
+    M, N = Xh.shape[0], Yh.shape[0]
+    assert tuple(p[0]) == (0, 0) and tuple(p[-1]) == (M - 1, N - 1)
+    assert {tuple(v) for v in np.diff(p, axis=0).tolist()} <= {(0, 1), (1, 0), (1, 1)}
+    c_ref, p_ref = oracle.full(Xh, Yh)
+    if prec == "fp64":
+        assert p.tolist() == p_ref.tolist()
+    assert -1e-12 <= (cost - c_ref) / c_ref <= TOL[prec], (prec, cost, c_ref)
+    assert abs(cost - oracle.path_cost(Xh, Yh, p)) <= 1e-12 * c_ref
+
+
 def test_results_same_alone_and_in_the_mix(dtw):
-    reqs = mixed_requests(20)
+    reqs = mixed_requests(20, host=True)
     srv = dtw.Server(pool_bytes=256 << 20, max_slots=3, max_batch=4)
     try:
-        tickets = [srv.submit(X, Y, precision=p, min_block=128) for X, Y, p in reqs]
+        tickets = [srv.submit(X, Y, precision=p, min_block=128) for X, Y, p, _, _ in reqs]
         results = [srv.wait(t) for t in tickets]
     finally:
         srv.close()
-    for (X, Y, p), res in zip(reqs, results):
+    for (X, Y, p, Xh, Yh), res in zip(reqs, results):
         assert res["status"] == 0 and res["device_error"] == 0, res
         cost, path, _ = dtw.align(X, Y, precision=p, min_block=128)
         assert res["cost"] == cost
         assert torch.equal(res["path"], path)
+        check_against_oracle(Xh, Yh, p, res["cost"], res["path"])
     # several requests per batch, and batches of different requests overlapped in time
     assert max(r["batch_size"] for r in results) > 1
     spans = sorted((r["t_admit_ns"], r["t_done_ns"]) for r in results)
@@ -89,6 +118,35 @@ def test_requests_arriving_while_others_run(dtw):
     assert sum(r["t_done_ns"] < res_long["t_done_ns"] for r in res_short) >= 3
     cost, path, _ = dtw.align(*long_req)
     assert res_long["cost"] == cost and torch.equal(res_long["path"], path)
+    check_against_oracle(X, Y, "fp64", res_long["cost"], res_long["path"])
+
+
+def test_long_request_in_the_mix(dtw):
+    # one request of 120000 x 100000 frames (FP32, d = 12) served beside
+    # shorter ones: its cost is within 1e-5 of the GPU's exact FP64 path on the
+    # same frames (whose path equals the oracle's by the parity tests), and the
+    # reported cost is the FP64 cost of the returned path
+    X, Y = synth.make_pair(5, 300, 120000, 100000, 12, "chroma")
+    X32, Y32 = dev(X, torch.float32), dev(Y, torch.float32)
+    Xh, Yh = X32.double().cpu().numpy(), Y32.double().cpu().numpy()
+    shorts = mixed_requests(4, seed=11)
+    srv = dtw.Server(pool_bytes=2 << 30, max_slots=4, max_batch=4)
+    try:
+        t_long = srv.submit(X32, Y32, precision="fp32")
+        t_short = [srv.submit(Xs, Ys, precision=p) for Xs, Ys, p in shorts]
+        res = srv.wait(t_long)
+        res_short = [srv.wait(t) for t in t_short]
+    finally:
+        srv.close()
+    assert res["status"] == 0 and res["device_error"] == 0, res
+    assert all(r["status"] == 0 for r in res_short)
+    c64, p64, st = dtw.align(X32.double(), Y32.double())
+    assert st["device_error"] == 0
+    assert -1e-12 <= (res["cost"] - c64) / c64 <= 1e-5
+    p = res["path"].cpu().numpy()
+    assert tuple(p[0]) == (0, 0) and tuple(p[-1]) == (X.shape[0] - 1, Y.shape[0] - 1)
+    assert {tuple(v) for v in np.diff(p, axis=0).tolist()} <= {(0, 1), (1, 0), (1, 1)}
+    assert abs(res["cost"] - oracle.path_cost(Xh, Yh, p)) <= 1e-12 * c64
 
 
 def test_poll_busy_then_done_and_errors(dtw):

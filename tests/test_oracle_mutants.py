@@ -34,6 +34,12 @@ MUTANTS = {
     "duplicate_pivot_kept": ("    start = 1;\n", "    start = 0;\n"),
     "pivot_tie_last": ("if (s < best) { best = s; ba = a; bk = k; }",
                        "if (s <= best) { best = s; ba = a; bk = k; }"),
+    "f32_subtracts_before_rounding": ("float e = (float)X[i * d + t] - (float)Y[j * d + t];",
+                                      "float e = (float)(X[i * d + t] - Y[j * d + t]);"),
+    "f32_drops_diag": ("        float best;\n        if (dg <= up && dg <= lf) {",
+                       "        float best;\n        if (0) {"),
+    "left_first_up_before_left": ("if (lf <= up && lf <= dg) {", "if (lf < up && lf <= dg) {"),
+    "left_first_diag_before_up": ("} else if (up <= dg) {", "} else if (up < dg) {"),
     "path_cost_scaled": ("s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d);",
                           "s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d) * 1.0000001;"),
 }
@@ -87,6 +93,16 @@ CHECKS = textwrap.dedent(r'''
         c, _ = oracle.full(X, Y, L=L)
         r = oracle.linmdtw(X, Y, min_block=3, L=L)
         check("linm_ties", r["cost"] == c)
+    # the references of Sec. 4.2: float32 table against the float32 brute
+    # force, reversed tie rule against the brute force under that ranking
+    from oracle.brute import brute_dtw_f32, DIAG, UP, LEFT
+    for s in range(10):
+        X, Y = synth.random_pair(900 + s, 2 + s % 6, 3 + s % 5, 1, "normal")
+        check("f32_brute", oracle.full_f32(X, Y, L=L)[0] == brute_dtw_f32(X, Y))
+        X, Y = synth.random_pair(700 + s, 3 + s % 5, 2 + s % 6, 1, "int3")
+        c, p = oracle.full_left_first(X, Y, L=L)
+        b, bp, _ = brute_dtw(X, Y, order=(LEFT, UP, DIAG))
+        check("left_first_brute", c == b and p.tolist() == [list(q) for q in bp])
     # pivot tie rule on an all-tie input (every split cost is 0)
     Z = np.zeros((40, 1)); W = np.zeros((33, 1))
     r = oracle.linmdtw(Z, W, min_block=3, L=L)

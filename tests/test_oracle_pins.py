@@ -104,6 +104,75 @@ def test_full_equals_brute_ties(s, M, N, d):
     assert path.tolist() == [list(c) for c in bp]
 
 
+# ------------------------------------------- Sec. 4.2: 32-bit and tie-rule references
+
+@pytest.mark.parametrize("s,M,N,d", list(_cases("int3", 40)))
+def test_left_first_equals_brute_under_reversed_order(s, M, N, d):
+    # Integer frames make ties exact; the reversed tie rule (LEFT, then UP,
+    # then DIAG) must give the backward-lexicographic minimiser under that
+    # ranking, with the same optimal cost as the default rule.
+    from oracle.brute import DIAG, LEFT, UP
+    X, Y = synth.random_pair(700 + s, M, N, d, "int3")
+    cost, path = oracle.full_left_first(X, Y)
+    b, bp, _ = brute_dtw(X, Y, order=(LEFT, UP, DIAG))
+    assert cost == b == oracle.full(X, Y)[0]
+    assert path.tolist() == [list(c) for c in bp]
+
+
+def test_left_first_differs_from_default_on_a_tie():
+    # X = Y = (0, 0): every path costs 0.  DIAG first steps from (1,1)
+    # straight back to (0,0); LEFT first steps to (1,0), whose only move (column
+    # 0) is UP to (0,0).
+    X = np.zeros((2, 1))
+    assert oracle.full(X, X)[1].tolist() == [[0, 0], [1, 1]]
+    assert oracle.full_left_first(X, X)[1].tolist() == [[0, 0], [1, 0], [1, 1]]
+
+
+@pytest.mark.parametrize("s,M,N", [(s, 1 + s % 7, 1 + (3 * s) % 8) for s in range(30)])
+def test_f32_equals_float32_brute_force(s, M, N):
+    # One-dimensional frames: the float32 table's optimum equals the smallest
+    # sequential float32 sum over all warping paths (float addition is
+    # monotone, so the recurrence reaches it exactly), and the returned path's
+    # float32 sum is that value.
+    from oracle.brute import brute_dtw_f32
+    X, Y = synth.random_pair(900 + s, M, N, 1, "normal")
+    cost, path = oracle.full_f32(X, Y)
+    assert cost == brute_dtw_f32(X, Y)
+    x32, y32 = X.astype(np.float32)[:, 0], Y.astype(np.float32)[:, 0]
+    acc = np.float32(0.0)
+    for i, j in path:
+        acc = np.float32(acc + np.sqrt((x32[i] - y32[j]) * (x32[i] - y32[j])))
+    assert float(acc) == cost
+    assert valid_path(path, M, N)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_f32_equals_f64_on_exact_inputs(seed):
+    # Small integer frames (d = 1): every frame cost |x - y| and every partial
+    # sum is an integer below 2^24, exact in both formats, so the float32
+    # table must reproduce the FP64 optimum and path exactly.
+    X, Y = synth.random_pair(950 + seed, 30 + seed, 25 + 2 * seed, 1, "int3")
+    c32, p32 = oracle.full_f32(X, Y)
+    c64, p64 = oracle.full(X, Y)
+    assert c32 == c64 and p32.tolist() == p64.tolist()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_f32_within_rounding_bound_of_f64(seed):
+    # Continuous 12-dimensional frames: each float32 frame cost is within
+    # (d + 3) units of 2^-24 of the exact one (input rounding, d fused steps,
+    # the square root) and each of the K path additions adds one more, so the
+    # optimum moves by at most (K + d + 3) * 2^-24 relative (plus a slack of
+    # 2); a dropped term or a wrong operand is far outside this.
+    X, Y = synth.make_pair(1, seed, 60 + 10 * seed, 50 + 7 * seed, 12, "gaussian_walk")
+    c32, p32 = oracle.full_f32(X, Y)
+    c64, _ = oracle.full(X, Y)
+    K = X.shape[0] + Y.shape[0] - 1
+    assert abs(c32 - c64) <= 2 * (K + 12 + 3) * 2.0 ** -24 * c64
+    assert abs(c32 - c64) > 0 or seed > 0  # float32 rounding is visible on the first pair
+    assert valid_path(p32, X.shape[0], Y.shape[0])
+
+
 # ---------------------------------------------------------------- closed forms
 
 def test_single_row_and_column_are_forced():
