@@ -48,6 +48,8 @@ def load(path: str):
     ip = ctypes.POINTER(ctypes.c_int32)
     lp = ctypes.POINTER(ctypes.c_int64)
     i64, i32 = ctypes.c_int64, ctypes.c_int32
+    L.dtwo_set_cost.restype = ctypes.c_int
+    L.dtwo_set_cost.argtypes = [i32]
     L.dtwo_frame_cost.restype = ctypes.c_double
     L.dtwo_frame_cost.argtypes = [dp, dp, i32]
     L.dtwo_full.restype = ctypes.c_int
@@ -110,13 +112,36 @@ def _as2d(X):
     return np.ascontiguousarray(X)
 
 
-def frame_cost(x, y, L=None) -> float:
+# Frame cost kinds of dtwo_set_cost (Sec. 4.1).
+COSTS = {"euclidean": 0, "cosine": 1}
+
+
+class _CostScope:
+    """Select a frame cost for the calls inside a `with` block, then restore
+    the Euclidean default."""
+
+    def __init__(self, L, cost):
+        self.L, self.kind = L, COSTS[cost]
+
+    def __enter__(self):
+        if self.L.dtwo_set_cost(self.kind) != 0:
+            raise ValueError(f"unknown cost kind {self.kind}")
+        return self.L
+
+    def __exit__(self, *exc):
+        self.L.dtwo_set_cost(0)
+        return False
+
+
+def frame_cost(x, y, L=None, cost="euclidean") -> float:
     x, y = _f64(x).ravel(), _f64(y).ravel()
-    return (L or lib()).dtwo_frame_cost(_dp(x), _dp(y), x.size)
+    with _CostScope(L or lib(), cost) as lb:
+        return lb.dtwo_frame_cost(_dp(x), _dp(y), x.size)
 
 
-def full(X, Y, return_table: bool = False, L=None):
+def full(X, Y, return_table: bool = False, L=None, cost="euclidean"):
     """Textbook DTW: returns (cost, path[K,2] int32[, F table M x N])."""
+    kind = cost
     X, Y = _as2d(X), _as2d(Y)
     M, d = X.shape
     N = Y.shape[0]
@@ -125,15 +150,16 @@ def full(X, Y, return_table: bool = False, L=None):
     path = np.zeros((M + N - 1, 2), dtype=np.int32)
     n = ctypes.c_int64()
     F = np.zeros((M, N), dtype=np.float64) if return_table else None
-    rc = (L or lib()).dtwo_full(_dp(X), M, _dp(Y), N, d, ctypes.byref(cost), _ip(path), M + N - 1,
-                         ctypes.byref(n), _dp(F) if F is not None else None)
+    with _CostScope(L or lib(), kind) as lb:
+        rc = lb.dtwo_full(_dp(X), M, _dp(Y), N, d, ctypes.byref(cost), _ip(path), M + N - 1,
+                          ctypes.byref(n), _dp(F) if F is not None else None)
     if rc:
         raise RuntimeError(f"dtwo_full failed: {rc}")
     out = (cost.value, path[: n.value].copy())
     return out + (F,) if return_table else out
 
 
-def _full_variant(name, X, Y, L):
+def _full_variant(name, X, Y, L, kind="euclidean"):
     X, Y = _as2d(X), _as2d(Y)
     M, d = X.shape
     N = Y.shape[0]
@@ -141,8 +167,9 @@ def _full_variant(name, X, Y, L):
     cost = ctypes.c_double()
     path = np.zeros((M + N - 1, 2), dtype=np.int32)
     n = ctypes.c_int64()
-    rc = getattr(L or lib(), name)(_dp(X), M, _dp(Y), N, d, ctypes.byref(cost), _ip(path), M + N - 1,
-                                   ctypes.byref(n))
+    with _CostScope(L or lib(), kind) as lb:
+        rc = getattr(lb, name)(_dp(X), M, _dp(Y), N, d, ctypes.byref(cost), _ip(path), M + N - 1,
+                               ctypes.byref(n))
     if rc:
         raise RuntimeError(f"{name} failed: {rc}")
     return cost.value, path[: n.value].copy()
@@ -154,45 +181,48 @@ def full_f32(X, Y, L=None):
     return _full_variant("dtwo_full_f32", X, Y, L)
 
 
-def full_left_first(X, Y, L=None):
+def full_left_first(X, Y, L=None, cost="euclidean"):
     """Textbook DTW in FP64 with LEFT, then UP, then DIAG winning ties (the
     second tie rule of Sec. 4.2): returns (cost, path[K,2] int32)."""
-    return _full_variant("dtwo_full_left_first", X, Y, L)
+    return _full_variant("dtwo_full_left_first", X, Y, L, cost)
 
 
-def diag(X, Y, i0, j0, i1, j1, reverse: bool, kstop: int, L=None):
+def diag(X, Y, i0, j0, i1, j1, reverse: bool, kstop: int, L=None, cost="euclidean"):
     """DiagDTW on a block; returns a (3, Mb) array of diagonals kstop-2..kstop by local row."""
     X, Y = _as2d(X), _as2d(Y)
     Mb = i1 - i0 + 1
     out = np.zeros((3, Mb), dtype=np.float64)
-    rc = (L or lib()).dtwo_diag(_dp(X), _dp(Y), X.shape[1], i0, j0, i1, j1, int(reverse), kstop, _dp(out))
+    with _CostScope(L or lib(), cost) as lb:
+        rc = lb.dtwo_diag(_dp(X), _dp(Y), X.shape[1], i0, j0, i1, j1, int(reverse), kstop, _dp(out))
     if rc:
         raise RuntimeError(f"dtwo_diag failed: {rc}")
     return out
 
 
-def linmdtw(X, Y, min_block: int = 500, pivots_cap: int = 1 << 16, L=None):
+def linmdtw(X, Y, min_block: int = 500, pivots_cap: int = 1 << 16, L=None, cost="euclidean"):
     """linmdtw: returns dict(cost, path, s_min, cells, pivots)."""
     X, Y = _as2d(X), _as2d(Y)
     M, d = X.shape
     N = Y.shape[0]
-    cost = ctypes.c_double()
+    kind, cost = cost, ctypes.c_double()
     smin = ctypes.c_double()
     cells = ctypes.c_int64()
     n = ctypes.c_int64()
     npiv = ctypes.c_int64()
     path = np.zeros((M + N - 1, 2), dtype=np.int32)
     piv = np.zeros((pivots_cap, 2), dtype=np.int32)
-    rc = (L or lib()).dtwo_linmdtw(_dp(X), M, _dp(Y), N, d, min_block, ctypes.byref(cost), _ip(path),
-                            M + N - 1, ctypes.byref(n), ctypes.byref(smin), ctypes.byref(cells),
-                            _ip(piv), pivots_cap, ctypes.byref(npiv))
+    with _CostScope(L or lib(), kind) as lb:
+        rc = lb.dtwo_linmdtw(_dp(X), M, _dp(Y), N, d, min_block, ctypes.byref(cost), _ip(path),
+                             M + N - 1, ctypes.byref(n), ctypes.byref(smin), ctypes.byref(cells),
+                             _ip(piv), pivots_cap, ctypes.byref(npiv))
     if rc:
         raise RuntimeError(f"dtwo_linmdtw failed: {rc}")
     return dict(cost=cost.value, path=path[: n.value].copy(), s_min=smin.value,
                 cells=cells.value, pivots=piv[: npiv.value].copy())
 
 
-def path_cost(X, Y, path, L=None) -> float:
+def path_cost(X, Y, path, L=None, cost="euclidean") -> float:
     X, Y = _as2d(X), _as2d(Y)
     p = np.ascontiguousarray(np.asarray(path, dtype=np.int32))
-    return (L or lib()).dtwo_path_cost(_dp(X), X.shape[0], _dp(Y), Y.shape[0], X.shape[1], _ip(p), p.shape[0])
+    with _CostScope(L or lib(), cost) as lb:
+        return lb.dtwo_path_cost(_dp(X), X.shape[0], _dp(Y), Y.shape[0], X.shape[1], _ip(p), p.shape[0])

@@ -35,13 +35,50 @@
 #include <string.h>
 
 /* Euclidean frame cost, Sec. 4.1. */
-double dtwo_frame_cost(const double* x, const double* y, int32_t d) {
+static double euclidean_cost(const double* x, const double* y, int32_t d) {
   double s = 0.0;
   for (int32_t t = 0; t < d; ++t) {
     double e = x[t] - y[t];
     s = fma(e, e, s);
   }
   return sqrt(s);
+}
+
+/* Cosine frame cost, the alternative Sec. 4.1 discusses for the chroma-type
+ * features: one minus the cosine of the angle between the two frames.  Each
+ * frame is divided by its Euclidean norm (sqrt of the fma chain of its
+ * squares, in dimension order; a zero frame stays zero), the normalised
+ * frames' dot product is an fma chain in dimension order, and the cost is
+ * 1 - dot, raised to 0 where rounding takes it below (so that no cost is
+ * negative). */
+static double cosine_cost(const double* x, const double* y, int32_t d) {
+  double nx = 0.0, ny = 0.0;
+  for (int32_t t = 0; t < d; ++t) nx = fma(x[t], x[t], nx);
+  for (int32_t t = 0; t < d; ++t) ny = fma(y[t], y[t], ny);
+  nx = sqrt(nx);
+  ny = sqrt(ny);
+  double s = 0.0;
+  for (int32_t t = 0; t < d; ++t) {
+    double xt = nx > 0.0 ? x[t] / nx : 0.0;
+    double yt = ny > 0.0 ? y[t] / ny : 0.0;
+    s = fma(xt, yt, s);
+  }
+  double c = 1.0 - s;
+  return c < 0.0 ? 0.0 : c;
+}
+
+/* The frame cost every table and sweep below uses: Euclidean unless
+ * dtwo_set_cost selected the cosine cost. */
+static int32_t g_cost_kind = DTWO_COST_EUCLIDEAN;
+
+int dtwo_set_cost(int32_t kind) {
+  if (kind != DTWO_COST_EUCLIDEAN && kind != DTWO_COST_COSINE) return -1;
+  g_cost_kind = kind;
+  return 0;
+}
+
+double dtwo_frame_cost(const double* x, const double* y, int32_t d) {
+  return g_cost_kind == DTWO_COST_COSINE ? cosine_cost(x, y, d) : euclidean_cost(x, y, d);
 }
 
 enum { MOVE_DIAG = 0, MOVE_UP = 1, MOVE_LEFT = 2 };

@@ -8,7 +8,8 @@
  * Warping Alignment with Linear Memory" (arXiv 2008.02734):
  *
  *   - frame cost C(i,j): Euclidean distance between frame i of X and frame j
- *     of Y (Sec. 4.1, "Features": Euclidean chosen over cosine);
+ *     of Y (Sec. 4.1, "Features": Euclidean chosen over cosine), or on
+ *     request the cosine cost that passage discusses;
  *   - warping path: starts at (0,0), ends at (M-1,N-1), steps (0,1),(1,0),
  *     (1,1) (Sec. 2.1);
  *   - textbook table: boundary equation (prefix sums along row 0 and column
@@ -40,7 +41,18 @@
 extern "C" {
 #endif
 
-/* C(i,j) for one pair of frames (Sec. 4.1: Euclidean distance). */
+/* Frame cost kinds (Sec. 4.1): the Euclidean distance the paper uses, and
+ * the cosine cost it discusses for chroma-type features (1 - cos of the
+ * angle between the frames; each frame divided by its norm, a zero frame
+ * kept zero; dot product of the normalised frames as an fma chain in
+ * dimension order; negative rounding results raised to 0). */
+enum { DTWO_COST_EUCLIDEAN = 0, DTWO_COST_COSINE = 1 };
+
+/* Select the frame cost of every later call (default Euclidean); -1 for an
+ * unknown kind.  Process-wide state: the oracle is single-threaded. */
+int dtwo_set_cost(int32_t kind);
+
+/* C(i,j) for one pair of frames under the selected cost. */
 double dtwo_frame_cost(const double* x, const double* y, int32_t d);
 
 /* Textbook DTW on the whole M x N grid (Sec. 2.1).

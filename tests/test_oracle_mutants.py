@@ -40,6 +40,9 @@ MUTANTS = {
                        "        float best;\n        if (0) {"),
     "left_first_up_before_left": ("if (lf <= up && lf <= dg) {", "if (lf < up && lf <= dg) {"),
     "left_first_diag_before_up": ("} else if (up <= dg) {", "} else if (up < dg) {"),
+    "cosine_unnormalised_x": ("double xt = nx > 0.0 ? x[t] / nx : 0.0;", "double xt = x[t];"),
+    "cosine_distance_not_complemented": ("double c = 1.0 - s;", "double c = s;"),
+    "cosine_zero_frame_nan": ("double yt = ny > 0.0 ? y[t] / ny : 0.0;", "double yt = y[t] / ny;"),
     "path_cost_scaled": ("s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d);",
                           "s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d) * 1.0000001;"),
 }
@@ -103,6 +106,26 @@ CHECKS = textwrap.dedent(r'''
         c, p = oracle.full_left_first(X, Y, L=L)
         b, bp, _ = brute_dtw(X, Y, order=(LEFT, UP, DIAG))
         check("left_first_brute", c == b and p.tolist() == [list(q) for q in bp])
+    # the cosine cost: closed forms, scale invariance, brute force
+    e1 = np.array([1.0, 0.0, 0.0]); e2 = np.array([0.0, 1.0, 0.0])
+    check("cos_closed", oracle.frame_cost(e1, e2, L=L, cost="cosine") == 1.0
+          and oracle.frame_cost(e1, -e1, L=L, cost="cosine") == 2.0
+          and oracle.frame_cost(np.zeros(3), e1, L=L, cost="cosine") == 1.0
+          and oracle.frame_cost(e1, np.zeros(3), L=L, cost="cosine") == 1.0
+          and oracle.frame_cost(e1, 5 * e1, L=L, cost="cosine") == 0.0)
+    X, Y = synth.make_pair(6, 0, 30, 26, 12, "chroma")
+    c, p = oracle.full(X, Y, L=L, cost="cosine")
+    c2, p2 = oracle.full(X * 8.0, Y * 0.25, L=L, cost="cosine")
+    check("cos_scale", c == c2 and p.tolist() == p2.tolist())
+    import math
+    def cpy(x, y):
+        nx = math.sqrt(sum(v * v for v in x)); ny = math.sqrt(sum(v * v for v in y))
+        return 1.0 if nx == 0 or ny == 0 else max(0.0, 1.0 - sum(a * b for a, b in zip(x, y)) / (nx * ny))
+    for s in range(6):
+        X, Y = synth.random_pair(1100 + s, 3 + s % 4, 2 + s % 5, 3, "normal")
+        c, p = oracle.full(X, Y, L=L, cost="cosine")
+        b, bp, _ = brute_dtw(X, Y, cost=cpy)
+        check("cos_brute", abs(c - b) <= 1e-12 * max(1, b) and p.tolist() == [list(q) for q in bp])
     # pivot tie rule on an all-tie input (every split cost is 0)
     Z = np.zeros((40, 1)); W = np.zeros((33, 1))
     r = oracle.linmdtw(Z, W, min_block=3, L=L)

@@ -173,6 +173,83 @@ def test_f32_within_rounding_bound_of_f64(seed):
     assert valid_path(p32, X.shape[0], Y.shape[0])
 
 
+# ------------------------------------------- Sec. 4.1: the cosine frame cost
+
+def _cos_cost_py(x, y):
+    # 1 - cos(angle), written out independently of the oracle (plain products
+    # and sums, math.sqrt), clamped at 0 like the oracle's definition
+    nx = math.sqrt(sum(float(v) * float(v) for v in x))
+    ny = math.sqrt(sum(float(v) * float(v) for v in y))
+    if nx == 0.0 or ny == 0.0:
+        return 1.0
+    return max(0.0, 1.0 - sum(float(a) * float(b) for a, b in zip(x, y)) / (nx * ny))
+
+
+def test_cosine_cost_closed_forms():
+    e1, e2 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    assert oracle.frame_cost(e1, e2, cost="cosine") == 1.0          # orthogonal
+    assert oracle.frame_cost(e1, -e1, cost="cosine") == 2.0         # opposite
+    assert oracle.frame_cost(e1, 5 * e1, cost="cosine") == 0.0      # parallel
+    assert oracle.frame_cost(np.zeros(3), e1, cost="cosine") == 1.0  # a zero frame
+    assert oracle.frame_cost(e1, np.zeros(3), cost="cosine") == 1.0
+    x, y = np.array([3.0, 4.0]), np.array([6.0, 8.0])
+    assert oracle.frame_cost(x, y, cost="cosine") <= 4e-16          # parallel, inexact quotients
+    # 60 degrees: cos = 1/2
+    a, b = np.array([1.0, 0.0]), np.array([0.5, math.sqrt(3) / 2])
+    assert oracle.frame_cost(a, b, cost="cosine") == pytest.approx(0.5, abs=1e-15)
+    # the Euclidean default is untouched afterwards
+    assert oracle.frame_cost(e1, e2) == math.sqrt(2.0)
+
+
+@pytest.mark.parametrize("s,M,N,d", list(_cases("normal", 30)))
+def test_cosine_full_equals_brute(s, M, N, d):
+    d = max(d, 2)
+    X, Y = synth.random_pair(1100 + s, M, N, d, "normal")
+    for i in range(X.shape[0]):
+        for j in range(Y.shape[0]):
+            assert oracle.frame_cost(X[i], Y[j], cost="cosine") == pytest.approx(_cos_cost_py(X[i], Y[j]),
+                                                                                  abs=2e-15)
+    cost, path = oracle.full(X, Y, cost="cosine")
+    b, bp, _ = brute_dtw(X, Y, cost=_cos_cost_py)
+    assert abs(cost - b) <= 1e-12 * max(1.0, b)
+    assert path.tolist() == [list(c) for c in bp]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_cosine_ignores_frame_scale(seed):
+    # the cosine cost depends on directions only: scaling every frame by a
+    # power of two leaves each normalised frame, hence every cost, path and
+    # accumulated value, bit for bit unchanged
+    X, Y = synth.make_pair(6, seed, 40 + seed, 33 + seed, 12, "chroma")
+    c, p = oracle.full(X, Y, cost="cosine")
+    rng = np.random.default_rng(seed)
+    Xs = X * 2.0 ** rng.integers(-6, 7, (X.shape[0], 1))
+    Ys = Y * 2.0 ** rng.integers(-6, 7, (Y.shape[0], 1))
+    c2, p2 = oracle.full(Xs, Ys, cost="cosine")
+    assert c2 == c and p2.tolist() == p.tolist()
+
+
+@pytest.mark.parametrize("seed,m", [(0, 3), (1, 8), (2, 16)])
+def test_cosine_linmdtw_equals_full_and_diag_equals_table(seed, m):
+    # the divide and conquer and the sweep under the cosine cost: the same
+    # identities as for the Euclidean cost (Lemma 2 gives the textbook path
+    # on tie-free inputs; DiagDTW equals the table bit for bit)
+    X, Y = synth.make_pair(6, 10 + seed, 70 + 9 * seed, 55 + 5 * seed, 12, "chroma")
+    c, p, F = oracle.full(X, Y, return_table=True, cost="cosine")
+    r = oracle.linmdtw(X, Y, min_block=m, cost="cosine")
+    assert r["path"].tolist() == p.tolist()
+    assert abs(r["cost"] - c) <= 1e-12 * c
+    assert oracle.path_cost(X, Y, p, cost="cosine") == pytest.approx(c, rel=1e-12)
+    M, N = X.shape[0], Y.shape[0]
+    kstop = (M + N) // 2
+    out = oracle.diag(X, Y, 0, 0, M - 1, N - 1, 0, kstop, cost="cosine")
+    for q in range(3):
+        for a in range(M):
+            b = kstop - 2 + q - a
+            if 0 <= b < N:
+                assert out[q, a] == F[a, b]
+
+
 # ---------------------------------------------------------------- closed forms
 
 def test_single_row_and_column_are_forced():
