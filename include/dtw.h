@@ -147,6 +147,28 @@ dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t
                      int64_t path_cap, int64_t* path_len_out, dtw_stats* stats,
                      void* stream);
 
+/* No-allocation form of dtw_align, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as dtw_align, except:
+ *   - there is no workspace argument: the library's own fixed device array of
+ *     DTW_NOALLOC_SCRATCH_BYTES (one per GPU, held from the library's load
+ *     until the process ends) serves as the workspace;
+ *   - a problem whose dtw_workspace_size() exceeds DTW_NOALLOC_SCRATCH_BYTES
+ *     is rejected with DTW_ERR_WORKSPACE before any work is enqueued (64 MiB
+ *     holds, e.g., 20000 x 16000 at d = 12 in FP64, about 10.4 MiB);
+ *   - opts->profile must be 0 (DTW_ERR_INVALID_ARG otherwise).
+ * The call allocates no device or pinned host memory.  Every call on one GPU
+ * shares that GPU's array, and each call re-initialises what it reads there,
+ * so successive calls on one stream are independent; calls that overlap in
+ * time on one GPU (different streams or host threads) race and give undefined
+ * results.  A device-side error shows as a NaN cost and path length 0, and in
+ * stats->device_error when stats is given. */
+#define DTW_NOALLOC_SCRATCH_BYTES (64u << 20)
+dtw_status dtw_align_noalloc(const void* X, int64_t M, const void* Y, int64_t N, int32_t d,
+                             int32_t in_dtype, const dtw_opts* opts, double* cost_out,
+                             int32_t* path_out, int64_t path_cap, int64_t* path_len_out,
+                             dtw_stats* stats, void* stream);
+
 /* DiagDTW (Algorithm 1): one wavefront sweep over the block rows i0..i1,
  * columns j0..j1 of X, Y, stopping at local diagonal kstop
  * (2 <= kstop <= Mb + Nb - 2, Mb = i1-i0+1, Nb = j1-j0+1).

@@ -472,6 +472,37 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   return DTW_OK;
 }
 
+// ------------------------------------------------------------ no-allocation form
+//
+// Workspace of dtw_align_noalloc: a fixed array in device memory, one copy per
+// GPU, held from the library's load until the process ends.  Host code never
+// passes `scratch` itself to a kernel or a copy (in host code the name is a
+// host-side stand-in, not a device address): it passes the address that
+// hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) unsigned char scratch[DTW_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};
+
+// Device address of the current device's `scratch`, looked up once per device
+// with that device current.
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 namespace dtw {
@@ -580,6 +611,23 @@ dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t
   const int64_t xo[2] = {0, M}, yo[2] = {0, N};
   return run(1, X, Y, xo, yo, d, in_dtype, opts, workspace, ws_bytes, cost_out, path_out, nullptr, path_cap,
              path_len_out, stats, (hipStream_t)stream);
+}
+
+dtw_status dtw_align_noalloc(const void* X, int64_t M, const void* Y, int64_t N, int32_t d, int32_t in_dtype,
+                             const dtw_opts* opts, double* cost_out, int32_t* path_out, int64_t path_cap,
+                             int64_t* path_len_out, dtw_stats* stats, void* stream) {
+  if (M < 1 || N < 1 || !X || !Y || !cost_out || !path_out || !path_len_out) return DTW_ERR_INVALID_ARG;
+  if (opts && opts->profile != 0) return DTW_ERR_INVALID_ARG;  // the profiler creates events
+  if (path_cap < M + N - 1) return DTW_ERR_CAPACITY;
+  size_t need = 0;
+  dtw_status rc = dtw_workspace_size(M, N, d, in_dtype, opts, &need);
+  if (rc != DTW_OK) return rc;
+  if (need > (size_t)DTW_NOALLOC_SCRATCH_BYTES) return DTW_ERR_WORKSPACE;
+  void* ws = nullptr;
+  HIP_TRY(scratch_address(&ws));
+  const int64_t xo[2] = {0, M}, yo[2] = {0, N};
+  return run(1, X, Y, xo, yo, d, in_dtype, opts, ws, (size_t)DTW_NOALLOC_SCRATCH_BYTES, cost_out, path_out,
+             nullptr, path_cap, path_len_out, stats, (hipStream_t)stream);
 }
 
 dtw_status dtw_device_error(const void* workspace, int32_t* code, void* stream) {

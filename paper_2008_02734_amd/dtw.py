@@ -77,6 +77,9 @@ def lib():
         L.dtw_align.argtypes = [vp, i64, vp, i64, i32, i32, ctypes.POINTER(Opts), vp, sz, vp, vp, i64, vp,
                                 ctypes.POINTER(Stats), vp]
         L.dtw_align.restype = i32
+        L.dtw_align_noalloc.argtypes = [vp, i64, vp, i64, i32, i32, ctypes.POINTER(Opts), vp, vp, i64, vp,
+                                        ctypes.POINTER(Stats), vp]
+        L.dtw_align_noalloc.restype = i32
         L.dtw_diag.argtypes = [vp, vp, i32, i32, i64, i64, i64, i64, i32, i64, i32, vp, sz, vp, vp]
         L.dtw_diag.restype = i32
         L.dtw_device_error.argtypes = [vp, ctypes.POINTER(i32), vp]
@@ -201,6 +204,29 @@ def align(X, Y, precision="fp64", min_block=500, validate_finite=False, stream=N
     st = al.run(X, Y, stats=True, stream=stream)
     n = int(st["path_len"])
     return float(al.cost.item()), al.path[:n], st
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DTW_NOALLOC_SCRATCH_BYTES of include/dtw.h
+
+
+def align_noalloc(X, Y, cost, path, plen, precision="fp64", min_block=500, stats=False, stream=None):
+    """dtw_align_noalloc: the alignment of X and Y into the caller's device
+    tensors cost (1 float64), path ([>= M+N-1, 2] int32) and plen (1 int64),
+    with the library's own fixed device array as the workspace.  Returns the
+    stats dict when `stats` is set (the call then synchronises), else None."""
+    if X.dtype != Y.dtype or X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+        raise ValueError("X and Y must be 2-D with equal dtype and feature dimension")
+    M, d = X.shape
+    N = Y.shape[0]
+    o = make_opts(precision, min_block)
+    st = Stats()
+    rc = lib().dtw_align_noalloc(_dev(X), M, _dev(Y), N, d, _dtype_code(X), ctypes.byref(o), _dev(cost),
+                                 _dev(path), path.shape[0], _dev(plen), ctypes.byref(st) if stats else None,
+                                 _stream_ptr(stream))
+    if rc == -9 and stats and st.device_error:
+        raise DeviceError(st.device_error, "dtw_align_noalloc")
+    _check(rc, "dtw_align_noalloc")
+    return st.to_dict() if stats else None
 
 
 class BatchAligner:

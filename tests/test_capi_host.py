@@ -86,3 +86,22 @@ def test_batched_argument_errors():
     rc = L.dtw_align_batched(2, vp(1), arr([0, 3, 3]), vp(1), arr([0, 3, 7]), 4, 0, ctypes.byref(o), vp(1),
                              1 << 40, vp(1), vp(1), arr([0, 5, 12]), vp(1), None, None)
     assert rc == -1
+
+
+def _noalloc(L, M=10, N=10, d=12, opts=None, cap=None):
+    o = opts if opts is not None else dtw.make_opts()
+    cap = (M + N - 1) if cap is None else cap
+    vp = ctypes.c_void_p
+    return L.dtw_align_noalloc(vp(1), M, vp(1), N, d, 0, ctypes.byref(o), vp(1), vp(1), cap, vp(1), None, None)
+
+
+def test_noalloc_rejects_before_any_device_work():
+    L = dtw.lib()
+    assert dtw.workspace_size(200000, 160000, 12) > dtw.NOALLOC_SCRATCH_BYTES
+    assert _noalloc(L, M=200000, N=160000) == -3      # beyond the fixed array
+    assert _noalloc(L, M=0) == -1
+    assert _noalloc(L, d=129) == -8
+    assert _noalloc(L, cap=18) == -2
+    assert _noalloc(L, opts=dtw.make_opts(profile=1)) == -1
+    assert "#define DTW_NOALLOC_SCRATCH_BYTES (64u << 20)" in open(dtw.HEADER).read()
+    assert dtw.NOALLOC_SCRATCH_BYTES == 64 << 20
