@@ -16,7 +16,8 @@
 #include <vector>
 
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidConfiguration = 9 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidConfiguration = 9, hipErrorInvalidDevice = 101,
+       hipErrorInvalidSymbol = 13 };
 typedef void* hipStream_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
 enum hipDeviceAttribute_t {
@@ -100,6 +101,10 @@ inline hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpy
 }
 inline hipError_t hipMemsetAsync(void* p, int v, size_t n, hipStream_t) { std::memset(p, v, n); return hipSuccess; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+// A device variable is an ordinary host object here, so its address is itself.
+#define HIP_SYMBOL(x) (&(x))
+template <class T>
+inline hipError_t hipGetSymbolAddress(void** p, T* sym) { *p = (void*)sym; return hipSuccess; }
 inline hipError_t hipGetLastError() { return hipSuccess; }
 typedef int* hipEvent_t;
 inline hipError_t hipEventCreate(hipEvent_t* e) { static int dummy; *e = &dummy; return hipSuccess; }
