@@ -110,7 +110,7 @@ struct Layout {
   int cbytes = 8;  // bytes of the compute type
   int D = 0;       // padded frame stride of the compute copies
   Region ctl, pairs, subs0, subs1, piv_key, piv_pos, smin, passes, tickets, hist, chunk_sub, bandF, bandC,
-      bandB, ring, gens, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, xnorm, ynorm,
+      bandB, ring, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, xnorm, ynorm,
       nonfinite;
   size_t total = 0;
 };
@@ -152,7 +152,6 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   c.band = (3 * K0sum) / 2 + (3 + kBandChunk) * c.sub + 3 * Mmax + kBandChunk;
   c.chunk = c.band / kBandChunk + c.sub + 1;
   c.ring = 2 * kRing * (Nsum + c.sub) + kRing * Mmax;
-  c.gen = 2 * kRing * c.sub + kRing;
   c.ticket = 2 * ((Msum + kWave - 1) / kWave + 2 * c.sub) + Mmax / kWave + 2;
   c.hist = Mmax / kWave + 3;
   // per leaf: ceil(R/64)*64 <= R+63 rows of ceil((Cc+63)/16) <= Cc/16+5 words, R < m,
@@ -179,8 +178,7 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   put(L, L.bandF, 8 * c.band);
   put(L, L.bandC, 8 * c.band);
   put(L, L.bandB, 8 * c.band);
-  put(L, L.ring, (size_t)L.cbytes * c.ring);
-  put(L, L.gens, 4 * (size_t)c.gen);
+  put(L, L.ring, (size_t)L.cbytes * 2 * c.ring);  // cells of 2 (FP64) or 1 (FP32) 8-byte words
   put(L, L.leaves, sizeof(LeafDesc) * c.leaf);
   put(L, L.leaf_scratch, 4 * c.leaf_words);
   put(L, L.tpath, 8 * c.pslots);
@@ -226,9 +224,8 @@ Work make_work(const Layout& L, void* ws, int d, int m, int precision) {
   w.bandF = at<double>(ws, L.bandF);
   w.bandC = at<double>(ws, L.bandC);
   w.bandB = at<double>(ws, L.bandB);
-  w.ring = at<void>(ws, L.ring);
-  w.ring_f32 = L.cbytes == 4 ? 1 : 0;
-  w.gens = at<uint32_t>(ws, L.gens);
+  w.ring = at<uint64_t>(ws, L.ring);
+  w.ring_words = L.cbytes / 4;
   w.leaves = at<LeafDesc>(ws, L.leaves);
   w.leaf_scratch = at<uint32_t>(ws, L.leaf_scratch);
   w.tpath = at<int2>(ws, L.tpath);

@@ -15,18 +15,19 @@
 namespace dtw {
 
 constexpr int kWave = 64;        // gfx950 wavefront width; one lane per DP row
-constexpr int kRing = 2;         // boundary-row slots per sweep (see pass kernel)
+constexpr int kRing = 2;         // boundary rows per sweep (see pass kernel)
 constexpr int kBandChunk = 256;  // band cells per split-cost work item
 constexpr int kMaxMinBlock = 1024;
 constexpr uint32_t kSpinIterCap = 1u << 26;  // polls before a wait gives up
 
-// Pass kernel workgroup: one recurrence wave, kProducers frame-cost waves and
-// one boundary-input wave; phases of kPhase steps between barriers.
+// Sweep and leaf workgroups: one recurrence wave, kProducers frame-cost
+// waves and one boundary-input wave; phases of kPhase steps between barriers.
 constexpr int kProducers = 8;
-constexpr int kPassThreads = kWave * (kProducers + 2);
+constexpr int kLeafThreads = kWave * (kProducers + 2);
 constexpr int kPhase = 32;
 constexpr int kCostRing = 128;  // LDS cost slots, indexed by step
-constexpr int kPubGroup = 16;   // steps per boundary-row publication
+constexpr int kPubGroup = 16;   // steps per bottom-row publication (sweep and leaf)
+constexpr int kStepGroup = 4;   // recurrence steps whose operands are read together
 
 // Frame cost forms: the exact Euclidean cost on the VALU (FP64 or FP32), or
 // the Gram form on the matrix cores (dtw_gram.h) from BF16 or FP16 frames.
@@ -40,12 +41,6 @@ constexpr bool is_gram(int cm) { return cm != kCostEuclid; }
 constexpr int pass_producers(int cm) { return is_gram(cm) ? 2 : kProducers; }
 constexpr int pass_threads(int cm) { return kWave * (pass_producers(cm) + 2); }
 constexpr bool is_gram_precision(int p) { return p == DTW_PREC_BF16_COST || p == DTW_PREC_FP16_COST; }
-
-// Content of a boundary-ring cell that has not been written: a signalling
-// NaN.  No arithmetic result is a signalling NaN, so a cell holding any other
-// bit pattern carries a published value.
-constexpr uint64_t kRingEmpty64 = 0xFFF7A5A5A5A5A5A5ull;
-constexpr uint32_t kRingEmpty32 = 0xFFA5A5A5u;
 
 struct Block {
   int32_t i0, j0, i1, j1;  // inclusive, global frame indices
@@ -73,8 +68,7 @@ struct PassDesc {
   int32_t raw;        // 1: band written in the sweep's own coordinates (dtw_diag)
   int32_t pad;
   int64_t band_off;   // element offset of the block's 3*L band slots
-  int64_t ring_off;   // element offset of the kRing boundary rows (kRing*Nb)
-  int64_t gen_off;    // offset of the kRing generation words of the rows
+  int64_t ring_off;   // cell offset of the kRing boundary rows (kRing*Nb cells)
 };
 
 struct LeafDesc {
@@ -123,8 +117,7 @@ struct Caps {
   int64_t cand;      // candidates per level (2 * sub, at least n_pairs)
   int64_t leaf;      // leaves over all levels
   int64_t band;      // band slots per level
-  int64_t ring;      // boundary-row elements per level
-  int64_t gen;       // boundary-row generation words per level
+  int64_t ring;      // boundary-row cells per level
   int64_t ticket;    // stripes per level
   int64_t chunk;     // band work items per level
   int64_t hist;      // histogram bins (max stripes + 1)
@@ -156,9 +149,8 @@ struct Work {
   double* bandF;        // forward accumulated cost on the band (S after combine)
   double* bandC;        // frame cost on the band
   double* bandB;        // backward accumulated cost on the band
-  void* ring;           // boundary rows, compute type (cells empty between levels)
-  int32_t ring_f32;     // 1: ring cells are float, else double
-  uint32_t* gens;       // per boundary row: tag of the stripe that owns it
+  uint64_t* ring;       // boundary-row cells of the sweeps (words of value half + writer id)
+  int32_t ring_words;   // words per ring cell: 2 for FP64 values, 1 for FP32
   LeafDesc* leaves;
   uint32_t* leaf_scratch;
   int2* tpath;          // diagonal-indexed path scratch

@@ -42,14 +42,8 @@ __global__ void init_kernel(Work w) {
     Ctl c = {};
     *w.ctl = c;
   }
-  for (int64_t u = tid; u < w.caps.gen; u += nt) w.gens[u] = 0u;
-  if (w.ring_f32) {
-    uint32_t* r = static_cast<uint32_t*>(w.ring);
-    for (int64_t u = tid; u < w.caps.ring; u += nt) r[u] = kRingEmpty32;
-  } else {
-    uint64_t* r = static_cast<uint64_t*>(w.ring);
-    for (int64_t u = tid; u < w.caps.ring; u += nt) r[u] = kRingEmpty64;
-  }
+  // boundary-row cells: writer id 0, which no stripe has
+  for (int64_t u = tid; u < w.caps.ring * w.ring_words; u += nt) w.ring[u] = 0ull;
   for (int64_t u = tid; u < w.caps.pslots; u += nt) w.cnt[u] = 0;
   for (int64_t u = tid; u < w.n_pairs; u += nt) w.smin[u] = __builtin_nan("");
 }
@@ -195,16 +189,13 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       P.L = min(Mb, Nb);
       P.band_off = (chunk_base + cb) * kBandChunk;
       P.ring_off = ring_base + rb;
-      P.gen_off = 2 * kRing * s;
       const bool ok = (P.band_off + nchunk * kBandChunk <= w.caps.band) &&
-                      (P.ring_off + ring_e <= w.caps.ring) && (chunk_base + cb + nchunk <= w.caps.chunk) &&
-                      (P.gen_off + 2 * kRing <= w.caps.gen);
+                      (P.ring_off + ring_e <= w.caps.ring) && (chunk_base + cb + nchunk <= w.caps.chunk);
       if (!ok) set_error(ctl, kErrBandCap);
-      const int64_t ring0 = P.ring_off, gen0 = P.gen_off;
+      const int64_t ring0 = P.ring_off;
       for (int dir = 0; dir < 2; ++dir) {
         P.dir = dir;
         P.ring_off = ring0 + dir * (int64_t)kRing * Nb;
-        P.gen_off = gen0 + dir * kRing;
         P.kstop = dir ? kb : kf;
         P.n_rows = min(Mb - 1, P.kstop) + 1;
         P.n_stripes = ok ? (P.n_rows + kWave - 1) / kWave : 0;
@@ -591,7 +582,6 @@ __global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, in
   P.L = P.Mb;
   P.band_off = 0;
   P.ring_off = 0;
-  P.gen_off = 0;
   w.passes[0] = P;
   for (int s = 0; s < P.n_stripes; ++s) w.tickets[s] = make_int2(0, s);
   c.n_tickets = P.n_stripes;

@@ -179,38 +179,35 @@ __device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const
 // producers write columns [32k+32, 32k+63], i.e. slots [32k+32, 32k+126]:
 // the two ranges never meet modulo 128.
 //
-// Bottom row hand-off between stripes: a per-sweep HBM ring of kRing rows
-// whose cells hold kRingEmpty until written.  Stripe s writes each value of
-// its bottom row into row s % 2 with a relaxed device-scope atomic store;
-// stripe s+1 polls each value it needs with relaxed device-scope loads until
-// it is not the empty pattern, then stores the empty pattern back and, at
-// the start of its next phase, waits for those stores to complete.  Every
-// value is its own flag, so neither side needs a fence.  Two orderings keep
-// a reused row correct (all chains below run through values one side
-// observed before it issued the next access):
-//  - writer: stripe s+2 writes column c of row s % 2 after computing its own
-//    column c, which needs column c of stripe s+1, which stripe s+1 computes
-//    at least one barrier after its input wave's reset of column c completed;
-//  - reader: stripe s+1 must not read row s % 2 before stripe s-1 has reset
-//    the values stripe s-2 left there.  Chunk p+1 is read only after chunk p
-//    of stripe s arrived, which stripe s computed after receiving column
-//    32p+31 of stripe s-1, published after stripe s-1's resets through chunk
-//    p+1 completed.  For chunk 0 the row's generation word stands in: stripe
-//    s sets it to its tag once it has received its first chunk from stripe
-//    s-1 (at once when s = 0), and stripe s+1 polls it before chunk 0.
+// Bottom row hand-off between stripes: a per-sweep HBM ring of kRing rows of
+// cells.  A cell carries one value and the id of the stripe that wrote it,
+// ring_tag(level, s), in 8-byte words that are each stored and loaded as one
+// relaxed device-scope atomic: a 32-bit half of the value and the id (FP32:
+// one word, FP64: two).  Stripe s publishes its bottom row (lane 63's
+// values, column c at step c + 63) into row s % kRing every kPubGroup
+// steps; the input wave of stripe s+1 polls each word it needs until it
+// carries stripe s's id, one phase ahead, into the LDS row `bring`.  No cell
+// is ever reset and no fence is needed:
+//  - an id is never reused within a call (the ring is cleared to id 0 when
+//    the call starts), so an earlier writer's value or a half-written FP64
+//    value (one word old, one new) never passes for the expected one;
+//  - stripe s + kRing overwrites column c of the row only after computing
+//    its own column c, which needs column c of stripe s + kRing - 1, ...,
+//    which stripe s+1 computed after its input wave's load of column c from
+//    the row had returned: no value is overwritten before it was read.
 // Stripes are dequeued stripe-major across all sweeps of the level, so a
 // stripe only waits on a stripe that a running workgroup dequeued before it:
 // the persistent grid cannot deadlock.
 
-template <typename T> struct RingWord;
-template <> struct RingWord<double> {
-  using U = uint64_t;
-  static constexpr U kEmpty = kRingEmpty64;
-};
-template <> struct RingWord<float> {
-  using U = uint32_t;
-  static constexpr U kEmpty = kRingEmpty32;
-};
+// Words of a ring cell: one per 32-bit half of the value.
+template <typename T>
+constexpr int kCellWords = (int)sizeof(T) / 4;
+
+// Id of stripe s of a level's sweep in the ring cells it writes: nonzero and
+// unique within a call (levels and stripes are below 2^8 and 2^24).
+__device__ __forceinline__ uint32_t ring_tag(int level, int s) {
+  return ((uint32_t)(level + 1) << 24) | (uint32_t)(s + 1);
+}
 
 // A wave-uniform integer moved into a vector register: LDS addresses built
 // from it keep their per-step parts as immediate offsets.
@@ -220,7 +217,6 @@ __device__ __forceinline__ int in_vgpr(int x) {
   return r;
 }
 
-constexpr int kStepGroup = 4;  // recurrence steps whose LDS operands are read together
 
 // Workgroup barrier that waits for this wave's LDS traffic only: global
 // stores in flight (boundary values, band cells) are not waited for.
@@ -234,23 +230,23 @@ __device__ __forceinline__ bool call_failed(const Work& w) {
   return __hip_atomic_load(&w.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Poll one word until it holds a value other than `empty` (or, with
-// `until_equal`, until it equals `empty`'s argument taken as the target).
-// The wait is bounded by the device wall clock (w.spin_ticks) and an
-// iteration cap; on expiry the lane records an error and returns what it
-// read last.  A wait also ends as soon as the call's error word is set, so
-// the first expiry (or any other device error) ends every wait of the
-// call: a broken hand-off costs one wait limit, not one per column.
-template <typename U>
-__device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_equal = false) {
-  U v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if ((v == empty) != until_equal) {
+// Poll one ring word until it carries the id `tag`.  The wait is bounded by
+// the device wall clock (w.spin_ticks) and an iteration cap; on expiry the
+// lane records an error and returns what it read last.  A wait also ends as
+// soon as the call's error word is set, so the first expiry (or any other
+// device error) ends every wait of the call: a broken hand-off costs one
+// wait limit, not one per column.
+__device__ __forceinline__ uint64_t poll_word(const uint64_t* p, uint32_t tag, const Work& w) {
+  uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((uint32_t)(v >> 32) != tag) {
     const uint64_t t0 = wall_clock64();
     for (uint32_t it = 0;; ++it) {
-      if (call_failed(w)) break;
       __builtin_amdgcn_s_sleep(1);
+      // the cell and the error word are loaded together: one memory round
+      // trip per poll
+      const int32_t err = __hip_atomic_load(&w.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if ((v == empty) == until_equal) break;
+      if ((uint32_t)(v >> 32) == tag || err != 0) break;
       if (wall_clock64() - t0 > w.spin_ticks || it > kSpinIterCap) {
         set_error(w.ctl, kErrSpinTimeout);
         break;
@@ -261,19 +257,24 @@ __device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_
 }
 
 // Publish lane 63's values of the steps g0..t (g0 = t rounded down to a
-// multiple of kPubGroup): lane 48+u stores step g0+u, i.e. column g0 + u - 63
-// of the stripe's bottom row.  The values are read from the cost ring: after
-// the recurrence has read the cost of step s from slot s it writes its value
-// of step s into that slot, which the producers do not write again before
-// the phase's closing barrier.
+// multiple of kPubGroup), i.e. the columns g0 + u - 63 of the stripe's
+// bottom row that the next stripe needs (col <= pub_max), with the stripe's
+// id: lane 64 - kPubGroup * kW + i stores word i % kW of step
+// g0 + i / kW.  The values are read from the cost ring: after the recurrence
+// has read the cost of step s from slot s it writes its value of step s into
+// that slot, which the producers do not write again before the phase's
+// closing barrier.
 template <typename T>
-__device__ __forceinline__ void publish(int t, int lane, const T* cring, typename RingWord<T>::U* ring_out,
+__device__ __forceinline__ void publish(int t, int lane, const T* cring, uint64_t* ring_out, uint32_t tag,
                                         int pub_max) {
-  const int st = (t & ~(kPubGroup - 1)) + (lane - (kWave - kPubGroup));
+  constexpr int kW = kCellWords<T>;
+  const int i = lane - (kWave - kPubGroup * kW);
+  const int st = (t & ~(kPubGroup - 1)) + (i >= 0 ? i / kW : 0);
   const int col = st - (kWave - 1);
-  if (lane >= kWave - kPubGroup && st <= t && col >= 0 && col <= pub_max) {
-    const T v = cring[(st & (kCostRing - 1)) * kWave + (kWave - 1)];
-    __hip_atomic_store(ring_out + col, __builtin_bit_cast(typename RingWord<T>::U, v), __ATOMIC_RELAXED,
+  if (i >= 0 && st <= t && col >= 0 && col <= pub_max) {
+    const uint32_t half =
+        reinterpret_cast<const uint32_t*>(cring + (st & (kCostRing - 1)) * kWave + (kWave - 1))[i % kW];
+    __hip_atomic_store(ring_out + (int64_t)col * kW + i % kW, ((uint64_t)tag << 32) | half, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -396,7 +397,6 @@ constexpr bool kPassStagesRows = (!is_gram(CM) && D >= 64) || kStageY<T, CM, D>;
 template <typename T, int D, int CM>
 __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
-  using U = typename RingWord<T>::U;
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
   __shared__ T bring[2 * kPhase];         // bottom row of the stripe above, [column & 63]
   __shared__ int sh_ticket;
@@ -440,10 +440,11 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
     const bool has_pred = s > 0;
     const bool has_succ = s + 1 < P.n_stripes;
     const int pub_max = has_succ ? min(P.Nb - 1, P.kstop - a0 - kWave) : -1;  // = need_max of stripe s+1
-    T* ring = static_cast<T*>(w.ring) + P.ring_off;
-    U* ring_out = reinterpret_cast<U*>(ring + (int64_t)(s % kRing) * P.Nb);
-    U* ring_in = reinterpret_cast<U*>(ring + (int64_t)((s + kRing - 1) % kRing) * P.Nb);
-    const uint32_t my_tag = ((uint32_t)(level + 1) << 20) | (uint32_t)(s + 1);
+    constexpr int kCW = kCellWords<T>;
+    uint64_t* ring = w.ring + P.ring_off * kCW;
+    uint64_t* ring_out = ring + (int64_t)(s % kRing) * P.Nb * kCW;
+    const uint64_t* ring_in = ring + (int64_t)((s + kRing - 1) % kRing) * P.Nb * kCW;
+    const uint32_t tag_out = ring_tag(level, s), tag_in = ring_tag(level, s - 1);
 
     if (wave == 0) {
       // ------------------------------------------------ recurrence
@@ -499,7 +500,8 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
               up_prev = up;
               if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
                 hp[u * kWave] = f;
-                if (has_succ) publish<T>(t0 + u, lane, cring, ring_out, pub_max);
+                __builtin_amdgcn_wave_barrier();  // lane 63's history read by the publishing lanes
+                if (has_succ) publish<T>(t0 + u, lane, cring, ring_out, tag_out, pub_max);
               }
             }
           }
@@ -535,8 +537,8 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
             up_prev = up;
             if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
               hp[u * kWave] = f;
-              __builtin_amdgcn_wave_barrier();  // lane 63's value read by lane 48 + (t & 15), see the leaf
-              if (has_succ) publish<T>(t, lane, cring, ring_out, pub_max);
+              __builtin_amdgcn_wave_barrier();  // lane 63's value read by the publishing lanes
+              if (has_succ) publish<T>(t, lane, cring, ring_out, tag_out, pub_max);
             }
           }
         }
@@ -639,26 +641,17 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
     } else {
       // ------------------------------------------------ boundary input
       stage_barrier<kPassStagesRows<T, CM, D>>();
-      uint32_t* gen_out = w.gens + P.gen_off + s % kRing;
-      uint32_t* gen_in = w.gens + P.gen_off + (s + kRing - 1) % kRing;
-      if (has_pred) (void)poll_cell<uint32_t>(gen_in, my_tag - 1u, w, true);
+      // lanes 0..kPhase*kW-1: word lane % kW of column lane / kW of the chunk
       for (int k = -1; k < n_phases; ++k) {
-        wait_vmem();  // the previous phase's resets have completed
-        const int col = (k + 1) * kPhase + lane;
-        if (lane < kPhase) {
-          T v = INF;
-          if (has_pred && col <= need_max) {
-            const U bits = poll_cell<U>(ring_in + col, RingWord<T>::kEmpty, w);
-            __hip_atomic_store(ring_in + col, RingWord<T>::kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            v = __builtin_bit_cast(T, bits);
-          }
-          bring[col & (2 * kPhase - 1)] = v;
+        const int col = (k + 1) * kPhase + lane / kCW;
+        if (lane < kPhase * kCW) {
+          uint32_t half = (kCW == 2) ? ((lane % 2) ? 0x7FF00000u : 0u) : 0x7F800000u;  // a half of +inf
+          if (has_pred && col <= need_max)
+            half = (uint32_t)poll_word(ring_in + (int64_t)col * kCW + lane % kCW, tag_in, w);
+          reinterpret_cast<uint32_t*>(bring)[(col & (2 * kPhase - 1)) * kCW + lane % kCW] = half;
         }
-        if (k == -1 && lane == 0)  // after the first chunk arrived (see above)
-          __hip_atomic_store(gen_out, my_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         lds_barrier();
       }
-      wait_vmem();
     }
   }
 }
@@ -942,7 +935,7 @@ __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShap
 }
 
 template <typename T, int D, int CM>
-__global__ __launch_bounds__(kPassThreads, 3) void leaf_kernel(
+__global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
     const T* __restrict__ X, const T* __restrict__ Y, Work w, int64_t lds_leaf_bytes, const void* Xorig,
     const void* Yorig, int in_f64, int d) {
   extern __shared__ __align__(16) unsigned char lds_raw[];  // pointers and bottom row when they fit
@@ -1103,11 +1096,11 @@ hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
     DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&pass_kernel<float, D_, kCostGramF16>, grid,
                                                                pass_threads(kCostGramF16), 0, st, nf, nf, w, level))
   } else if (w.precision == DTW_PREC_FP32) {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<float, D_, kCostEuclid>, grid, kPassThreads, 0,
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<float, D_, kCostEuclid>, grid, pass_threads(kCostEuclid), 0,
                                                              st, static_cast<const float*>(w.X),
                                                              static_cast<const float*>(w.Y), w, level))
   } else {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostEuclid>, grid, kPassThreads, 0,
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostEuclid>, grid, pass_threads(kCostEuclid), 0,
                                                              st, static_cast<const double*>(w.X),
                                                              static_cast<const double*>(w.Y), w, level))
   }
@@ -1119,18 +1112,18 @@ hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const vo
   const size_t dyn = (size_t)lds_leaf_bytes;
   const float* nf = nullptr;
   if (w.precision == DTW_PREC_BF16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGram>, grid, kPassThreads,
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGram>, grid, kLeafThreads,
                                                                dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d))
   } else if (w.precision == DTW_PREC_FP16_COST) {
-    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGramF16>, grid, kPassThreads,
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGramF16>, grid, kLeafThreads,
                                                                dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d))
   } else if (w.precision == DTW_PREC_FP32) {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<float, D_, kCostEuclid>, grid, kPassThreads,
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<float, D_, kCostEuclid>, grid, kLeafThreads,
                                                              dyn, st, static_cast<const float*>(w.X),
                                                              static_cast<const float*>(w.Y), w, lds_leaf_bytes, Xo, Yo,
                                                              in_f64, w.d))
   } else {
-    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<double, D_, kCostEuclid>, grid, kPassThreads,
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<double, D_, kCostEuclid>, grid, kLeafThreads,
                                                              dyn, st, static_cast<const double*>(w.X),
                                                              static_cast<const double*>(w.Y), w, lds_leaf_bytes, Xo, Yo,
                                                              in_f64, w.d))

@@ -21,7 +21,7 @@ thread_local std::barrier<>* cpu_wave_barrier = nullptr;
 
 #include "wave_shim.h"
 uint64_t cpu_wave_slots[16][64];
-std::atomic<long> cpu_poll_calls{0};  // boundary waits entered by the wave kernels (instrumented model)
+std::atomic<long> cpu_poll_calls{0};  // boundary-row reads of the wave kernels (instrumented model)
 alignas(16) unsigned char cpu_dynamic_lds[163840];
 #include "dtw_plan_kernels.inc"
 #ifdef MODEL_WAVE
@@ -68,8 +68,8 @@ static char tag_pass[2], tag_leaf[2], tag_plan, tag_init, tag_small, tag_scan;
 
 static const CpuKernelRes* cpu_res_of(const void* fn) {
   using namespace dtw;
-  static const CpuKernelRes pass64{kPassThreads, 8 * kCostRing * kWave + 8 * 2 * kPhase + 64};
-  static const CpuKernelRes pass32{kPassThreads, 4 * kCostRing * kWave + 4 * 2 * kPhase + 64};
+  static const CpuKernelRes pass64{kLeafThreads, 8 * kCostRing * kWave + 8 * 2 * kPhase + 64};
+  static const CpuKernelRes pass32{kLeafThreads, 4 * kCostRing * kWave + 4 * 2 * kPhase + 64};
   static const CpuKernelRes plan{1024, 8 * 1024 + 4 * 1024 + 8};
   static const CpuKernelRes small{1024, 0};
   static const CpuKernelRes scan{1024, 8 * 1024 + 16 * 1024 + 4 * 8 * 1024};
@@ -355,45 +355,45 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
   }
 hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t) {
   MODEL_LAUNCH_CHECK(&tag_pass[w.precision != DTW_PREC_FP64], grid,
-                     is_gram_precision(w.precision) ? pass_threads(kCostGram) : kPassThreads, 0);
+                     is_gram_precision(w.precision) ? pass_threads(kCostGram) : pass_threads(kCostEuclid), 0);
   model_check_queue(w);
   if (w.precision == DTW_PREC_BF16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGram), [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
   } else if (w.precision == DTW_PREC_FP16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGramF16), [&] { pass_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, level); })))
   } else if (w.precision == DTW_PREC_FP32) {
-    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, level); })))
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostEuclid), [&] { pass_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, level); })))
   } else {
-    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { pass_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, level); })))
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostEuclid), [&] { pass_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, level); })))
   }
   return hipSuccess;
 }
 hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
                        hipStream_t) {
-  MODEL_LAUNCH_CHECK(&tag_leaf[w.precision != DTW_PREC_FP64], grid, kPassThreads, (size_t)lds_leaf_bytes);
+  MODEL_LAUNCH_CHECK(&tag_leaf[w.precision != DTW_PREC_FP64], grid, kLeafThreads, (size_t)lds_leaf_bytes);
   model_check_leaves(w);
   if (w.precision == DTW_PREC_BF16_COST) {
-    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostGram>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGram>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else if (w.precision == DTW_PREC_FP16_COST) {
-    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else if (w.precision == DTW_PREC_FP32) {
-    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else {
-    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kPassThreads, [&] { leaf_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   }
   return hipSuccess;
 }
 #else
 hipError_t launch_pass(const Work& w, int, int grid, hipStream_t) {
   MODEL_LAUNCH_CHECK(&tag_pass[w.precision != DTW_PREC_FP64], grid,
-                     is_gram_precision(w.precision) ? pass_threads(kCostGram) : kPassThreads, 0);
+                     is_gram_precision(w.precision) ? pass_threads(kCostGram) : pass_threads(kCostEuclid), 0);
   if (w.precision != DTW_PREC_FP64) model_pass<float>(w);
   else model_pass<double>(w);
   return hipSuccess;
 }
 hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const void* Xo, const void* Yo, int in_f64,
                        hipStream_t) {
-  MODEL_LAUNCH_CHECK(&tag_leaf[w.precision != DTW_PREC_FP64], grid, kPassThreads, (size_t)lds_leaf_bytes);
+  MODEL_LAUNCH_CHECK(&tag_leaf[w.precision != DTW_PREC_FP64], grid, kLeafThreads, (size_t)lds_leaf_bytes);
   if (w.precision != DTW_PREC_FP64) model_leaf<float>(w, Xo, Yo, in_f64);
   else model_leaf<double>(w, Xo, Yo, in_f64);
   return hipSuccess;
@@ -459,9 +459,16 @@ hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag
   else cpu_launch(2, 64, [&] { nonfinite_kernel<float>((const float*)in, n, flag); });
   return hipSuccess;
 }
-hipError_t launch_diag(const Work&, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int, double*,
-                       hipStream_t) {
-  return hipErrorInvalidValue;  // the sweep itself is a wave kernel: GPU tests cover it
+// DiagDTW: the device sequence (init, one-pass setup, the sweep, band copy-out)
+// with the model's sweep (the real wave kernel in the MODEL_WAVE build).
+hipError_t launch_diag(const Work& w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir, int32_t kstop,
+                       int grid, double* out, hipStream_t st) {
+  cpu_launch(2, 64, [&] { init_kernel(w); });
+  cpu_launch(1, 1, [&] { diag_setup_kernel(w, i0, j0, i1, j1, dir, kstop); });
+  const hipError_t e = launch_pass(w, 0, grid, st);
+  if (e != hipSuccess) return e;
+  cpu_launch(2, 64, [&] { diag_out_kernel(w, out); });
+  return hipSuccess;
 }
 
 }  // namespace dtw

@@ -28,6 +28,17 @@ inline T cpu_wave_exchange(T v, int src) {
   return out;
 }
 
+// Bit l set when lane l's predicate holds (all 64 lanes take part).
+inline uint64_t cpu_ballot(bool pred) {
+  uint64_t* slots = cpu_wave_slots[threadIdx.x / 64];
+  slots[cpu_lane()] = pred ? 1u : 0u;
+  cpu_wave_barrier->arrive_and_wait();
+  uint64_t m = 0;
+  for (int l = 0; l < 64; ++l) m |= (slots[l] & 1u) << l;
+  cpu_wave_barrier->arrive_and_wait();
+  return m;
+}
+
 inline int cpu_update_dpp(int old, int src, int ctrl) {
   if (ctrl != 0x138) std::abort();  // only wave_shr:1 is used
   const int v = cpu_wave_exchange(src, cpu_lane() - 1);
@@ -36,6 +47,7 @@ inline int cpu_update_dpp(int old, int src, int ctrl) {
 
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) cpu_update_dpp((old), (src), (ctrl))
 #define __builtin_amdgcn_readfirstlane(v) cpu_wave_exchange((int)(v), 0)
+#define __builtin_amdgcn_ballot_w64(p) cpu_ballot((bool)(p))
 #define __builtin_amdgcn_readlane(v, l) cpu_wave_exchange((int)(v), (int)(l))
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
 #define __builtin_amdgcn_s_barrier() cpu_block_barrier->arrive_and_wait()

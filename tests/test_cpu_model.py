@@ -47,10 +47,10 @@ WAVE_EDITS = [
     ('asm volatile("s_waitcnt lgkmcnt(0)\\n\\ts_barrier" ::: "memory");', "__syncthreads();"),
     ('asm volatile("s_waitcnt vmcnt(0)" ::: "memory");', "std::atomic_thread_fence(std::memory_order_seq_cst);"),
     ("extern __shared__ __align__(16) unsigned char lds_raw[];", "unsigned char* lds_raw = cpu_dynamic_lds;"),
-    # instrumentation: count every boundary wait (poll of a ring cell or a
-    # generation word) that a wave kernel enters
-    ("__device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_equal = false) {\n",
-     "__device__ __forceinline__ U poll_cell(U* p, U empty, const Work& w, bool until_equal = false) {\n"
+    # instrumentation: count every read of a boundary-ring cell, i.e. every
+    # place where a stripe depends on another stripe's published values
+    ("__device__ __forceinline__ uint64_t poll_word(const uint64_t* p, uint32_t tag, const Work& w) {\n",
+     "__device__ __forceinline__ uint64_t poll_word(const uint64_t* p, uint32_t tag, const Work& w) {\n"
      "  cpu_poll_calls.fetch_add(1);\n"),
 ]
 
@@ -120,6 +120,25 @@ def run_model(exe, pairs, m, precision=0, env=None):
     return dict(rc=rc, device_error=derr, levels=levels, leaves=leaves, cells=cells, results=out, polls=polls)
 
 
+def run_model_diag(exe, X, Y, i0, j0, i1, j1, reverse, kstop, precision=0):
+    """DiagDTW (dtw_diag) in the model: (status, device error, (3, Mb) array)."""
+    d = X.shape[1]
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
+        with open(fin, "wb") as f:
+            f.write(struct.pack("4i", -1, d, 0, precision))
+            f.write(struct.pack("8q", X.shape[0], Y.shape[0], i0, j0, i1, j1, reverse, kstop))
+            f.write(np.ascontiguousarray(X, dtype=np.float64).tobytes())
+            f.write(np.ascontiguousarray(Y, dtype=np.float64).tobytes())
+        r = subprocess.run([exe, fin, fout], capture_output=True, timeout=300,
+                           env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+        assert r.returncode == 0, r.stderr.decode()[-3000:]
+        buf = open(fout, "rb").read()
+    rc, derr = struct.unpack_from("2i", buf, 0)
+    Mb = i1 - i0 + 1
+    return rc, derr, np.frombuffer(buf, dtype=np.float64, count=3 * Mb, offset=8).reshape(3, Mb)
+
+
 CASES = [(37, 29, 3, 3), (100, 80, 12, 3), (129, 257, 5, 16), (300, 240, 12, 16), (70, 70, 4, 64),
          (2, 300, 4, 3), (300, 1, 4, 3), (1, 1, 2, 3), (200, 130, 1, 5), (64, 65, 32, 3),
          (2200, 300, 2, 100),  # several scan chunks, > 16 stripes per top-level sweep
@@ -177,8 +196,8 @@ def test_wave_model_matches_oracle(wave_exe, M, N, d, m):
 
 def test_wave_model_single_stripe_case_has_no_wait(wave_exe):
     # 37 x 29 at m = 3: every sweep has at most 34 rows (one stripe) and every
-    # leaf at most 2 rows, so no kernel of this alignment ever enters a
-    # boundary wait; a taller pair at the same cutoff does
+    # leaf at most 2 rows, so no kernel of this alignment ever reads a
+    # boundary row from another stripe; a taller pair at the same cutoff does
     X, Y = synth.random_pair(8000, 37, 29, 3, "normal")
     r = run_model(wave_exe, [(X, Y)], 3)
     assert r["rc"] == 0 and r["device_error"] == 0, r
@@ -274,3 +293,22 @@ def test_wave_model_gram_form(model_exe, wave_exe, M, N, d, m, prec):
     assert r_wave["results"][0][1].tolist() == r_plain["results"][0][1].tolist()
     # the FP64 path cost: compensated per-leaf sums on the device, a plain sum in the model
     assert abs(r_wave["results"][0][0] - r_plain["results"][0][0]) <= 1e-12 * r_plain["results"][0][0]
+
+
+@pytest.mark.parametrize("M,N,d,block,rev,ks", [
+    (70, 50, 12, (0, 0, 69, 49), 0, 60),      # one stripe: full phase, then the band tail
+    (200, 150, 12, (0, 0, 199, 149), 0, 175),  # four stripes chained through the boundary ring
+    (200, 150, 12, (0, 0, 199, 149), 1, 176),  # the same on the reversed series
+    (260, 90, 5, (3, 7, 250, 80), 0, 200),     # sub-block, stripes past the triangle, ragged tail
+    (150, 140, 64, (0, 0, 149, 139), 1, 150),  # wide frames staged in LDS
+])
+def test_wave_model_diag_bitwise(wave_exe, M, N, d, block, rev, ks):
+    # the real sweep kernel (Algorithm 1) lane by lane: every band value equals
+    # the oracle's DiagDTW bit for bit
+    X, Y = synth.random_pair(8200 + M + d, M, N, d, "normal")
+    rc, derr, out = run_model_diag(wave_exe, X, Y, *block, rev, ks)
+    assert rc == 0 and derr == 0
+    ref = oracle.diag(X, Y, *block, rev, ks)
+    assert np.array_equal(np.isnan(out), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(out[ok].view(np.int64), ref[ok].view(np.int64))
