@@ -15,7 +15,8 @@
  * Conventions for every entry point:
  *   - X is M x d and Y is N x d, row-major, one frame per row, contiguous, in
  *     device memory.  Element type is given by dtw_dtype.
- *   - The frame cost is the Euclidean distance (Sec. 4.1).
+ *   - The frame cost is the Euclidean distance (Sec. 4.1), or on request the
+ *     cosine cost that passage discusses (dtw_opts.cost).
  *   - The warping path (Sec. 2.1) is written as int32 pairs (i, j) from (0,0)
  *     to (M-1, N-1); its length lies in [max(M,N), M+N-1].
  *   - Ownership: the caller owns X, Y, the outputs and the workspace; the
@@ -70,6 +71,15 @@ typedef enum {
   DTW_PREC_FP16_COST = 3  /* the same Gram tile from FP16 frames (finer rounding, same rate) */
 } dtw_precision;
 
+/* Frame cost C(i,j) (Sec. 4.1): the Euclidean distance the paper uses, or the
+ * cosine cost it discusses for chroma-type features, 1 - x.y / (|x| |y|) with
+ * a zero frame kept zero, raised to 0 where rounding takes it below.  In
+ * DTW_PREC_FP64 the cosine cost is: each frame divided by its norm (the
+ * correctly rounded square root of the fma chain of its squares in dimension
+ * order; IEEE division), the dot product of the normalised frames as an fma
+ * chain in dimension order, then 1 - dot. */
+typedef enum { DTW_COST_EUCLIDEAN = 0, DTW_COST_COSINE = 1 } dtw_cost;
+
 typedef struct dtw_opts {
   int32_t precision;       /* dtw_precision, default DTW_PREC_FP64                       */
   int32_t min_block;       /* m of Algorithm 2: a block is solved with the full table when
@@ -85,7 +95,10 @@ typedef struct dtw_opts {
                               the device wall clock; 0 = the default of 20 s.  When a wait
                               runs out, the call fails with DTW_ERR_INTERNAL and device
                               error 9, and every other wait of the call ends at once       */
-  int32_t reserved[3];     /* must be zero                                                */
+  int32_t cost;            /* dtw_cost, default DTW_COST_EUCLIDEAN; DTW_COST_COSINE is
+                              available in DTW_PREC_FP64 and DTW_PREC_FP32
+                              (DTW_ERR_UNSUPPORTED with the Gram forms)                  */
+  int32_t reserved[2];     /* must be zero                                                */
 } dtw_opts;
 
 typedef struct dtw_stats {

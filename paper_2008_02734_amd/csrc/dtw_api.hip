@@ -26,6 +26,8 @@ hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* 
                            int32_t* paths, int grid, hipStream_t st);
 hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
                               hipStream_t st);
+hipError_t launch_normalize(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
+                            hipStream_t st);
 hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
                              float* norms,
                              hipStream_t st);
@@ -131,7 +133,7 @@ int frame_width(int d, int precision) {
 
 // Xrows / Yrows: frames of X / Y that the compute copies must cover.
 Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vector<int64_t>& Ns, int d,
-                   int in_dtype, int precision, int m, int64_t Xrows, int64_t Yrows) {
+                   int in_dtype, int precision, int m, int64_t Xrows, int64_t Yrows, int cost) {
   Layout L;
   L.n_pairs = n_pairs;
   int64_t K0sum = 0, Msum = 0, Nsum = 0, Mmax = 0, sub = 0, leaf = 0;
@@ -163,7 +165,8 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   const bool f32 = precision == DTW_PREC_FP32 || gram;  // compute type of the recurrence
   L.cbytes = f32 ? 4 : 8;
   L.D = frame_width(d, precision);
-  L.conv = gram || (f32 && in_dtype == DTW_F64) || (!f32 && in_dtype == DTW_F32) || (L.D != d);
+  L.conv = gram || (f32 && in_dtype == DTW_F64) || (!f32 && in_dtype == DTW_F32) || (L.D != d) ||
+           cost == DTW_COST_COSINE;  // the cosine cost reads normalised copies
   put(L, L.ctl, sizeof(Ctl));  // first, at offset 0: dtw_device_error reads it there
   put(L, L.pairs, sizeof(PairDesc) * n_pairs);
   put(L, L.subs0, sizeof(Block) * c.sub);
@@ -204,8 +207,9 @@ T* at(void* base, const Region& r) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + r.off);
 }
 
-Work make_work(const Layout& L, void* ws, int d, int m, int precision) {
+Work make_work(const Layout& L, void* ws, int d, int m, int precision, int cost) {
   Work w{};
+  w.cost = cost;
   w.ctl = at<Ctl>(ws, L.ctl);
   w.pairs = at<PairDesc>(ws, L.pairs);
   w.n_pairs = L.n_pairs;
@@ -253,8 +257,10 @@ dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
   if (!valid_precision(out->precision)) return DTW_ERR_INVALID_ARG;
   if (out->min_block < 3 || out->min_block > kMaxMinBlock) return DTW_ERR_INVALID_ARG;
   if (out->wait_limit_us < 0) return DTW_ERR_INVALID_ARG;
-  for (int i = 0; i < 3; ++i)
+  if (out->cost != DTW_COST_EUCLIDEAN && out->cost != DTW_COST_COSINE) return DTW_ERR_INVALID_ARG;
+  for (int i = 0; i < 2; ++i)
     if (out->reserved[i] != 0) return DTW_ERR_INVALID_ARG;
+  if (out->cost == DTW_COST_COSINE && is_gram_precision(out->precision)) return DTW_ERR_UNSUPPORTED;
   return DTW_OK;
 }
 
@@ -328,7 +334,7 @@ struct Profiler {
 // squared norms for the Gram form.  Points w.X / w.Y (and w.Xn / w.Yn) at
 // what the kernels read.
 hipError_t stage_inputs(const Layout& L, void* ws, const void* X, const void* Y, int in_f64, int64_t xrows,
-                        int64_t yrows, int d, int precision, Work& w, hipStream_t st) {
+                        int64_t yrows, int d, int precision, int cost, Work& w, hipStream_t st) {
   w.X = X;
   w.Y = Y;
   w.Xn = nullptr;
@@ -345,6 +351,10 @@ hipError_t stage_inputs(const Layout& L, void* ws, const void* X, const void* Y,
     if (e == hipSuccess) e = launch_gram_stage(Y, in_f64, yrows, d, L.D, bf16, static_cast<uint16_t*>(yc), yn, st);
     w.Xn = xn;
     w.Yn = yn;
+  } else if (cost == DTW_COST_COSINE) {
+    const int out_f64 = precision == DTW_PREC_FP64 ? 1 : 0;
+    e = launch_normalize(X, in_f64, xc, out_f64, xrows, d, L.D, st);
+    if (e == hipSuccess) e = launch_normalize(Y, in_f64, yc, out_f64, yrows, d, L.D, st);
   } else {
     const int out_f64 = precision == DTW_PREC_FP64 ? 1 : 0;
     e = launch_pad_convert(X, in_f64, xc, out_f64, xrows, d, L.D, st);
@@ -389,7 +399,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
     Ntot = std::max(Ntot, yo[b + 1]);
   }
   const int m = opts.min_block;
-  Layout L = plan_layout(n_pairs, Ms, Ns, d, in_dtype, opts.precision, m, Mtot, Ntot);
+  Layout L = plan_layout(n_pairs, Ms, Ns, d, in_dtype, opts.precision, m, Mtot, Ntot, opts.cost);
   if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
   const bool f32 = opts.precision != DTW_PREC_FP64;  // FP32 recurrence (FP32 and Gram forms)
   const int in_f64 = in_dtype == DTW_F64;
@@ -412,12 +422,12 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
 
   Profiler prof;
   HIP_TRY(prof.init(opts.profile != 0 && stats != nullptr, opts.profile == 2, st));
-  Work w = make_work(L, ws, d, m, opts.precision);
+  Work w = make_work(L, ws, d, m, opts.precision, opts.cost);
   if (device_error_word) *device_error_word = &w.ctl->error;
   w.X = X;
   w.Y = Y;
   w.spin_ticks = wait_ticks(I, opts.wait_limit_us);
-  PROF_TRY(prof, kProfOther, stage_inputs(L, ws, X, Y, in_f64, Mtot, Ntot, d, opts.precision, w, st));
+  PROF_TRY(prof, kProfOther, stage_inputs(L, ws, X, Y, in_f64, Mtot, Ntot, d, opts.precision, opts.cost, w, st));
   HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
   PROF_TRY(prof, kProfOther, launch_init(w, st));
 
@@ -596,7 +606,7 @@ dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
   if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
   if (frame_width(d, opts.precision) == 0) return DTW_ERR_UNSUPPORTED;
   std::vector<int64_t> Ms{M}, Ns{N};
-  *bytes = plan_layout(1, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, M, N).total;
+  *bytes = plan_layout(1, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, M, N, opts.cost).total;
   return DTW_OK;
 }
 
@@ -655,7 +665,7 @@ dtw_status dtw_workspace_size_batched(int32_t B, const int64_t* x_offsets, const
     Xrows = std::max(Xrows, x_offsets[b + 1]);
     Yrows = std::max(Yrows, y_offsets[b + 1]);
   }
-  *bytes = plan_layout(B, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, Xrows, Yrows).total;
+  *bytes = plan_layout(B, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, Xrows, Yrows, opts.cost).total;
   return DTW_OK;
 }
 
@@ -682,16 +692,16 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype, i
   const int in_f64 = in_dtype == DTW_F64;
   std::vector<int64_t> Ms{Mb}, Ns{Nb};
   // same layout as dtw_workspace_size(i1+1, j1+1, d, in_dtype, opts with this precision)
-  Layout L = plan_layout(1, Ms, Ns, d, in_dtype, precision, 500, i1 + 1, j1 + 1);
+  Layout L = plan_layout(1, Ms, Ns, d, in_dtype, precision, 500, i1 + 1, j1 + 1, DTW_COST_EUCLIDEAN);
   {
     std::vector<int64_t> Mf{i1 + 1}, Nf{j1 + 1};
-    Layout Lf = plan_layout(1, Mf, Nf, d, in_dtype, precision, 500, i1 + 1, j1 + 1);
+    Layout Lf = plan_layout(1, Mf, Nf, d, in_dtype, precision, 500, i1 + 1, j1 + 1, DTW_COST_EUCLIDEAN);
     if (Lf.total > L.total) L = Lf;
   }
   if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  Work w = make_work(L, workspace, d, 500, precision);
-  HIP_TRY(stage_inputs(L, workspace, X, Y, in_f64, i1 + 1, j1 + 1, d, precision, w, st));
+  Work w = make_work(L, workspace, d, 500, precision, DTW_COST_EUCLIDEAN);
+  HIP_TRY(stage_inputs(L, workspace, X, Y, in_f64, i1 + 1, j1 + 1, d, precision, DTW_COST_EUCLIDEAN, w, st));
   w.bandC = nullptr;
   DevInfo& I = dev_info();
   w.spin_ticks = wait_ticks(I, 0);

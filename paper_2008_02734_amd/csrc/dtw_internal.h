@@ -29,12 +29,15 @@ constexpr int kCostRing = 128;  // LDS cost slots, indexed by step
 constexpr int kPubGroup = 16;   // steps per bottom-row publication (sweep and leaf)
 constexpr int kStepGroup = 4;   // recurrence steps whose operands are read together
 
-// Frame cost forms: the exact Euclidean cost on the VALU (FP64 or FP32), or
-// the Gram form on the matrix cores (dtw_gram.h) from BF16 or FP16 frames.
+// Frame cost forms: the exact Euclidean cost on the VALU (FP64 or FP32), the
+// Gram form on the matrix cores (dtw_gram.h) from BF16 or FP16 frames, or the
+// cosine cost on the VALU from frames normalised at staging.
 constexpr int kCostEuclid = 0;
 constexpr int kCostGram = 1;     // BF16 frames
 constexpr int kCostGramF16 = 2;  // FP16 frames
-constexpr bool is_gram(int cm) { return cm != kCostEuclid; }
+constexpr int kCostCosine = 3;   // 1 - dot product of the normalised frames
+constexpr bool is_gram(int cm) { return cm == kCostGram || cm == kCostGramF16; }
+constexpr bool is_cos(int cm) { return cm == kCostCosine; }
 // Producer waves of a sweep workgroup: the Gram form needs only two (its
 // matrix-core tiles are cheap), which makes its workgroup 4 waves and lets
 // four workgroups share a CU; the Euclidean forms use eight.
@@ -133,6 +136,7 @@ struct Work {
   int32_t min_block;
   int32_t d;
   int32_t precision;
+  int32_t cost;         // DTW_COST_EUCLIDEAN or DTW_COST_COSINE
   const void* X;        // compute-type copies (or the caller's arrays); bf16 in the Gram form
   const void* Y;
   const float* Xn;      // Gram form: squared norms of the bf16 frames, FP32

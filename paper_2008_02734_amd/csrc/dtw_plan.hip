@@ -497,6 +497,22 @@ __global__ void pad_convert_kernel(const TI* in, TO* out, int64_t rows, int d, i
   }
 }
 
+// Normalised compute-type copy for the cosine cost (Sec. 4.1), one frame per
+// thread, in FP64: each frame divided by its norm, the correctly rounded
+// square root of the fma chain of its squares in dimension order (IEEE
+// division; a zero frame stays zero), zero-padded from d to D dimensions.
+template <typename TO, typename TI>
+__global__ void normalize_kernel(const TI* in, TO* out, int64_t rows, int d, int D) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+    const TI* x = in + r * d;
+    double n = 0.0;
+    for (int t = 0; t < d; ++t) n = __builtin_fma((double)x[t], (double)x[t], n);
+    n = __builtin_sqrt(n);
+    TO* o = out + r * D;
+    for (int t = 0; t < D; ++t) o[t] = (t < d && n > 0.0) ? (TO)((double)x[t] / n) : (TO)0;
+  }
+}
+
 template <typename TI>
 __global__ void nonfinite_kernel(const TI* in, int64_t n, int32_t* flag) {
   for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
@@ -630,6 +646,21 @@ hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64
     return launch_checked(&pad_convert_kernel<double, float>, grid, 256, 0, st, static_cast<const float*>(in),
                           static_cast<double*>(out), rows, d, D);
   return launch_checked(&pad_convert_kernel<float, float>, grid, 256, 0, st, static_cast<const float*>(in),
+                        static_cast<float*>(out), rows, d, D);
+}
+hipError_t launch_normalize(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
+                            hipStream_t st) {
+  const int grid = (int)min((int64_t)2048, (rows + 255) / 256 + 1);
+  if (in_f64 && out_f64)
+    return launch_checked(&normalize_kernel<double, double>, grid, 256, 0, st, static_cast<const double*>(in),
+                          static_cast<double*>(out), rows, d, D);
+  if (in_f64)
+    return launch_checked(&normalize_kernel<float, double>, grid, 256, 0, st, static_cast<const double*>(in),
+                          static_cast<float*>(out), rows, d, D);
+  if (out_f64)
+    return launch_checked(&normalize_kernel<double, float>, grid, 256, 0, st, static_cast<const float*>(in),
+                          static_cast<double*>(out), rows, d, D);
+  return launch_checked(&normalize_kernel<float, float>, grid, 256, 0, st, static_cast<const float*>(in),
                         static_cast<float*>(out), rows, d, D);
 }
 hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,

@@ -64,32 +64,54 @@ __device__ __forceinline__ float wave_shr1(float old, float v) {
       __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), kDppWaveShr1, 0xf, 0xf, false));
 }
 
+// One dimension of a frame cost, and its final form.  Euclidean cost
+// (Sec. 4.1): s = fma(e, e, s) with e = x_t - y_t, then the square root.
+// Cosine cost (frames normalised at staging): s = fma(x_t, y_t, s), then
+// 1 - s, raised to 0 where rounding takes it below.
+template <bool kCos, typename T>
+__device__ __forceinline__ T cost_acc(T x, T y, T s) {
+  if constexpr (kCos) {
+    return fma_t(x, y, s);
+  } else {
+    const T e = x - y;
+    return fma_t(e, e, s);
+  }
+}
+template <bool kCos, typename T>
+__device__ __forceinline__ T cost_fin(T s) {
+  if constexpr (kCos) {
+    const T c = T(1) - s;
+    return c < T(0) ? T(0) : c;
+  } else {
+    return sqrt_t(s);
+  }
+}
+
 // Euclidean frame cost (Sec. 4.1): sum over t of fma(e, e, s), e = x_t - y_t,
-// in dimension order, then the square root.  Frames are zero-padded to D
+// in dimension order, then the square root (the cosine form likewise with
+// cost_acc / cost_fin).  Frames are zero-padded to D
 // dimensions; a padded dimension contributes fma(0, 0, s) = s exactly.  x is
 // the lane's own frame in registers; y0 and y1 are wave-uniform frames (the
 // leaf reads them with scalar loads).  Two Y frames at once give two
 // independent fma chains.
-template <typename T, int D>
+template <typename T, int D, bool kCos = false>
 __device__ __forceinline__ void frame_cost2(const T (&x)[D], const T* __restrict__ y0, const T* __restrict__ y1,
                                             T& c0, T& c1) {
   T s0 = T(0), s1 = T(0);
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const T e0 = x[k] - y0[k];
-    const T e1 = x[k] - y1[k];
-    s0 = fma_t(e0, e0, s0);
-    s1 = fma_t(e1, e1, s1);
+    s0 = cost_acc<kCos>(x[k], y0[k], s0);
+    s1 = cost_acc<kCos>(x[k], y1[k], s1);
   }
-  c0 = sqrt_t(s0);
-  c1 = sqrt_t(s1);
+  c0 = cost_fin<kCos>(s0);
+  c1 = cost_fin<kCos>(s1);
 }
 
 // The same two costs with the Y frames in LDS (broadcast reads), KC
 // dimensions at a time: the scheduling barrier keeps the compiler from
 // hoisting every read ahead of the arithmetic, which would hold 2D values in
 // registers; the other producer waves on the SIMD cover the read latency.
-template <typename T, int D>
+template <typename T, int D, bool kCos = false>
 __device__ __forceinline__ void frame_cost2_lds(const T (&x)[D], const T* __restrict__ y0, const T* __restrict__ y1,
                                                 T& c0, T& c1) {
   constexpr int KC = (sizeof(T) == 8 && D >= 24) ? 2 : 4;
@@ -105,15 +127,13 @@ __device__ __forceinline__ void frame_cost2_lds(const T (&x)[D], const T* __rest
     }
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
-      const T e0 = x[k0 + q] - a[q];
-      const T e1 = x[k0 + q] - b[q];
-      s0 = fma_t(e0, e0, s0);
-      s1 = fma_t(e1, e1, s1);
+      s0 = cost_acc<kCos>(x[k0 + q], a[q], s0);
+      s1 = cost_acc<kCos>(x[k0 + q], b[q], s1);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
-  c0 = sqrt_t(s0);
-  c1 = sqrt_t(s1);
+  c0 = cost_fin<kCos>(s0);
+  c1 = cost_fin<kCos>(s1);
 }
 
 // Frame widths of 64 and more: the lane's frame xl is read in chunks of 16
@@ -122,7 +142,7 @@ __device__ __forceinline__ void frame_cost2_lds(const T (&x)[D], const T* __rest
 // register use stays bounded and every cost keeps the dimension order of
 // frame_cost2.  kUnroll chunks are unrolled (the leaf, with more live state,
 // takes 1 to stay within its registers).
-template <typename T, int D, int kUnroll>
+template <typename T, int D, int kUnroll, bool kCos = false>
 __device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const T* __restrict__ y0,
                                                  const T* __restrict__ y1, const T* __restrict__ y2,
                                                  const T* __restrict__ y3, T (&c)[4]) {
@@ -136,20 +156,16 @@ __device__ __forceinline__ void frame_cost4_wide(const T* __restrict__ xl, const
     for (int q = 0; q < KC; ++q) xc[q] = xl[kc + q];
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
-      const T e0 = xc[q] - y0[kc + q];
-      const T e1 = xc[q] - y1[kc + q];
-      const T e2 = xc[q] - y2[kc + q];
-      const T e3 = xc[q] - y3[kc + q];
-      s0 = fma_t(e0, e0, s0);
-      s1 = fma_t(e1, e1, s1);
-      s2 = fma_t(e2, e2, s2);
-      s3 = fma_t(e3, e3, s3);
+      s0 = cost_acc<kCos>(xc[q], y0[kc + q], s0);
+      s1 = cost_acc<kCos>(xc[q], y1[kc + q], s1);
+      s2 = cost_acc<kCos>(xc[q], y2[kc + q], s2);
+      s3 = cost_acc<kCos>(xc[q], y3[kc + q], s3);
     }
   }
-  c[0] = sqrt_t(s0);
-  c[1] = sqrt_t(s1);
-  c[2] = sqrt_t(s2);
-  c[3] = sqrt_t(s3);
+  c[0] = cost_fin<kCos>(s0);
+  c[1] = cost_fin<kCos>(s1);
+  c[2] = cost_fin<kCos>(s2);
+  c[3] = cost_fin<kCos>(s3);
 }
 
 // ----------------------------------------------------------------- pass kernel
@@ -390,7 +406,7 @@ __device__ __forceinline__ void gram_stage_barrier() {
 // once per frame chunk, which is slow when the workgroups of a batch read
 // frames of many different pairs.
 template <typename T, int CM, int D>
-constexpr bool kStageY = (CM == kCostEuclid) && (D <= 32);
+constexpr bool kStageY = !is_gram(CM) && (D <= 32);
 template <typename T, int CM, int D>
 constexpr bool kPassStagesRows = (!is_gram(CM) && D >= 64) || kStageY<T, CM, D>;
 
@@ -576,7 +592,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
               gj[i] = __builtin_amdgcn_readfirstlane(P.dir ? P.j1 - jc : P.j0 + jc);
             }
             T cv[4];
-            frame_cost4_wide<T, D, 2>(xl, Y + (int64_t)gj[0] * D, Y + (int64_t)gj[1] * D, Y + (int64_t)gj[2] * D,
+            frame_cost4_wide<T, D, 2, is_cos(CM)>(xl, Y + (int64_t)gj[0] * D, Y + (int64_t)gj[1] * D, Y + (int64_t)gj[2] * D,
                                    Y + (int64_t)gj[3] * D, cv);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -628,7 +644,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
             for (int i = 0; i < kPhase / kProducers; i += 2) {
               const int jj0 = pw + i * kProducers, jj1 = jj0 + kProducers;
               T cv0, cv1;
-              frame_cost2_lds<T, D>(x, yb + jj0 * D, yb + jj1 * D, cv0, cv1);
+              frame_cost2_lds<T, D, is_cos(CM)>(x, yb + jj0 * D, yb + jj1 * D, cv0, cv1);
               cring[((c0 + jj0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
               cring[((c0 + jj1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
             }
@@ -818,7 +834,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
 #pragma unroll
             for (int i = 0; i < 4; ++i) gj[i] = __builtin_amdgcn_readfirstlane(S.c0 + min(cb0 + pw + i * kProducers, S.Cc - 1));
             T cv[4];
-            frame_cost4_wide<T, D, 1>(xl, ColSrc + (int64_t)gj[0] * D, ColSrc + (int64_t)gj[1] * D,
+            frame_cost4_wide<T, D, 1, is_cos(CM)>(xl, ColSrc + (int64_t)gj[0] * D, ColSrc + (int64_t)gj[1] * D,
                                    ColSrc + (int64_t)gj[2] * D, ColSrc + (int64_t)gj[3] * D, cv);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -846,7 +862,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
               const int gj0 = __builtin_amdgcn_readfirstlane(S.c0 + min(j0, S.Cc - 1));
               const int gj1 = __builtin_amdgcn_readfirstlane(S.c0 + min(j1, S.Cc - 1));
               T cv0, cv1;
-              frame_cost2<T, D>(x, ColSrc + (int64_t)gj0 * D, ColSrc + (int64_t)gj1 * D, cv0, cv1);
+              frame_cost2<T, D, is_cos(CM)>(x, ColSrc + (int64_t)gj0 * D, ColSrc + (int64_t)gj1 * D, cv0, cv1);
               cring[((j0 + lane) & (kCostRing - 1)) * kWave + lane] = cv0;
               cring[((j1 + lane) & (kCostRing - 1)) * kWave + lane] = cv1;
             }
@@ -934,6 +950,35 @@ __device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShap
   return cnt;
 }
 
+// The FP64 frame cost of one path cell from the caller's frames (FP64 or
+// FP32, widened): the Euclidean cost, or the cosine cost with each frame
+// divided by its norm (a zero frame kept zero).
+template <bool kCos, typename TI>
+__device__ __forceinline__ double path_cell_cost(const TI* xr, const TI* yr, int d) {
+  if constexpr (kCos) {
+    double nx = 0.0, ny = 0.0;
+    for (int k = 0; k < d; ++k) nx = __builtin_fma((double)xr[k], (double)xr[k], nx);
+    for (int k = 0; k < d; ++k) ny = __builtin_fma((double)yr[k], (double)yr[k], ny);
+    nx = __builtin_sqrt(nx);
+    ny = __builtin_sqrt(ny);
+    double ss = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double xk = nx > 0.0 ? (double)xr[k] / nx : 0.0;
+      const double yk = ny > 0.0 ? (double)yr[k] / ny : 0.0;
+      ss = __builtin_fma(xk, yk, ss);
+    }
+    const double c = 1.0 - ss;
+    return c < 0.0 ? 0.0 : c;
+  } else {
+    double ss = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double ee = (double)xr[k] - (double)yr[k];
+      ss = __builtin_fma(ee, ee, ss);
+    }
+    return __builtin_sqrt(ss);
+  }
+}
+
 template <typename T, int D, int CM>
 __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
     const T* __restrict__ X, const T* __restrict__ Y, Work w, int64_t lds_leaf_bytes, const void* Xorig,
@@ -1014,17 +1059,11 @@ __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
       for (int q = lane; q < cnt_written; q += kWave) {
         const int2 cell = w.tpath[slot_end - cnt_written + 1 + q];
         const int64_t gi = pd.x_off + cell.x, gj = pd.y_off + cell.y;
-        double ss = 0.0;
-        if (in_f64) {
-          const double* xr = static_cast<const double*>(Xorig) + gi * d;
-          const double* yr = static_cast<const double*>(Yorig) + gj * d;
-          for (int k = 0; k < d; ++k) { const double ee = xr[k] - yr[k]; ss = __builtin_fma(ee, ee, ss); }
-        } else {
-          const float* xr = static_cast<const float*>(Xorig) + gi * d;
-          const float* yr = static_cast<const float*>(Yorig) + gj * d;
-          for (int k = 0; k < d; ++k) { const double ee = (double)xr[k] - (double)yr[k]; ss = __builtin_fma(ee, ee, ss); }
-        }
-        acc = two_sum_acc(acc, __builtin_sqrt(ss));
+        const double c = in_f64 ? path_cell_cost<is_cos(CM)>(static_cast<const double*>(Xorig) + gi * d,
+                                                              static_cast<const double*>(Yorig) + gj * d, d)
+                                : path_cell_cost<is_cos(CM)>(static_cast<const float*>(Xorig) + gi * d,
+                                                              static_cast<const float*>(Yorig) + gj * d, d);
+        acc = two_sum_acc(acc, c);
       }
       // fixed-order tree reduction over the wave
       for (int off = 1; off < kWave; off <<= 1) {
@@ -1095,10 +1134,18 @@ hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
   } else if (w.precision == DTW_PREC_FP16_COST) {
     DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&pass_kernel<float, D_, kCostGramF16>, grid,
                                                                pass_threads(kCostGramF16), 0, st, nf, nf, w, level))
+  } else if (w.precision == DTW_PREC_FP32 && w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<float, D_, kCostCosine>, grid, pass_threads(kCostCosine), 0,
+                                                             st, static_cast<const float*>(w.X),
+                                                             static_cast<const float*>(w.Y), w, level))
   } else if (w.precision == DTW_PREC_FP32) {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<float, D_, kCostEuclid>, grid, pass_threads(kCostEuclid), 0,
                                                              st, static_cast<const float*>(w.X),
                                                              static_cast<const float*>(w.Y), w, level))
+  } else if (w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostCosine>, grid, pass_threads(kCostCosine), 0,
+                                                             st, static_cast<const double*>(w.X),
+                                                             static_cast<const double*>(w.Y), w, level))
   } else {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostEuclid>, grid, pass_threads(kCostEuclid), 0,
                                                              st, static_cast<const double*>(w.X),
@@ -1117,10 +1164,20 @@ hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const vo
   } else if (w.precision == DTW_PREC_FP16_COST) {
     DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGramF16>, grid, kLeafThreads,
                                                                dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d))
+  } else if (w.precision == DTW_PREC_FP32 && w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<float, D_, kCostCosine>, grid, kLeafThreads,
+                                                             dyn, st, static_cast<const float*>(w.X),
+                                                             static_cast<const float*>(w.Y), w, lds_leaf_bytes, Xo, Yo,
+                                                             in_f64, w.d))
   } else if (w.precision == DTW_PREC_FP32) {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<float, D_, kCostEuclid>, grid, kLeafThreads,
                                                              dyn, st, static_cast<const float*>(w.X),
                                                              static_cast<const float*>(w.Y), w, lds_leaf_bytes, Xo, Yo,
+                                                             in_f64, w.d))
+  } else if (w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<double, D_, kCostCosine>, grid, kLeafThreads,
+                                                             dyn, st, static_cast<const double*>(w.X),
+                                                             static_cast<const double*>(w.Y), w, lds_leaf_bytes, Xo, Yo,
                                                              in_f64, w.d))
   } else {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&leaf_kernel<double, D_, kCostEuclid>, grid, kLeafThreads,
@@ -1152,6 +1209,12 @@ hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32) {
   M_(float, 4, kCostEuclid, 1) M_(float, 8, kCostEuclid, 1) M_(float, 12, kCostEuclid, 1)                 \
   M_(float, 16, kCostEuclid, 1) M_(float, 24, kCostEuclid, 1) M_(float, 32, kCostEuclid, 1)               \
   M_(float, 64, kCostEuclid, 1) M_(float, 128, kCostEuclid, 1)                                            \
+  M_(double, 4, kCostCosine, 0) M_(double, 8, kCostCosine, 0) M_(double, 12, kCostCosine, 0)              \
+  M_(double, 16, kCostCosine, 0) M_(double, 24, kCostCosine, 0) M_(double, 32, kCostCosine, 0)            \
+  M_(double, 64, kCostCosine, 0) M_(double, 128, kCostCosine, 0)                                          \
+  M_(float, 4, kCostCosine, 1) M_(float, 8, kCostCosine, 1) M_(float, 12, kCostCosine, 1)                 \
+  M_(float, 16, kCostCosine, 1) M_(float, 24, kCostCosine, 1) M_(float, 32, kCostCosine, 1)               \
+  M_(float, 64, kCostCosine, 1) M_(float, 128, kCostCosine, 1)                                            \
   M_(float, 32, kCostGram, 1) M_(float, 64, kCostGram, 1) M_(float, 128, kCostGram, 1)                   \
   M_(float, 32, kCostGramF16, 1) M_(float, 64, kCostGramF16, 1) M_(float, 128, kCostGramF16, 1)
   DTW_LEAF_ALL(DTW_LEAF_STATIC)

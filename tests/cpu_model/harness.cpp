@@ -136,6 +136,14 @@ static float model_gram_cost(const uint16_t* x, const uint16_t* y, float nx, flo
 
 // The frame cost of (gi, gj) in the form the Work asks for.
 template <typename T>
+static T model_cos_cost(const T* x, const T* y, int D) {  // frames normalised at staging
+  T s = T(0);
+  for (int k = 0; k < D; ++k) s = std::fma(x[k], y[k], s);
+  const T c = T(1) - s;
+  return c < T(0) ? T(0) : c;
+}
+
+template <typename T>
 static T model_frame_cost(const Work& w, int64_t gi, int64_t gj) {
   if (is_gram_precision(w.precision)) {
     const int D = pick_dgram(w.d);
@@ -143,6 +151,8 @@ static T model_frame_cost(const Work& w, int64_t gi, int64_t gj) {
                               w.Xn[gi], w.Yn[gj], D, w.precision == DTW_PREC_BF16_COST);
   }
   const int D = pick_dmax(w.d);
+  if (w.cost == DTW_COST_COSINE)
+    return model_cos_cost(static_cast<const T*>(w.X) + gi * D, static_cast<const T*>(w.Y) + gj * D, D);
   return model_cost(static_cast<const T*>(w.X) + gi * D, static_cast<const T*>(w.Y) + gj * D, D);
 }
 
@@ -307,13 +317,29 @@ static void model_leaf(const Work& w, const void* Xo, const void* Yo, int in_f64
         w.tpath[slot_end - cnt] = make_int2((int)(Lf.i0 + i - pd.x_off), (int)(Lf.j0 + j - pd.y_off));
         ++cnt;
         const int64_t gi = Lf.i0 + i, gj = Lf.j0 + j;
-        double s = 0.0;
+        std::vector<double> xv(d), yv(d);
         for (int k = 0; k < d; ++k) {
-          const double ee = in_f64 ? static_cast<const double*>(Xo)[gi * d + k] - static_cast<const double*>(Yo)[gj * d + k]
-                                   : (double)static_cast<const float*>(Xo)[gi * d + k] - (double)static_cast<const float*>(Yo)[gj * d + k];
-          s = std::fma(ee, ee, s);
+          xv[k] = in_f64 ? static_cast<const double*>(Xo)[gi * d + k] : (double)static_cast<const float*>(Xo)[gi * d + k];
+          yv[k] = in_f64 ? static_cast<const double*>(Yo)[gj * d + k] : (double)static_cast<const float*>(Yo)[gj * d + k];
         }
-        cost += std::sqrt(s);
+        if (w.cost == DTW_COST_COSINE) {
+          double nx = 0.0, ny = 0.0;
+          for (int k = 0; k < d; ++k) nx = std::fma(xv[k], xv[k], nx);
+          for (int k = 0; k < d; ++k) ny = std::fma(yv[k], yv[k], ny);
+          nx = std::sqrt(nx);
+          ny = std::sqrt(ny);
+          double s = 0.0;
+          for (int k = 0; k < d; ++k) s = std::fma(nx > 0.0 ? xv[k] / nx : 0.0, ny > 0.0 ? yv[k] / ny : 0.0, s);
+          const double c = 1.0 - s;
+          cost += c < 0.0 ? 0.0 : c;
+        } else {
+          double s = 0.0;
+          for (int k = 0; k < d; ++k) {
+            const double ee = xv[k] - yv[k];
+            s = std::fma(ee, ee, s);
+          }
+          cost += std::sqrt(s);
+        }
       }
       if (at_start) break;
       const unsigned char mv = (i == 0) ? 2 : (j == 0) ? 1 : P[(size_t)i * Nb + j];
@@ -361,8 +387,12 @@ hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGram), [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
   } else if (w.precision == DTW_PREC_FP16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGramF16), [&] { pass_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, level); })))
+  } else if (w.precision == DTW_PREC_FP32 && w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostCosine), [&] { pass_kernel<float, D_, kCostCosine>((const float*)w.X, (const float*)w.Y, w, level); })))
   } else if (w.precision == DTW_PREC_FP32) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostEuclid), [&] { pass_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, level); })))
+  } else if (w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostCosine), [&] { pass_kernel<double, D_, kCostCosine>((const double*)w.X, (const double*)w.Y, w, level); })))
   } else {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostEuclid), [&] { pass_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, level); })))
   }
@@ -376,8 +406,12 @@ hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const vo
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGram>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else if (w.precision == DTW_PREC_FP16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  } else if (w.precision == DTW_PREC_FP32 && w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostCosine>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else if (w.precision == DTW_PREC_FP32) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  } else if (w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<double, D_, kCostCosine>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<double, D_, kCostEuclid>((const double*)w.X, (const double*)w.Y, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   }
@@ -432,6 +466,18 @@ hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* 
   cpu_launch(2, 64, [&] { leaf_index_kernel(w, lidx); });
   cpu_launch(w.n_pairs, 128, [&] { scan_kernel(w, poff, lidx, costs, lens); });
   cpu_launch(2, 64, [&] { copy_kernel(w, poff, paths); });
+  return hipSuccess;
+}
+hipError_t launch_normalize(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
+                            hipStream_t) {
+  if (in_f64 && out_f64)
+    cpu_launch(2, 64, [&] { normalize_kernel<double, double>((const double*)in, (double*)out, rows, d, D); });
+  else if (in_f64)
+    cpu_launch(2, 64, [&] { normalize_kernel<float, double>((const double*)in, (float*)out, rows, d, D); });
+  else if (out_f64)
+    cpu_launch(2, 64, [&] { normalize_kernel<double, float>((const float*)in, (double*)out, rows, d, D); });
+  else
+    cpu_launch(2, 64, [&] { normalize_kernel<float, float>((const float*)in, (float*)out, rows, d, D); });
   return hipSuccess;
 }
 hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,

@@ -62,6 +62,10 @@ def test_argument_errors_before_any_device_work():
     assert _align(L, opts=bad) == -1
     bad = dtw.make_opts(precision=9)
     assert _align(L, opts=bad) == -1
+    bad = dtw.make_opts(cost=5)
+    assert _align(L, opts=bad) == -1      # unknown frame cost
+    bad = dtw.make_opts(precision="bf16", cost="cosine")
+    assert _align(L, opts=bad) == -8      # cosine cost: FP64 and FP32 forms only
 
 
 def test_workspace_size_errors():

@@ -90,12 +90,12 @@ def wave_exe(tmp_path_factory):
     return _build_model(tmp_path_factory.mktemp("cpu_model_wave"), wave=True)
 
 
-def run_model(exe, pairs, m, precision=0, env=None):
+def run_model(exe, pairs, m, precision=0, env=None, cost=0):
     d = pairs[0][0].shape[1]
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
         with open(fin, "wb") as f:
-            f.write(struct.pack("4i", len(pairs), d, m, precision))
+            f.write(struct.pack("4i", len(pairs), d, m, precision | (cost << 8)))
             for X, Y in pairs:
                 f.write(struct.pack("2q", X.shape[0], Y.shape[0]))
             for X, _ in pairs:
@@ -312,3 +312,23 @@ def test_wave_model_diag_bitwise(wave_exe, M, N, d, block, rev, ks):
     assert np.array_equal(np.isnan(out), np.isnan(ref))
     ok = ~np.isnan(ref)
     assert np.array_equal(out[ok].view(np.int64), ref[ok].view(np.int64))
+
+
+@pytest.mark.parametrize("M,N,d,m,prec", [(130, 90, 12, 16, 0), (90, 110, 5, 8, 0), (80, 70, 64, 16, 0),
+                                          (100, 80, 12, 16, 1)])
+def test_wave_model_cosine(model_exe, wave_exe, M, N, d, m, prec):
+    # the cosine frame cost (Sec. 4.1): the real kernels lane by lane give the
+    # oracle's textbook path under the cosine cost in FP64, and the FP32 form
+    # lies within 1e-5 of its optimum; the plain-loop model agrees
+    X, Y = synth.make_pair(8300, M + d, M, N, d, "chroma")
+    for exe in (model_exe, wave_exe):
+        r = run_model(exe, [(X, Y)], m, precision=prec, cost=1)
+        assert r["rc"] == 0 and r["device_error"] == 0, r
+        cost, path = r["results"][0]
+        c_ref, p_ref = oracle.full(X, Y, cost="cosine")
+        assert oracle.path_cost(X, Y, path, cost="cosine") == pytest.approx(cost, rel=1e-12)
+        if prec == 0:
+            assert path.tolist() == p_ref.tolist()
+            assert abs(cost - c_ref) <= 1e-12 * c_ref
+        else:
+            assert (cost - c_ref) / c_ref <= 1e-5 and cost >= c_ref * (1 - 1e-12)
