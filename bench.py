@@ -13,9 +13,19 @@ VALU peak divided by the algorithmic VALU slots one cell needs.  kernel_ms is
 the per-class breakdown from untimed runs with events around every launch.  The CPU baseline is the oracle's textbook full-table
 DTW timed single-threaded on this host.
 
+The default run also measures, in the same process, the two other targets
+of the method's AI-systems forms (unless --no-extras):
+  long_pair  the 200000 x 160000, d = 128 pair in the BF16 and FP16 Gram
+             forms, each against the all-FP64 path on the same input (time,
+             relative cost error, frame deviation of the path);
+  serving    a Poisson stream of 96 requests, M log-uniform in [2000, 400000],
+             through the serving loop in the BF16 and FP16 mixes, against every
+             request one at a time through the plain FP64 path (throughput
+             ratio, p50/p99 latency, largest relative cost error).
+
 Other workloads (--config): 1 = 500 x 400 FP64 latency; 3 = 200000 x 160000,
 d = 128, BF16 Gram cost on the matrix cores; 4 = 512 pairs in one batched
-call, d = 24, FP32; 5 = a Poisson stream of requests through the serving loop.
+call, d = 24, FP32; 5 = the serving stream alone (also an all-FP32 mix).
 """
 import argparse
 import json
@@ -153,6 +163,7 @@ def bench_single(args, cfg):
     })
     if cfg == 3 and not args.no_fp64_comparison:
         out["fp64_same_input"] = fp64_comparison_single(Xd, Yd, W, al)
+        del out["fp64_same_input"]["_aligner"]
         out["fp64_same_input"]["speedup_of_reduced_precision"] = out["fp64_same_input"]["ms"] / ms
     if not args.no_cpu_baseline:
         import oracle
@@ -177,28 +188,33 @@ def bench_single(args, cfg):
     return out
 
 
-def fp64_comparison_single(Xd, Yd, W, al):
+def fp64_comparison_single(Xd, Yd, W, al, prev=None):
     """The same input through the exact all-FP64 path (identical to the
     oracle's path by the parity tests): its time, and the reduced-precision
-    result's cost error and frame deviation against it."""
+    result's cost error and frame deviation against it.  `prev` (the
+    "_aligner" entry of an earlier result on the same input) is reused
+    instead of running the FP64 path again."""
     import torch
 
     from paper_2008_02734_amd import dtw, metrics
     M, N, d = Xd.shape[0], Yd.shape[0], Xd.shape[1]
-    X64, Y64 = Xd.to(torch.float64), Yd.to(torch.float64)
-    al64 = dtw.Aligner(M, N, d, torch.float64, "fp64", W["m"], device="cuda:0")
-    al64.run(X64, Y64)  # warm-up
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    st = al64.run(X64, Y64, stats=True)
-    s64 = time.perf_counter() - t
-    c64 = float(al64.cost.item())
-    p64 = al64.path[: int(al64.plen.item())].cpu().numpy()
+    if prev is None:
+        X64, Y64 = Xd.to(torch.float64), Yd.to(torch.float64)
+        al64 = dtw.Aligner(M, N, d, torch.float64, "fp64", W["m"], device="cuda:0")
+        al64.run(X64, Y64)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = al64.run(X64, Y64, stats=True)
+        s64 = time.perf_counter() - t
+        prev = {"ms": s64 * 1e3, "cost": float(al64.cost.item()), "device_error": st["device_error"],
+                "path": al64.path[: int(al64.plen.item())].cpu().numpy()}
+    c64, p64 = prev["cost"], prev["path"]
     plo = al.path[: int(al.plen.item())].cpu().numpy()
     dv = metrics.summary(plo, p64)
-    return {"ms": s64 * 1e3, "gcups": M * N / s64 / 1e9, "cost": c64, "device_error": st["device_error"],
-            "rel_cost_err": (float(al.cost.item()) - c64) / c64, "path_dev_mean_frames": dv["mean_frames"],
-            "path_dev_max_frames": int(dv["max_frames"]), "frac_within_1_frame": dv["frac_le_1"]}
+    return {"ms": prev["ms"], "gcups": M * N / (prev["ms"] * 1e-3) / 1e9, "cost": c64,
+            "device_error": prev["device_error"], "rel_cost_err": (float(al.cost.item()) - c64) / c64,
+            "path_dev_mean_frames": dv["mean_frames"], "path_dev_max_frames": int(dv["max_frames"]),
+            "frac_within_1_frame": dv["frac_le_1"], "_aligner": prev}
 
 
 def bench_batched(args):
@@ -309,60 +325,124 @@ def run_stream(dtw, reqs, precs, rng, frac=0.7):
             "costs": [r["cost"] for r in res]}
 
 
-def bench_serving(args):
-    """cfg 5, scaled: a Poisson stream of requests through the serving loop.
-    M log-uniform in [2000, 40000] (the configuration's upper end, 400000, is
-    scaled down so the stream finishes in seconds), N = M x U[0.75, 1.3],
-    half d = 12 chroma-like, half d = 128 embedding-like.  Two streams: the
-    configuration's mix (d = 12 in FP32, d = 128 in the BF16 Gram form), the
-    same mix with the FP16 Gram form, and every request in FP32.  A pilot (all requests at once) gives the saturated
-    rate; each stream then arrives at 0.7 of it.  Baseline: every request one
-    at a time through the plain FP64 path, which also gives the FP64 costs
-    the reduced-precision results are measured against."""
+def serving_requests(n_requests, m_hi):
+    """The request list of the serving workload: M log-uniform in [2000, m_hi],
+    N = M x U[0.75, 1.3] (within the warp generator's slope range), half d = 12
+    chroma-like, half d = 128 embedding-like, seeds [5, r]; FP32 device copies
+    plus the FP64 host arrays."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
 
-    from paper_2008_02734_amd import dtw, synth
+    from paper_2008_02734_amd import synth
 
     rng = np.random.default_rng([5, 999])
-    reqs = []
-    for r in range(args.requests):
-        M = int(np.exp(rng.uniform(np.log(2000), np.log(40000))))
+    specs = []
+    for r in range(n_requests):
+        M = int(np.exp(rng.uniform(np.log(2000), np.log(m_hi))))
         N = int(M * rng.uniform(0.75, 1.3))
         d, fam = (12, "chroma") if r % 2 == 0 else (128, "embedding")
-        X, Y = synth.make_pair(5, r, M, N, d, fam)
+        specs.append((r, M, N, d, fam))
+    with ThreadPoolExecutor(8) as ex:
+        pairs = list(ex.map(lambda q: synth.make_pair(5, q[0], q[1], q[2], q[3], q[4]), specs))
+    reqs = []
+    for (r, M, N, d, fam), (X, Y) in zip(specs, pairs):
         reqs.append((torch.from_numpy(X.astype(np.float32)).cuda(), torch.from_numpy(Y.astype(np.float32)).cuda(),
                      d, X, Y))
     torch.cuda.synchronize()
-    cells = sum(q[0].shape[0] * q[1].shape[0] for q in reqs)
-    mixed = run_stream(dtw, reqs, ["fp32" if q[2] == 12 else "bf16" for q in reqs], rng)
-    mixed16 = run_stream(dtw, reqs, ["fp32" if q[2] == 12 else "fp16" for q in reqs], rng)
-    fp32 = run_stream(dtw, reqs, ["fp32"] * len(reqs), rng)
-    # baseline: one at a time, plain FP64
+    return reqs, rng
+
+
+def fp64_one_at_a_time(dtw, reqs):
+    """Every request alone through the plain FP64 path: each request's
+    buffers are allocated before its timed call (an Aligner of its shape),
+    so the time is the alignment alone.  Returns (seconds, FP64 costs)."""
+    import torch
     c64, bt = [], 0.0
     for X, Y, d, Xh, Yh in reqs:
         Xd, Yd = torch.from_numpy(Xh).cuda(), torch.from_numpy(Yh).cuda()
+        al = dtw.Aligner(Xh.shape[0], Yh.shape[0], d, torch.float64, "fp64", 500, device="cuda")
         torch.cuda.synchronize()
         s0 = time.perf_counter()
-        c, _, _ = dtw.align(Xd, Yd)
+        st = al.run(Xd, Yd, stats=True)
         bt += time.perf_counter() - s0
-        c64.append(c)
-    c64 = np.array(c64)
+        assert st["device_error"] == 0
+        c64.append(float(al.cost.item()))
+        del al, Xd, Yd
+    return bt, np.array(c64)
+
+
+def serving_summary(args, n_requests, m_hi, mixes):
+    """The serving workload: a Poisson stream of requests through the serving
+    loop (each mix: a pilot with every request at once gives the saturated
+    rate, then arrivals at 0.7 of it), against every request one at a time
+    through the plain FP64 path, which also gives the FP64 costs that the
+    reduced-precision results are measured against."""
+    from paper_2008_02734_amd import dtw
+
+    reqs, rng = serving_requests(n_requests, m_hi)
+    cells = sum(q[0].shape[0] * q[1].shape[0] for q in reqs)
+    streams = {name: run_stream(dtw, reqs, [("fp32" if q[2] == 12 else big) for q in reqs], rng)
+               for name, big in mixes}
+    bt, c64 = fp64_one_at_a_time(dtw, reqs)
     base = cells / bt / 1e9
     is12 = np.array([q[2] == 12 for q in reqs])
-    for st in (mixed, mixed16, fp32):
+    for st in streams.values():
         rel = np.abs((np.array(st.pop("costs")) - c64) / c64)
         st["max_rel_cost_err"] = float(np.max(rel))
         st["max_rel_cost_err_d12"] = float(np.max(rel[is12]))
         st["max_rel_cost_err_d128"] = float(np.max(rel[~is12]))
+        st["meets_1e-5"] = bool(np.max(rel) <= 1e-5)
         st["vs_fp64_one_at_a_time"] = st["gcups"] / base
         st["saturated_vs_fp64_one_at_a_time"] = st["saturated_gcups"] / base
+    return {"workload": f"Poisson stream of {len(reqs)} requests, M log-uniform in [2000, {m_hi}], N = M x "
+                        "U[0.75, 1.3], half d=12 (FP32), half d=128 (Gram cost), at 0.7x the saturated rate",
+            "requests": len(reqs), "textbook_cells": cells, "seed": [5, "r"],
+            "fp64_one_at_a_time_gcups": base, "fp64_one_at_a_time_s": bt, "streams": streams}, reqs
+
+
+def bench_serving(args):
+    """cfg 5: a Poisson stream of requests through the serving loop: the
+    configuration's mix (d = 12 in FP32, d = 128 in the BF16 Gram form), the
+    same mix with the FP16 Gram form, and every request in FP32."""
+    summ, reqs = serving_summary(args, args.requests, args.serving_m_hi,
+                                 [("bf16_mix", "bf16"), ("fp16_mix", "fp16"), ("fp32_all", "fp32")])
+    mixed = summ["streams"]["bf16_mix"]
     out = base_record(args, mixed["gcups"], mixed["makespan_ms"], "f32+bf16",
-                      {"workload": f"Poisson stream of {len(reqs)} requests, M log-uniform in [2000, 40000], half "
-                                   "d=12 FP32, half d=128 BF16 Gram cost, at 0.7x the saturated rate",
-                       "requests": len(reqs), "seed": [5, "r"]})
-    out.update({"p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed_stream": mixed,
-                "mixed_fp16_stream": mixed16, "fp32_stream": fp32, "fp64_one_at_a_time_gcups": base})
+                      {"workload": summ["workload"], "requests": summ["requests"], "seed": [5, "r"]})
+    out.update({"p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "serving": summ})
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_sample_serving(reqs)
+    return out
+
+
+def long_pair_summary(args):
+    """The long pair (200000 x 160000, d = 128, embedding-like) in the BF16
+    and FP16 Gram forms, each against the all-FP64 path on the same input."""
+    import torch
+
+    from paper_2008_02734_amd import dtw, synth
+
+    W = WORKLOADS[3]
+    M, N, d = W["M"], W["N"], W["d"]
+    X, Y = synth.make_pair(3, 0, M, N, d, W["family"])
+    Xd = torch.from_numpy(X).to("cuda:0", torch.float32)
+    Yd = torch.from_numpy(Y).to("cuda:0", torch.float32)
+    out = {"workload": "single pair 200000x160000, d=128 embedding-like (m=500)", "M": M, "N": N, "d": d}
+    fp64 = None
+    for prec in ("bf16", "fp16"):
+        al = dtw.Aligner(M, N, d, torch.float32, prec, W["m"], device="cuda:0")
+        al.opts.profile = 2
+        ms, lat, stats = timed_steps(lambda: al.run(Xd, Yd, stats=True), 2, 1)
+        r = {"ms": ms, "gcups": M * N / (ms * 1e-3) / 1e9, "sweep_ms": float(np.mean([s["ms_sweep"] for s in stats])),
+             "roofline": roofline(stats, prec, d, f"pass_kernel<float,128,{'Gram' if prec == 'bf16' else 'GramF16'}>")}
+        cmp = fp64_comparison_single(Xd, Yd, W, al, fp64)
+        fp64 = cmp.pop("_aligner")
+        r.update({k: cmp[k] for k in ("rel_cost_err", "path_dev_mean_frames", "path_dev_max_frames",
+                                      "frac_within_1_frame")})
+        r["speedup_vs_fp64"] = cmp["ms"] / ms
+        out[prec] = r
+        out["fp64"] = {k: cmp[k] for k in ("ms", "gcups", "cost")}
+        del al
     return out
 
 
@@ -392,6 +472,10 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="pairs of the batched workload (config 4)")
     ap.add_argument("--batch-d", type=int, default=24, help="frame width of the batched workload (config 4)")
     ap.add_argument("--requests", type=int, default=96, help="requests of the serving stream (config 5)")
+    ap.add_argument("--serving-m-hi", type=int, default=400000,
+                    help="upper end of the serving requests' lengths (config 5 and the default run)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default run: skip the long-pair and serving summaries (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
                     help="override the single-pair workload's arithmetic (e.g. fp16 for config 3)")
@@ -415,6 +499,12 @@ def main():
         sys.exit(2)
     if args.config in WORKLOADS:
         out = bench_single(args, args.config)
+        if args.config == 2 and not args.no_extras:
+            # the two other targets, measured in the same run: the long pair in
+            # the reduced-precision Gram forms against FP64, and the serving loop
+            out["long_pair"] = long_pair_summary(args)
+            out["serving"], _ = serving_summary(args, args.requests, args.serving_m_hi,
+                                                [("bf16_mix", "bf16"), ("fp16_mix", "fp16")])
     elif args.config == 4:
         out = bench_batched(args)
     elif args.config == 5:
