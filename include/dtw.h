@@ -77,7 +77,11 @@ typedef enum {
  * DTW_PREC_FP64 the cosine cost is: each frame divided by its norm (the
  * correctly rounded square root of the fma chain of its squares in dimension
  * order; IEEE division), the dot product of the normalised frames as an fma
- * chain in dimension order, then 1 - dot. */
+ * chain in dimension order, then 1 - dot.  In DTW_PREC_FP32 the normalised
+ * frames are rounded to FP32 and the dot product is an FP32 fma chain.  In
+ * the Gram forms the normalised frames are rounded to FP32 and then to bf16
+ * or fp16, and the cost is max(0, 1 - dot) with the dot product from the
+ * matrix-core tile (FP32 accumulation). */
 typedef enum { DTW_COST_EUCLIDEAN = 0, DTW_COST_COSINE = 1 } dtw_cost;
 
 typedef struct dtw_opts {
@@ -95,9 +99,8 @@ typedef struct dtw_opts {
                               the device wall clock; 0 = the default of 20 s.  When a wait
                               runs out, the call fails with DTW_ERR_INTERNAL and device
                               error 9, and every other wait of the call ends at once       */
-  int32_t cost;            /* dtw_cost, default DTW_COST_EUCLIDEAN; DTW_COST_COSINE is
-                              available in DTW_PREC_FP64 and DTW_PREC_FP32
-                              (DTW_ERR_UNSUPPORTED with the Gram forms)                  */
+  int32_t cost;            /* dtw_cost, default DTW_COST_EUCLIDEAN; every precision
+                              takes either                                               */
   int32_t reserved[2];     /* must be zero                                                */
 } dtw_opts;
 
@@ -136,7 +139,18 @@ const char* dtw_status_string(int32_t status);
 int32_t dtw_last_hip_error(void);
 
 /* Workspace bytes needed by dtw_align for an M x N problem of dimension d.
- * opts may be NULL (defaults).  Returns DTW_OK and writes *bytes. */
+ * opts may be NULL (defaults).  Returns DTW_OK and writes *bytes, or
+ * DTW_ERR_INVALID_ARG (M, N < 1, bytes NULL, bad opts) / DTW_ERR_UNSUPPORTED.
+ * The size is linear in M + N, as the memory bound of the divide-and-conquer
+ * recursion (Sec. 3.2) and the memory comparison of Sec. 4.3 require: the three
+ * split-diagonal bands F, B and C of every block of one recursion level
+ * (Eq. "splitcost"; about 4.5 (M + N) doubles summed over a level), the
+ * boundary rows handed from one wavefront stripe to the next (Algorithm 1),
+ * the leaf tables of side < m (two bits per cell: the traceback choice), the path, the
+ * block and pass descriptors, and a converted copy of X and Y when the sweep
+ * arithmetic, the frame padding or the cosine cost needs one.  Never the
+ * M x N table.  The size depends only on M, N, d, in_dtype, opts->precision,
+ * opts->min_block and opts->cost. */
 dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
                               const dtw_opts* opts, size_t* bytes);
 
@@ -212,7 +226,9 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype,
  * stats->device_error and return DTW_ERR_INTERNAL. */
 dtw_status dtw_device_error(const void* workspace, int32_t* code, void* stream);
 
-/* Batched form: B independent pairs packed back to back.
+/* Batched form: B independent pairs packed back to back, each solved by
+ * Algorithm 2 exactly as dtw_align solves it (the paper aligns one pair per
+ * call; batching is this library's, for many short pairs).
  *   x_offsets, y_offsets  host, B+1 frame offsets (pair b uses frames
  *                         x_offsets[b] .. x_offsets[b+1]-1 of X_packed)
  *   path_offsets          host, B+1 pair offsets into paths_out; pair b needs
@@ -220,7 +236,11 @@ dtw_status dtw_device_error(const void* workspace, int32_t* code, void* stream);
  *   costs_out             device, B doubles; paths_out device int32 pairs;
  *   path_lens_out         device, B int64
  * All pairs share one launch per recursion level.  Results are identical to
- * calling dtw_align on each pair.  Workspace: dtw_workspace_size_batched(). */
+ * calling dtw_align on each pair.  Errors: as dtw_align, checked for every
+ * pair before any work is enqueued (B < 1, offsets not increasing, a pair's
+ * path capacity too small).  Workspace: dtw_workspace_size_batched(), the sum
+ * of the per-pair linear terms above (one level's bands, rings and leaf
+ * tables over all pairs) plus one copy of the shared descriptors. */
 dtw_status dtw_workspace_size_batched(int32_t B, const int64_t* x_offsets,
                                       const int64_t* y_offsets, int32_t d, int32_t in_dtype,
                                       const dtw_opts* opts, size_t* bytes);

@@ -28,7 +28,7 @@ hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64
                               hipStream_t st);
 hipError_t launch_normalize(const void* in, int in_f64, void* out, int out_f64, int64_t rows, int d, int D,
                             hipStream_t st);
-hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
+hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, int cos, uint16_t* out,
                              float* norms,
                              hipStream_t st);
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st);
@@ -260,7 +260,6 @@ dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
   if (out->cost != DTW_COST_EUCLIDEAN && out->cost != DTW_COST_COSINE) return DTW_ERR_INVALID_ARG;
   for (int i = 0; i < 2; ++i)
     if (out->reserved[i] != 0) return DTW_ERR_INVALID_ARG;
-  if (out->cost == DTW_COST_COSINE && is_gram_precision(out->precision)) return DTW_ERR_UNSUPPORTED;
   return DTW_OK;
 }
 
@@ -347,8 +346,9 @@ hipError_t stage_inputs(const Layout& L, void* ws, const void* X, const void* Y,
     float* xn = at<float>(ws, L.xnorm);
     float* yn = at<float>(ws, L.ynorm);
     const int bf16 = precision == DTW_PREC_BF16_COST ? 1 : 0;
-    e = launch_gram_stage(X, in_f64, xrows, d, L.D, bf16, static_cast<uint16_t*>(xc), xn, st);
-    if (e == hipSuccess) e = launch_gram_stage(Y, in_f64, yrows, d, L.D, bf16, static_cast<uint16_t*>(yc), yn, st);
+    const int cos = cost == DTW_COST_COSINE ? 1 : 0;
+    e = launch_gram_stage(X, in_f64, xrows, d, L.D, bf16, cos, static_cast<uint16_t*>(xc), xn, st);
+    if (e == hipSuccess) e = launch_gram_stage(Y, in_f64, yrows, d, L.D, bf16, cos, static_cast<uint16_t*>(yc), yn, st);
     w.Xn = xn;
     w.Yn = yn;
   } else if (cost == DTW_COST_COSINE) {

@@ -36,8 +36,13 @@ constexpr int kCostEuclid = 0;
 constexpr int kCostGram = 1;     // BF16 frames
 constexpr int kCostGramF16 = 2;  // FP16 frames
 constexpr int kCostCosine = 3;   // 1 - dot product of the normalised frames
-constexpr bool is_gram(int cm) { return cm == kCostGram || cm == kCostGramF16; }
-constexpr bool is_cos(int cm) { return cm == kCostCosine; }
+constexpr int kCostGramCos = 4;     // the Gram form's tile on normalised BF16 frames: 1 - dot
+constexpr int kCostGramF16Cos = 5;  // the same on normalised FP16 frames
+constexpr bool is_gram(int cm) {
+  return cm == kCostGram || cm == kCostGramF16 || cm == kCostGramCos || cm == kCostGramF16Cos;
+}
+constexpr bool gram_bf16(int cm) { return cm == kCostGram || cm == kCostGramCos; }
+constexpr bool is_cos(int cm) { return cm == kCostCosine || cm == kCostGramCos || cm == kCostGramF16Cos; }
 // Producer waves of a sweep workgroup: the Gram form needs only two (its
 // matrix-core tiles are cheap), which makes its workgroup 4 waves and lets
 // four workgroups share a CU; the Euclidean forms use eight.

@@ -563,15 +563,26 @@ __device__ __forceinline__ float f16_to_f32(uint16_t h) {
   return __builtin_bit_cast(float, sign | ((e + 112u) << 23) | (m << 13));
 }
 
-template <typename TI, bool kBf16>
+template <typename TI, bool kBf16, bool kCos>
 __global__ __launch_bounds__(256) void gram_stage_kernel(const TI* __restrict__ in, int64_t rows, int d, int D,
                                                           uint16_t* __restrict__ out, float* __restrict__ norms) {
   const int lane = threadIdx.x % 64;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
   for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; r < rows; r += nw) {
+    // kCos: the frame is first divided by its FP64 norm exactly as the
+    // normalising copy of the VALU forms does it (every lane forms the same
+    // fma chain in dimension order), then rounded like any other frame
+    double n = 1.0;
+    if constexpr (kCos) {
+      n = 0.0;
+      for (int t = 0; t < d; ++t) n = __builtin_fma((double)in[r * d + t], (double)in[r * d + t], n);
+      n = __builtin_sqrt(n);
+    }
     float s = 0.0f;
     for (int k = lane; k < D; k += 64) {
-      const float f = (k < d) ? (float)in[r * d + k] : 0.0f;
+      float f;
+      if constexpr (kCos) f = (k < d && n > 0.0) ? (float)((double)in[r * d + k] / n) : 0.0f;
+      else f = (k < d) ? (float)in[r * d + k] : 0.0f;
       const uint16_t h = kBf16 ? f32_to_bf16_rne(f) : f32_to_f16_rne(f);
       out[r * D + k] = h;
       const float g = kBf16 ? bf16_to_f32(h) : f16_to_f32(h);
@@ -663,15 +674,23 @@ hipError_t launch_normalize(const void* in, int in_f64, void* out, int out_f64, 
   return launch_checked(&normalize_kernel<float, float>, grid, 256, 0, st, static_cast<const float*>(in),
                         static_cast<float*>(out), rows, d, D);
 }
-hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
-                             float* norms, hipStream_t st) {
+template <bool kCos>
+hipError_t launch_gram_stage_t(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
+                               float* norms, hipStream_t st) {
   const int grid = (int)min((int64_t)2048, (rows + 3) / 4 + 1);
   const double* id = static_cast<const double*>(in);
   const float* is = static_cast<const float*>(in);
-  if (in_f64 && bf16) return launch_checked(&gram_stage_kernel<double, true>, grid, 256, 0, st, id, rows, d, D, out, norms);
-  if (bf16) return launch_checked(&gram_stage_kernel<float, true>, grid, 256, 0, st, is, rows, d, D, out, norms);
-  if (in_f64) return launch_checked(&gram_stage_kernel<double, false>, grid, 256, 0, st, id, rows, d, D, out, norms);
-  return launch_checked(&gram_stage_kernel<float, false>, grid, 256, 0, st, is, rows, d, D, out, norms);
+  if (in_f64 && bf16)
+    return launch_checked(&gram_stage_kernel<double, true, kCos>, grid, 256, 0, st, id, rows, d, D, out, norms);
+  if (bf16) return launch_checked(&gram_stage_kernel<float, true, kCos>, grid, 256, 0, st, is, rows, d, D, out, norms);
+  if (in_f64)
+    return launch_checked(&gram_stage_kernel<double, false, kCos>, grid, 256, 0, st, id, rows, d, D, out, norms);
+  return launch_checked(&gram_stage_kernel<float, false, kCos>, grid, 256, 0, st, is, rows, d, D, out, norms);
+}
+hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, int cos,
+                             uint16_t* out, float* norms, hipStream_t st) {
+  return cos ? launch_gram_stage_t<true>(in, in_f64, rows, d, D, bf16, out, norms, st)
+             : launch_gram_stage_t<false>(in, in_f64, rows, d, D, bf16, out, norms, st);
 }
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t st) {
   const int grid = (int)min((int64_t)1024, (n + 255) / 256 + 1);

@@ -307,13 +307,15 @@ __device__ __forceinline__ void publish(int t, int lane, const T* cring, uint64_
 // writing its current block, so they have the NPW/2 - 1 phases in between
 // plus the rest of the current one to arrive, and at its phase it runs
 // DP/16 matrix-core operations and the FP32 epilogue
-// sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring.  The tile is formed
+// sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) into the cost ring (kCos: the frames
+// were normalised before rounding and the epilogue is max(0, 1 - x.y), the
+// cosine cost of Sec. 4.1).  The tile is formed
 // transposed (Y frames as the first operand): each lane's results then share
 // one stripe row, and the 32 lanes of a half-wave write 32 distinct rows of
 // the ring at once.  Row r of the stripe is frame gi0 + gis*(a0 + r) of Xb,
 // column j is frame gj0 + gjs*j of Yb; rows past Lr reuse row Lr and columns
 // past need_max reuse column need_max.
-template <int DP, bool kBf16, int NPW, bool kXRegs>
+template <int DP, bool kBf16, bool kCos, int NPW, bool kXRegs>
 __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, const uint16_t* __restrict__ Yb,
                                               const float* __restrict__ Xn, const float* __restrict__ Yn, int gi0,
                                               int gis, int gj0, int gjs, int a0, int Lr, int need_max, int n_phases,
@@ -378,8 +380,14 @@ __device__ __forceinline__ void gram_producer(const uint16_t* __restrict__ Xb, c
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int jj = 8 * (q / 4) + 4 * half + q % 4;
-          const float v = fmaxf(__builtin_fmaf(-2.0f, acc[q], nx + nys[jj]), 0.0f);
-          cring[((c0 + jj + row) & (kCostRing - 1)) * kWave + row] = __builtin_amdgcn_sqrtf(v);
+          float c;
+          if constexpr (kCos) {
+            c = fmaxf(1.0f - acc[q], 0.0f);
+          } else {
+            const float v = fmaxf(__builtin_fmaf(-2.0f, acc[q], nx + nys[jj]), 0.0f);
+            c = __builtin_amdgcn_sqrtf(v);
+          }
+          cring[((c0 + jj + row) & (kCostRing - 1)) * kWave + row] = c;
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -563,7 +571,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
     } else if (wave <= pass_producers(CM) && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
-        gram_producer<D, CM == kCostGram, pass_producers(CM), true>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
+        gram_producer<D, gram_bf16(CM), is_cos(CM), pass_producers(CM), true>(static_cast<const uint16_t*>(w.X), static_cast<const uint16_t*>(w.Y), w.Xn, w.Yn,
                          P.dir ? P.i1 : P.i0, P.dir ? -1 : 1, P.dir ? P.j1 : P.j0, P.dir ? -1 : 1, a0, Lr,
                          need_max, n_phases, wave, lane, reinterpret_cast<float*>(cring));
     } else if (wave <= pass_producers(CM) && D >= 64) {
@@ -819,7 +827,7 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     } else if (wave <= kProducers && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
-        gram_producer<D, CM == kCostGram, kProducers, false>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
+        gram_producer<D, gram_bf16(CM), is_cos(CM), kProducers, false>(reinterpret_cast<const uint16_t*>(RowSrc), reinterpret_cast<const uint16_t*>(ColSrc), RowN,
                          ColN, S.r0 + sw, 1, S.c0, 1, 0, Lr, S.Cc - 1, n_phases, wave, lane,
                          reinterpret_cast<float*>(cring));
     } else if (wave <= kProducers && D >= 64) {
@@ -1128,7 +1136,13 @@ int pick_dgram(int d) {
 // VALU, or BF16 Gram costs on the matrix cores with the FP32 recurrence.
 hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
   const float* nf = nullptr;
-  if (w.precision == DTW_PREC_BF16_COST) {
+  if (w.precision == DTW_PREC_BF16_COST && w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&pass_kernel<float, D_, kCostGramCos>, grid,
+                                                               pass_threads(kCostGramCos), 0, st, nf, nf, w, level))
+  } else if (w.precision == DTW_PREC_FP16_COST && w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&pass_kernel<float, D_, kCostGramF16Cos>, grid,
+                                                               pass_threads(kCostGramF16Cos), 0, st, nf, nf, w, level))
+  } else if (w.precision == DTW_PREC_BF16_COST) {
     DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&pass_kernel<float, D_, kCostGram>, grid,
                                                                pass_threads(kCostGram), 0, st, nf, nf, w, level))
   } else if (w.precision == DTW_PREC_FP16_COST) {
@@ -1158,7 +1172,15 @@ hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const vo
                        hipStream_t st) {
   const size_t dyn = (size_t)lds_leaf_bytes;
   const float* nf = nullptr;
-  if (w.precision == DTW_PREC_BF16_COST) {
+  if (w.precision == DTW_PREC_BF16_COST && w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGramCos>, grid,
+                                                               kLeafThreads, dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo,
+                                                               in_f64, w.d))
+  } else if (w.precision == DTW_PREC_FP16_COST && w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGramF16Cos>, grid,
+                                                               kLeafThreads, dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo,
+                                                               in_f64, w.d))
+  } else if (w.precision == DTW_PREC_BF16_COST) {
     DTW_DISPATCH_DGRAM(pick_dgram(w.d), return launch_checked(&leaf_kernel<float, D_, kCostGram>, grid, kLeafThreads,
                                                                dyn, st, nf, nf, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d))
   } else if (w.precision == DTW_PREC_FP16_COST) {
@@ -1216,7 +1238,9 @@ hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32) {
   M_(float, 16, kCostCosine, 1) M_(float, 24, kCostCosine, 1) M_(float, 32, kCostCosine, 1)               \
   M_(float, 64, kCostCosine, 1) M_(float, 128, kCostCosine, 1)                                            \
   M_(float, 32, kCostGram, 1) M_(float, 64, kCostGram, 1) M_(float, 128, kCostGram, 1)                   \
-  M_(float, 32, kCostGramF16, 1) M_(float, 64, kCostGramF16, 1) M_(float, 128, kCostGramF16, 1)
+  M_(float, 32, kCostGramF16, 1) M_(float, 64, kCostGramF16, 1) M_(float, 128, kCostGramF16, 1)                \
+  M_(float, 32, kCostGramCos, 1) M_(float, 64, kCostGramCos, 1) M_(float, 128, kCostGramCos, 1)                \
+  M_(float, 32, kCostGramF16Cos, 1) M_(float, 64, kCostGramF16Cos, 1) M_(float, 128, kCostGramF16Cos, 1)
   DTW_LEAF_ALL(DTW_LEAF_STATIC)
 #undef DTW_LEAF_STATIC
   lim[0] &= ~(int64_t)255;

@@ -126,10 +126,11 @@ static float model_f16(uint16_t h) {
 }
 
 // Gram-form cost from the staged 16-bit frames and FP32 norms (k-order FP32 sum).
-static float model_gram_cost(const uint16_t* x, const uint16_t* y, float nx, float ny, int D, bool bf16) {
+static float model_gram_cost(const uint16_t* x, const uint16_t* y, float nx, float ny, int D, bool bf16, bool cos) {
   float dot = 0.0f;
   for (int k = 0; k < D; ++k)
     dot += bf16 ? model_bf16(x[k]) * model_bf16(y[k]) : model_f16(x[k]) * model_f16(y[k]);
+  if (cos) return std::fmax(1.0f - dot, 0.0f);  // frames normalised before rounding
   const float v = std::fmax(std::fma(-2.0f, dot, nx + ny), 0.0f);
   return std::sqrt(v);
 }
@@ -148,7 +149,8 @@ static T model_frame_cost(const Work& w, int64_t gi, int64_t gj) {
   if (is_gram_precision(w.precision)) {
     const int D = pick_dgram(w.d);
     return (T)model_gram_cost(static_cast<const uint16_t*>(w.X) + gi * D, static_cast<const uint16_t*>(w.Y) + gj * D,
-                              w.Xn[gi], w.Yn[gj], D, w.precision == DTW_PREC_BF16_COST);
+                              w.Xn[gi], w.Yn[gj], D, w.precision == DTW_PREC_BF16_COST,
+                              w.cost == DTW_COST_COSINE);
   }
   const int D = pick_dmax(w.d);
   if (w.cost == DTW_COST_COSINE)
@@ -383,7 +385,11 @@ hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t) {
   MODEL_LAUNCH_CHECK(&tag_pass[w.precision != DTW_PREC_FP64], grid,
                      is_gram_precision(w.precision) ? pass_threads(kCostGram) : pass_threads(kCostEuclid), 0);
   model_check_queue(w);
-  if (w.precision == DTW_PREC_BF16_COST) {
+  if (w.precision == DTW_PREC_BF16_COST && w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGramCos), [&] { pass_kernel<float, D_, kCostGramCos>(nullptr, nullptr, w, level); })))
+  } else if (w.precision == DTW_PREC_FP16_COST && w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGramF16Cos), [&] { pass_kernel<float, D_, kCostGramF16Cos>(nullptr, nullptr, w, level); })))
+  } else if (w.precision == DTW_PREC_BF16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGram), [&] { pass_kernel<float, D_, kCostGram>(nullptr, nullptr, w, level); })))
   } else if (w.precision == DTW_PREC_FP16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, pass_threads(kCostGramF16), [&] { pass_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, level); })))
@@ -402,7 +408,11 @@ hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const vo
                        hipStream_t) {
   MODEL_LAUNCH_CHECK(&tag_leaf[w.precision != DTW_PREC_FP64], grid, kLeafThreads, (size_t)lds_leaf_bytes);
   model_check_leaves(w);
-  if (w.precision == DTW_PREC_BF16_COST) {
+  if (w.precision == DTW_PREC_BF16_COST && w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGramCos>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  } else if (w.precision == DTW_PREC_FP16_COST && w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGramF16Cos>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
+  } else if (w.precision == DTW_PREC_BF16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGram>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
   } else if (w.precision == DTW_PREC_FP16_COST) {
     MODEL_DISPATCH_GRAM(pick_dgram(w.d), (cpu_launch(2, kLeafThreads, [&] { leaf_kernel<float, D_, kCostGramF16>(nullptr, nullptr, w, lds_leaf_bytes, Xo, Yo, in_f64, w.d); })))
@@ -492,12 +502,18 @@ hipError_t launch_pad_convert(const void* in, int in_f64, void* out, int out_f64
     cpu_launch(2, 64, [&] { pad_convert_kernel<float, float>((const float*)in, (float*)out, rows, d, D); });
   return hipSuccess;
 }
-hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
-                             float* norms, hipStream_t) {
-  if (in_f64 && bf16) cpu_launch(2, 256, [&] { gram_stage_kernel<double, true>((const double*)in, rows, d, D, out, norms); });
-  else if (bf16) cpu_launch(2, 256, [&] { gram_stage_kernel<float, true>((const float*)in, rows, d, D, out, norms); });
-  else if (in_f64) cpu_launch(2, 256, [&] { gram_stage_kernel<double, false>((const double*)in, rows, d, D, out, norms); });
-  else cpu_launch(2, 256, [&] { gram_stage_kernel<float, false>((const float*)in, rows, d, D, out, norms); });
+template <bool kCos>
+static void model_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, uint16_t* out,
+                             float* norms) {
+  if (in_f64 && bf16) cpu_launch(2, 256, [&] { gram_stage_kernel<double, true, kCos>((const double*)in, rows, d, D, out, norms); });
+  else if (bf16) cpu_launch(2, 256, [&] { gram_stage_kernel<float, true, kCos>((const float*)in, rows, d, D, out, norms); });
+  else if (in_f64) cpu_launch(2, 256, [&] { gram_stage_kernel<double, false, kCos>((const double*)in, rows, d, D, out, norms); });
+  else cpu_launch(2, 256, [&] { gram_stage_kernel<float, false, kCos>((const float*)in, rows, d, D, out, norms); });
+}
+hipError_t launch_gram_stage(const void* in, int in_f64, int64_t rows, int d, int D, int bf16, int cos,
+                             uint16_t* out, float* norms, hipStream_t) {
+  if (cos) model_gram_stage<true>(in, in_f64, rows, d, D, bf16, out, norms);
+  else model_gram_stage<false>(in, in_f64, rows, d, D, bf16, out, norms);
   return hipSuccess;
 }
 hipError_t launch_nonfinite(const void* in, int in_f64, int64_t n, int32_t* flag, hipStream_t) {

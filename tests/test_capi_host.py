@@ -64,8 +64,10 @@ def test_argument_errors_before_any_device_work():
     assert _align(L, opts=bad) == -1
     bad = dtw.make_opts(cost=5)
     assert _align(L, opts=bad) == -1      # unknown frame cost
-    bad = dtw.make_opts(precision="bf16", cost="cosine")
-    assert _align(L, opts=bad) == -8      # cosine cost: FP64 and FP32 forms only
+    n = ctypes.c_size_t()
+    for prec in ("fp64", "fp32", "bf16", "fp16"):  # every precision takes the cosine cost
+        o = dtw.make_opts(precision=prec, cost="cosine")
+        assert L.dtw_workspace_size(100, 80, 128, 0, ctypes.byref(o), ctypes.byref(n)) == 0 and n.value > 0
 
 
 def test_workspace_size_errors():

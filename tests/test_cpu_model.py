@@ -332,3 +332,22 @@ def test_wave_model_cosine(model_exe, wave_exe, M, N, d, m, prec):
             assert abs(cost - c_ref) <= 1e-12 * c_ref
         else:
             assert (cost - c_ref) / c_ref <= 1e-5 and cost >= c_ref * (1 - 1e-12)
+
+
+@pytest.mark.parametrize("M,N,d,m,prec", [(90, 70, 64, 16, 2), (80, 75, 128, 16, 3), (100, 60, 40, 500, 3)])
+def test_wave_model_gram_cosine(model_exe, wave_exe, M, N, d, m, prec):
+    # the cosine cost on the matrix-core tile: frames normalised in FP64 at
+    # staging, rounded to bf16/fp16, cost max(0, 1 - dot).  The real kernels
+    # (matrix-core operation emulated in its lane layout) and the plain model
+    # take the same path, whose FP64 cosine cost is reported exactly
+    X, Y = synth.make_pair(8400, M + d, M, N, d, "embedding")
+    r_wave = run_model(wave_exe, [(X, Y)], m, precision=prec, cost=1)
+    r_plain = run_model(model_exe, [(X, Y)], m, precision=prec, cost=1)
+    assert r_wave["rc"] == 0 and r_wave["device_error"] == 0, r_wave
+    cost, path = r_wave["results"][0]
+    assert path.tolist() == r_plain["results"][0][1].tolist()
+    assert abs(cost - r_plain["results"][0][0]) <= 1e-12 * cost
+    c_ref, _ = oracle.full(X, Y, cost="cosine")
+    assert oracle.path_cost(X, Y, path, cost="cosine") == pytest.approx(cost, rel=1e-12)
+    print("rel", (cost - c_ref) / c_ref)
+    assert -1e-12 <= (cost - c_ref) / c_ref <= (BF16_REL_TOL if prec == 2 else 1e-5)
