@@ -174,10 +174,11 @@ def bench_single(args, cfg):
         t = time.perf_counter()
         c_ref, p_ref = oracle.full(Xs, Ys)
         cpu_s = time.perf_counter() - t
-        out["cpu_baseline"] = {
-            "value": Ms * Ns / cpu_s / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
-            "sample": (f"the full {M}x{N} pair" if cfg != 3 else f"the leading {Ms}x{Ns} block of the pair")
-                      + f": textbook FP64 full table + backtrace, single thread, {cpu_s:.1f} s"}
+        out["cpu_baseline"] = cpu_record(
+            Ms * Ns, cpu_s,
+            (f"the full {M}x{N} pair" if cfg != 3 else
+             f"the leading {Ms}x{Ns} block of the pair (its rate taken as the whole pair's)")
+            + f": textbook FP64 full table + backtrace, single thread, {cpu_s:.1f} s", cfg != 3)
         if cfg != 3:
             path = al.path[: int(al.plen.item())].cpu().numpy()
             out["parity"] = {"path_equal_to_oracle": bool(path.tolist() == p_ref.tolist()),
@@ -287,9 +288,10 @@ def bench_batched(args):
             if time.perf_counter() - t > 15:
                 break
         cpu_s = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": done / cpu_s / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
-                               "sample": f"the batch's first {p + 1} pairs ({done / 1e6:.0f} M cells): textbook "
-                                         f"FP64 full table + backtrace, single thread, {cpu_s:.1f} s"}
+        out["cpu_baseline"] = cpu_record(
+            done, cpu_s, f"the batch's first {p + 1} of {len(shapes)} pairs ({done / 1e6:.0f} M cells; their rate "
+                         f"taken as the batch's): textbook FP64 full table + backtrace, single thread, {cpu_s:.1f} s",
+            p + 1 == len(shapes))
     return out
 
 
@@ -446,6 +448,17 @@ def long_pair_summary(args):
     return out
 
 
+def cpu_record(cells, cpu_s, sample, whole):
+    """The cpu_baseline object: the oracle's rate on `sample`.  `whole` says
+    whether the sample is the entire workload; if not, the rate is the
+    sample's, taken as the workload's (an extrapolation, marked so)."""
+    import oracle
+    flags = [a for a in oracle.GCC_CMD if a.startswith(("-O", "-std", "-f")) and a != "-fPIC"]
+    return {"value": cells / cpu_s / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle", "sample": sample,
+            "sample_s": cpu_s, "extrapolated": not whole,
+            "oracle_build": "gcc " + " ".join(flags) + " (oracle/dtw_oracle.c, untuned)"}
+
+
 def cpu_sample_serving(reqs):
     import oracle
     t = time.perf_counter()
@@ -458,9 +471,9 @@ def cpu_sample_serving(reqs):
         if time.perf_counter() - t > 15:
             break
     cpu_s = time.perf_counter() - t
-    return {"value": done / cpu_s / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
-            "sample": f"requests with M <= 6000 in stream order ({done / 1e6:.0f} M cells): textbook FP64 full table, "
-                      f"single thread, {cpu_s:.1f} s"}
+    return cpu_record(done, cpu_s, f"requests with M <= 6000 in stream order ({done / 1e6:.0f} M cells; their rate "
+                                   f"taken as the stream's): textbook FP64 full table, single thread, {cpu_s:.1f} s",
+                      False)
 
 
 def main():

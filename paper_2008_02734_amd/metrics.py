@@ -1,4 +1,4 @@
-"""Alignment discrepancy between two warping paths (Sec. 5.3 of arXiv 2008.02734).
+"""Alignment discrepancy between two warping paths (Sec. 4.4 of arXiv 2008.02734).
 
 For every cell (i, j) of one path the row error is the smallest |j - k| over
 the cells (i, k) of the other path; the column error is defined the same way

@@ -5,7 +5,7 @@ VALU; band sums S = F + B - C and the argmin in FP64 (the FP32 values
 widened); the returned cost is the FP64 sum of FP64 frame costs along the
 returned path.  The gate is the relative error of that cost against the
 oracle's optimum, <= 1e-5.  The frame deviation of the path from the FP64
-path (Sec. 5.3 discrepancy) is reported.
+path (Sec. 4.4 discrepancy) is reported.
 """
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""The alignment discrepancy of Sec. 5.3, checked on hand-made paths."""
+"""The alignment discrepancy of Sec. 4.4, checked on hand-made paths."""
 import numpy as np
 
 from paper_2008_02734_amd import metrics

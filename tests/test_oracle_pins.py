@@ -452,7 +452,7 @@ def _replay_recursion(M, N, m, pivots):
 def test_cells_processed_bound(m):
     # Sec. 3.2 complexity: at most 2MN + (M+N) log2(M+N) cells once the three
     # band diagonals that both half sweeps evaluate are counted once more, and
-    # Sec. 4.5 (Fig. "Cell"): the ratio to MN is close to 2 for warped pairs.
+    # Sec. 4.4 (Fig. "Cell"): the ratio to MN is close to 2 for warped pairs.
     X, Y = synth.make_pair(1, 7, 600, 480, 6, "gaussian_walk")
     M, N = 600, 480
     r = oracle.linmdtw(X, Y, min_block=m)
