@@ -219,7 +219,7 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype,
  *   0      no error
  *   9      a boundary-row wait of a sweep ran past opts->wait_limit_us; every
  *          other wait of the call then ends at once
- *   other  a planner, queue or descriptor check failed (1..8, 10..13)
+ *   other  a planner, queue or descriptor check failed (1..8, 10..14)
  * A nonzero code also shows in the outputs without this query: the cost is
  * NaN and the path length 0 (dtw_align, dtw_align_batched), every value NaN
  * (dtw_diag).  With stats != NULL, dtw_align / dtw_align_batched report it in

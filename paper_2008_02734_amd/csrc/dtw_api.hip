@@ -112,8 +112,8 @@ struct Layout {
   int cbytes = 8;  // bytes of the compute type
   int D = 0;       // padded frame stride of the compute copies
   Region ctl, pairs, subs0, subs1, piv_key, piv_pos, smin, passes, tickets, hist, chunk_sub, bandF, bandC,
-      bandB, ring, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, xconv, yconv, xnorm, ynorm,
-      nonfinite;
+      bandB, ring, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, leaf_tk, leaf_ring, leaf_done, xconv,
+      yconv, xnorm, ynorm, nonfinite;
   size_t total = 0;
 };
 
@@ -161,6 +161,11 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   c.leaf_words = (((int64_t)m + kWave) * (K0sum + c.leaf)) / 16 + ((int64_t)m + kWave) * 6 * c.leaf +
                  2 * (K0sum + c.leaf) + 64;
   c.pslots = K0sum;
+  // leaf stripes: a leaf's shorter side is below m, so at most ceil((m-1)/64)
+  // stripes; a leaf of several stripes has min(stripes - 1, kRing) boundary
+  // rows of Cc cells, and the Cc of all leaves sum to at most K0sum + leaves
+  c.leaf_tk = c.leaf * (((int64_t)m - 1 + kWave - 1) / kWave) + 1;
+  c.leaf_ring = kRing * (K0sum + c.leaf) + 1;
   const bool gram = is_gram_precision(precision);
   const bool f32 = precision == DTW_PREC_FP32 || gram;  // compute type of the recurrence
   L.cbytes = f32 ? 4 : 8;
@@ -189,6 +194,9 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   put(L, L.poff, 4 * c.pslots);
   put(L, L.lidx, 4 * c.pslots);
   put(L, L.leaf_cost, 16 * c.leaf);
+  put(L, L.leaf_tk, sizeof(int2) * c.leaf_tk);
+  put(L, L.leaf_ring, (size_t)L.cbytes * 2 * c.leaf_ring);  // cells as in the sweep ring
+  put(L, L.leaf_done, 4 * c.leaf);
   if (L.conv) {
     const size_t eb = gram ? 2 : (size_t)L.cbytes;  // bf16 frames in the Gram form
     put(L, L.xconv, eb * Xrows * L.D);
@@ -235,6 +243,9 @@ Work make_work(const Layout& L, void* ws, int d, int m, int precision, int cost)
   w.tpath = at<int2>(ws, L.tpath);
   w.cnt = at<int32_t>(ws, L.cnt);
   w.leaf_cost = at<double2>(ws, L.leaf_cost);
+  w.leaf_tk = at<int2>(ws, L.leaf_tk);
+  w.leaf_ring = at<uint64_t>(ws, L.leaf_ring);
+  w.leaf_done = at<int32_t>(ws, L.leaf_done);
   w.caps = L.caps;
   return w;
 }

@@ -84,6 +84,9 @@ struct LeafDesc {
   int32_t pair;
   int32_t first;           // 1 when the leaf starts at the pair's (0,0)
   int64_t scratch_off;     // word offset in leaf scratch, or -1 when it fits in LDS
+  int32_t stripe_off;      // first leaf-stripe ticket of the leaf
+  int32_t n_stripes;       // ceil(R / 64) stripes of the shorter side
+  int64_t ring_off;        // first cell of its min(n_stripes - 1, kRing) boundary rows in the leaf ring
 };
 
 // Device control block.
@@ -101,6 +104,9 @@ struct Ctl {
   int64_t leaf_words;   // leaf scratch words handed out
   int64_t cells;        // cells evaluated by the sweeps
   int64_t leaf_cells;   // cells of the leaf tables
+  int32_t leaf_stripes; // leaf-stripe tickets emitted so far
+  int32_t pad;
+  int64_t leaf_ring_cells;  // leaf-ring cells handed out
 };
 
 enum DeviceError : int32_t {
@@ -117,6 +123,7 @@ enum DeviceError : int32_t {
   kErrBadLeaf = 11,
   kErrBadPass = 12,
   kErrBadCount = 13,
+  kErrLeafRing = 14,
 };
 
 // Capacities chosen by the host planner (see plan_workspace in dtw_api.hip).
@@ -131,6 +138,8 @@ struct Caps {
   int64_t hist;      // histogram bins (max stripes + 1)
   int64_t leaf_words;// global leaf scratch words
   int64_t pslots;    // diagonal-indexed path scratch slots (sum of M+N-1)
+  int64_t leaf_tk;   // leaf-stripe tickets over all leaves
+  int64_t leaf_ring; // boundary-row cells between the stripes of all leaves
 };
 
 // Device pointers carved out of the caller's workspace; passed by value.
@@ -165,6 +174,9 @@ struct Work {
   int2* tpath;          // diagonal-indexed path scratch
   int32_t* cnt;         // cells written by the leaf that ends on this diagonal
   double2* leaf_cost;   // per leaf (hi, lo) compensated sum
+  int2* leaf_tk;        // leaf-stripe ticket -> (leaf, stripe)
+  uint64_t* leaf_ring;  // boundary rows between the stripes of a leaf (cells as in `ring`)
+  int32_t* leaf_done;   // per leaf: stripes whose pointers are complete
   uint64_t spin_ticks;  // bound on one boundary wait, device wall-clock ticks
   Caps caps;
 };

@@ -45,6 +45,8 @@ __global__ void init_kernel(Work w) {
   // boundary-row cells: writer id 0, which no stripe has
   for (int64_t u = tid; u < w.caps.ring * w.ring_words; u += nt) w.ring[u] = 0ull;
   for (int64_t u = tid; u < w.caps.pslots; u += nt) w.cnt[u] = 0;
+  for (int64_t u = tid; u < w.caps.leaf_ring * w.ring_words; u += nt) w.leaf_ring[u] = 0ull;
+  for (int64_t u = tid; u < w.caps.leaf; u += nt) w.leaf_done[u] = 0;
   for (int64_t u = tid; u < w.n_pairs; u += nt) w.smin[u] = __builtin_nan("");
 }
 
@@ -78,12 +80,13 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
   __syncthreads();
 
   int64_t leaf_base = clamp_count(ctl, ctl->n_leaf, w.caps.leaf), sub_base = 0, words_base = ctl->leaf_words;
+  int64_t lstripe_base = ctl->leaf_stripes, lring_base = ctl->leaf_ring_cells;
   for (int64_t tile = 0; tile < n_cand; tile += nt) {
     const int64_t ci = tile + tid;
     const bool valid = ci < n_cand;
     Block c = {0, 0, 0, 0, 0, 0};
     bool is_leaf = false;
-    int64_t words = 0;
+    int64_t words = 0, nst = 0, lcells = 0;
     if (valid) {
       if (level == 0) {
         const PairDesc pd = w.pairs[ci];
@@ -117,29 +120,47 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       const int64_t Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
       is_leaf = (Mb < m) || (Nb < m);
       if (is_leaf) {
-        // pointer words by stripe and step (see the leaf kernel), then the
-        // bottom row of a stripe in the compute type (at most 2 words each)
+        // pointer words by stripe and step (see the leaf kernel).  A leaf of
+        // one stripe keeps them in LDS when they fit (with room for a bottom
+        // row of the compute type, at most 2 words per column); a leaf of
+        // several stripes runs them on several workgroups, so its pointers
+        // are in global scratch and its stripes hand their bottom rows over
+        // through (n_stripes - 1) rows of the leaf ring.
         const int64_t R = min(Mb, Nb), Cc = max(Mb, Nb);
-        const int64_t bpw = ((R + kWave - 1) / kWave) * ((Cc + kWave - 1 + 15) / 16) * kWave;
+        nst = (R + kWave - 1) / kWave;
+        const int64_t bpw = nst * ((Cc + kWave - 1 + 15) / 16) * kWave;
         const int64_t need = bpw + 2 * Cc;
-        if (need * 4 > lds_leaf_bytes) words = need;
+        if (nst > 1 || need * 4 > lds_leaf_bytes) words = need;
+        lcells = min(nst - 1, (int64_t)kRing) * Cc;
       }
     }
     int64_t tot_leaf, tot_sub, tot_words;
     const int64_t lrank = block_excl_scan(valid && is_leaf ? 1 : 0, tmp, &tot_leaf);
     const int64_t srank = block_excl_scan(valid && !is_leaf ? 1 : 0, tmp, &tot_sub);
     const int64_t wrank = block_excl_scan(words, tmp, &tot_words);
+    int64_t tot_nst, tot_lcells;
+    const int64_t strank = block_excl_scan(nst, tmp, &tot_nst);
+    const int64_t crank = block_excl_scan(lcells, tmp, &tot_lcells);
     if (valid && is_leaf) {
       const int64_t li = leaf_base + lrank;
-      if (li < w.caps.leaf) {
+      const int64_t so = lstripe_base + strank, ro = lring_base + crank;
+      if (li >= w.caps.leaf || so + nst > w.caps.leaf_tk) {
+        set_error(ctl, kErrLeafCap);
+      } else if (ro + lcells > w.caps.leaf_ring) {
+        set_error(ctl, kErrLeafRing);
+      } else {
         const PairDesc pd = w.pairs[c.pair];
         LeafDesc L;
         L.i0 = c.i0; L.j0 = c.j0; L.i1 = c.i1; L.j1 = c.j1; L.pair = c.pair;
         L.first = (c.i0 == pd.x_off && c.j0 == pd.y_off) ? 1 : 0;
         L.scratch_off = words ? words_base + wrank : -1;
+        L.stripe_off = (int32_t)so;
+        L.n_stripes = (int32_t)nst;
+        L.ring_off = ro;
         w.leaves[li] = L;
-      } else {
-        set_error(ctl, kErrLeafCap);
+        // the leaf's tickets: its stripes top to bottom, consecutive, so a
+        // stripe only waits on stripes of lower tickets
+        for (int u = 0; u < nst; ++u) w.leaf_tk[so + u] = make_int2((int32_t)li, u);
       }
     }
     if (valid && !is_leaf) {
@@ -150,6 +171,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
     leaf_base += tot_leaf;
     sub_base += tot_sub;
     words_base += tot_words;
+    lstripe_base += tot_nst;
+    lring_base += tot_lcells;
   }
   // cur[] was written by rank, i.e. by other threads than the ones that read
   // it below: every write must be visible before the descriptor loop.
@@ -298,6 +321,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       ctl->n_chunks = (int32_t)chunk_base;
       ctl->n_leaf = (int32_t)min(leaf_base, w.caps.leaf);
       ctl->leaf_words = words_base;
+      ctl->leaf_stripes = (int32_t)min(lstripe_base, w.caps.leaf_tk);
+      ctl->leaf_ring_cells = lring_base;
       if (n_sub_run > 0) ctl->levels_run += 1;
     }
   } else if (tid == 0) {
@@ -307,6 +332,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
     ctl->n_chunks = 0;
     ctl->n_leaf = (int32_t)min(leaf_base, w.caps.leaf);
     ctl->leaf_words = words_base;
+    ctl->leaf_stripes = (int32_t)min(lstripe_base, w.caps.leaf_tk);
+    ctl->leaf_ring_cells = lring_base;
   }
 }
 

@@ -731,10 +731,17 @@ __device__ __forceinline__ void leaf_step(T c, T bv, T& f, T& up_prev, uint32_t&
   word |= code << (2 * (t & 15));
 }
 
+template <typename T>
+__device__ __forceinline__ void leaf_pub(int t, int lane, const T* cring, T* brow, uint64_t* ring_out,
+                                         uint32_t tag_out, int Cc) {
+  if (ring_out) publish<T>(t, lane, cring, ring_out, tag_out, Cc - 1);
+  else leaf_publish<T>(t, lane, cring, brow, Cc);
+}
+
 template <typename T, bool TR>
 __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr, int n_steps, int n_phases,
-                                             bool has_succ, uint32_t* bpst, T* brow, T* cring,
-                                             const T* bring, int lane) {
+                                             bool has_succ, uint32_t* bpst, T* brow, uint64_t* ring_out,
+                                             uint32_t tag_out, T* cring, const T* bring, int lane) {
   const T INF = inf_t<T>();
   // Unpredicated steps as in the pass kernel: +inf before a lane's row
   // starts, DIAG = 0 for the block's first cell.
@@ -777,7 +784,7 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
           }
           if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
             hp[u * kWave] = f;
-            if (has_succ) leaf_publish<T>(t0 + u, lane, cring, brow, S.Cc);
+            if (has_succ) leaf_pub<T>(t0 + u, lane, cring, brow, ring_out, tag_out, S.Cc);
           }
         }
       }
@@ -796,7 +803,7 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
           // 63 has just written: LDS operations of one wave are in order, and
           // this keeps the compiler from reordering them
           __builtin_amdgcn_wave_barrier();
-          if (has_succ) leaf_publish<T>(t, lane, cring, brow, S.Cc);
+          if (has_succ) leaf_pub<T>(t, lane, cring, brow, ring_out, tag_out, S.Cc);
         }
       }
     }
@@ -806,14 +813,29 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
   return f;  // lane Lr ends on the stripe's last cell (its column Cc-1 is the last step)
 }
 
+// Stripes s_lo..s_hi of a leaf, one after the other.  A stripe's bottom row
+// reaches the next one through `brow` (same workgroup), or, when `ring`
+// rows are given (the leaf's stripes run on several workgroups), through the
+// leaf ring with the sweep's cell protocol and reuse rule: stripe s
+// publishes into ring row s % kRing with id tag0 + s and its successor polls
+// that row for that id.
+struct LeafRing {
+  uint64_t* rows;  // row s: the bottom row of stripe s, Cc cells; nullptr: brow
+  uint32_t tag0;
+};
+
 template <typename T, int D, int CM>
 __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* __restrict__ ColSrc,
                                         const float* __restrict__ RowN, const float* __restrict__ ColN,
                                         const LeafShape& S, uint32_t* bp, T* brow, T* cring, T* bring,
-                                        int wave, int lane) {
+                                        int wave, int lane, int s_lo, int s_hi, LeafRing rg, const Work& w) {
   const T INF = inf_t<T>();
   T fend = T(0);
-  for (int sw = 0; sw < S.R; sw += kWave) {
+  for (int sw = s_lo * kWave; sw <= s_hi * kWave && sw < S.R; sw += kWave) {
+    const int st = sw / kWave;
+    constexpr int kCW = kCellWords<T>;
+    uint64_t* const ring_out = rg.rows ? rg.rows + (int64_t)(st % kRing) * S.Cc * kCW : nullptr;
+    const uint64_t* const ring_in = rg.rows ? rg.rows + (int64_t)((st + kRing - 1) % kRing) * S.Cc * kCW : nullptr;
     const int Lr = min(kWave - 1, S.R - 1 - sw);
     const int n_steps = S.Cc + Lr;
     const int n_phases = (n_steps + kPhase - 1) / kPhase;
@@ -822,8 +844,10 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     if (wave == 0) {
       uint32_t* bpst = bp + (int64_t)(sw / kWave) * S.Wm * kWave;
       gram_stage_barrier<CM>();
-      fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, lane)
-                  : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, cring, bring, lane);
+      fend = S.tr ? leaf_recurrence<T, true>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, ring_out,
+                                             rg.tag0 + st, cring, bring, lane)
+                  : leaf_recurrence<T, false>(S, sw, Lr, n_steps, n_phases, has_succ, bpst, brow, ring_out,
+                                              rg.tag0 + st, cring, bring, lane);
     } else if (wave <= kProducers && is_gram(CM)) {
       // ------------------------------------------------ frame costs, Gram form (BF16 or FP16 frames)
       if constexpr (is_gram(CM))
@@ -881,10 +905,24 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
     } else {
       // ------------------------------------------------ boundary input
       gram_stage_barrier<CM>();
-      for (int k = -1; k < n_phases; ++k) {
-        const int col = (k + 1) * kPhase + lane;
-        if (lane < kPhase) bring[col & (2 * kPhase - 1)] = (has_pred && col < S.Cc) ? brow[col] : INF;
-        lds_barrier();
+      if (ring_in) {
+        // lanes 0..kPhase*kCW-1: word lane % kCW of column lane / kCW of the chunk
+        for (int k = -1; k < n_phases; ++k) {
+          const int col = (k + 1) * kPhase + lane / kCW;
+          if (lane < kPhase * kCW) {
+            uint32_t half = (kCW == 2) ? ((lane % 2) ? 0x7FF00000u : 0u) : 0x7F800000u;  // a half of +inf
+            if (has_pred && col < S.Cc)
+              half = (uint32_t)poll_word(ring_in + (int64_t)col * kCW + lane % kCW, rg.tag0 + st - 1, w);
+            reinterpret_cast<uint32_t*>(bring)[(col & (2 * kPhase - 1)) * kCW + lane % kCW] = half;
+          }
+          lds_barrier();
+        }
+      } else {
+        for (int k = -1; k < n_phases; ++k) {
+          const int col = (k + 1) * kPhase + lane;
+          if (lane < kPhase) bring[col & (2 * kPhase - 1)] = (has_pred && col < S.Cc) ? brow[col] : INF;
+          lds_barrier();
+        }
       }
     }
     // the stripe's bottom row and pointers are complete for the next stripe
@@ -900,62 +938,108 @@ __device__ __forceinline__ T leaf_sweep(const T* __restrict__ RowSrc, const T* _
 // vertical: a bit scan over the row's packed 2-bit codes finds it, one word
 // of 16 steps at a time. The row's run of cells is then stored by the lanes
 // at once, backwards from slot_end of the diagonal-indexed path scratch.
-// Returns the number of cells written (the block's first cell only for the
-// pair's first leaf: otherwise it is the previous leaf's last cell).
-__device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShape& S, const LeafDesc& Lf,
-                                              const PairDesc& pd, int64_t slot_end, int2* tpath, int lane) {
-  const int R = __builtin_amdgcn_readfirstlane(S.R), Cc = __builtin_amdgcn_readfirstlane(S.Cc);
-  const int Wm = __builtin_amdgcn_readfirstlane(S.Wm);
-  const bool tr = __builtin_amdgcn_readfirstlane(S.tr ? 1 : 0) != 0;
-  const bool first = __builtin_amdgcn_readfirstlane(Lf.first) != 0;
-  const int oi = __builtin_amdgcn_readfirstlane((int)(Lf.i0 - pd.x_off));  // block origin in the pair
-  const int oj = __builtin_amdgcn_readfirstlane((int)(Lf.j0 - pd.y_off));
+// The walk goes stripe by stripe (walk_rows takes the rows of stripe s from
+// its block of pointer words, wherever that block is), then walk_row0 ends it
+// on row 0; the result is the number of cells written (the block's first
+// cell only for the pair's first leaf: otherwise it is the previous leaf's
+// last cell).
+struct LeafWalk {
+  int R, Cc, Wm, oi, oj;  // wave-uniform shape and block origin in the pair
+  bool tr, first;
+  int ri, cj, cnt;        // position and cells written so far
+  int64_t slot_end;
+};
+
+__device__ __forceinline__ LeafWalk walk_begin(const LeafShape& S, const LeafDesc& Lf, const PairDesc& pd,
+                                               int64_t slot_end) {
+  LeafWalk k;
+  k.R = __builtin_amdgcn_readfirstlane(S.R);
+  k.Cc = __builtin_amdgcn_readfirstlane(S.Cc);
+  k.Wm = __builtin_amdgcn_readfirstlane(S.Wm);
+  k.tr = __builtin_amdgcn_readfirstlane(S.tr ? 1 : 0) != 0;
+  k.first = __builtin_amdgcn_readfirstlane(Lf.first) != 0;
+  k.oi = __builtin_amdgcn_readfirstlane((int)(Lf.i0 - pd.x_off));
+  k.oj = __builtin_amdgcn_readfirstlane((int)(Lf.j0 - pd.y_off));
+  k.ri = k.R - 1;
+  k.cj = k.Cc - 1;
+  k.cnt = 0;
+  k.slot_end = slot_end;
+  return k;
+}
+
+// Rows of stripe s (ri >> 6 == s, ri > 0); blk holds the stripe's pointer
+// words, word b of lane r at blk[b * 64 + r].  One row is a straight line of
+// scalar work in the common case (the row's run ends in the word of its
+// entry step); a run that crosses into earlier words takes the inner loop.
+__device__ __forceinline__ void walk_rows(const uint32_t* blk, int s, LeafWalk& k, int2* tpath, int lane) {
   constexpr uint32_t kLo = 0x55555555u;  // bit 0 of every 2-bit field
-  int cnt = 0;
-  int ri = R - 1, cj = Cc - 1;
   // code 0 DIAG; 1 UP and 2 LEFT in the block's own orientation, swapped
   // when transposed. A move along the row (cj - 1) is code 2 or 3, or code 1
   // when transposed; field mask of the other codes:
   //   not transposed: hi bit clear;  transposed: hi bit set or lo bit clear.
-  for (int guard = 0; guard < R && ri > 0; ++guard) {
-    const int r = ri & (kWave - 1), s = ri >> 6;
-    int t = cj + r;  // step of (ri, cj) in lane r's pointer words
-    int tx = r;      // step where the row is left (column 0 when no other code is found)
-    uint32_t v = 1u; // the code there
-    for (int g = 0; g < Wm; ++g) {
-      const int b = t >> 4, p = t & 15;
-      const uint32_t wd = (uint32_t)__builtin_amdgcn_readfirstlane((int)bp[(s * Wm + b) * kWave + r]);
-      const uint32_t lo = wd & kLo, hi = (wd >> 1) & kLo;
-      uint32_t m = tr ? (hi | (~lo & kLo)) : (~hi & kLo);
-      if (p < 15) m &= (1u << (2 * p + 2)) - 1u;  // steps b*16 .. t
-      if (m != 0u) {
-        const int f = (31 - __builtin_clz(m)) >> 1;
-        tx = (b << 4) + f;
-        v = (wd >> (2 * f)) & 3u;
-        break;
-      }
-      if ((b << 4) <= r) break;  // this word holds column 0: the run reaches it
-      t = (b << 4) - 1;
+  const bool tr = k.tr;
+  auto stop_mask = [tr](uint32_t wd) -> uint32_t {
+    const uint32_t lo = wd & kLo, hi = (wd >> 1) & kLo;
+    return tr ? (hi | (~lo & kLo)) : (~hi & kLo);
+  };
+  const int lo_row = max(s * kWave, 1);
+  // a cell (ri, c) of the row is written as (rbase + ri, cbase + c), or
+  // swapped when transposed
+  const int rbase = tr ? k.oj : k.oi, cbase = tr ? k.oi : k.oj;
+  int ri = k.ri, cj = k.cj, cnt = k.cnt;
+  while (ri >= lo_row) {
+    const int r = ri & (kWave - 1);
+    const int t = cj + r;  // step of (ri, cj) in lane r's pointer words
+    int b = t >> 4;
+    uint32_t wd = (uint32_t)__builtin_amdgcn_readfirstlane((int)blk[b * kWave + r]);
+    const int p = t & 15;
+    uint32_t m = stop_mask(wd) & ((p < 15) ? ((1u << (2 * p + 2)) - 1u) : ~0u);  // steps b*16 .. t
+    while (m == 0u && (b << 4) > r) {  // the run continues into the previous word
+      --b;
+      wd = (uint32_t)__builtin_amdgcn_readfirstlane((int)blk[b * kWave + r]);
+      m = stop_mask(wd);
     }
-    const int cx = max(tx - r, 0);  // a code found left of column 0 is not the row's
-    const int n = cj - cx + 1;      // cells (ri, cj) .. (ri, cx)
-    for (int q0 = 0; q0 < n; q0 += kWave) {
-      const int q = q0 + lane;
-      if (q < n) tpath[slot_end - cnt - q] = tr ? make_int2(oi + cj - q, oj + ri) : make_int2(oi + ri, oj + cj - q);
+    const int f = (31 - __builtin_clz(m | 1u)) >> 1;  // field of the stop (unused when m == 0)
+    // column where the row is left: 0 when the run reaches column 0 or the
+    // stop lies left of it (not the row's)
+    const int cx = (m != 0u) ? max((b << 4) + f - r, 0) : 0;
+    const bool diag = (m != 0u) && ((wd >> (2 * f)) & 3u) == 0u;
+    const int n = cj - cx + 1;  // cells (ri, cj) .. (ri, cx)
+    int2* const row_end = tpath + (k.slot_end - cnt);
+    const int cv = cbase + cj - lane, rv = rbase + ri;
+    if (lane < n) row_end[-lane] = tr ? make_int2(cv, rv) : make_int2(rv, cv);
+    for (int q0 = kWave; q0 < n; q0 += kWave) {  // runs longer than a wave
+      if (q0 + lane < n) row_end[-(q0 + lane)] = tr ? make_int2(cv - q0, rv) : make_int2(rv, cv - q0);
     }
     cnt += n;
     // leave the row: straight up at column 0 (the only move), DIAG for code 0, else up
-    cj = (cx == 0) ? 0 : ((v == 0u) ? cx - 1 : cx);
+    cj = (cx == 0) ? 0 : (diag ? cx - 1 : cx);
     --ri;
   }
-  // row 0: cells (0, cj) .. (0, 1), and (0, 0) for the pair's first leaf
-  const int n0 = cj + (first ? 1 : 0);
+  k.ri = ri;
+  k.cj = cj;
+  k.cnt = cnt;
+}
+
+// Row 0: cells (0, cj) .. (0, 1), and (0, 0) for the pair's first leaf.
+__device__ __forceinline__ int walk_row0(LeafWalk& k, int2* tpath, int lane) {
+  const int n0 = k.cj + (k.first ? 1 : 0);
   for (int q0 = 0; q0 < n0; q0 += kWave) {
     const int q = q0 + lane;
-    if (q < n0) tpath[slot_end - cnt - q] = tr ? make_int2(oi + cj - q, oj) : make_int2(oi, oj + cj - q);
+    if (q < n0)
+      tpath[k.slot_end - k.cnt - q] = k.tr ? make_int2(k.oi + k.cj - q, k.oj) : make_int2(k.oi, k.oj + k.cj - q);
   }
-  cnt += n0;
-  return cnt;
+  k.cnt += n0;
+  return k.cnt;
+}
+
+// The whole walk over pointer words bp in one memory space (the leaf's LDS
+// or its global scratch), stripe block s at bp + s * Wm * 64.
+__device__ __forceinline__ int leaf_backtrace(const uint32_t* bp, const LeafShape& S, const LeafDesc& Lf,
+                                              const PairDesc& pd, int64_t slot_end, int2* tpath, int lane) {
+  LeafWalk k = walk_begin(S, Lf, pd, slot_end);
+  for (int s = (k.R - 1) >> 6; s >= 0; --s) walk_rows(bp + (int64_t)s * k.Wm * kWave, s, k, tpath, lane);
+  return walk_row0(k, tpath, lane);
 }
 
 // The FP64 frame cost of one path cell from the caller's frames (FP64 or
@@ -987,6 +1071,34 @@ __device__ __forceinline__ double path_cell_cost(const TI* xr, const TI* yr, int
   }
 }
 
+// Wait until `*p` reaches `target` (another workgroup's stripes of the same
+// leaf, all dequeued before this one, count themselves done there), bounded
+// like poll_word; every lane of the calling wave polls the same word.
+__device__ __forceinline__ void wait_count(const int32_t* p, int32_t target, const Work& w) {
+  if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return;
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t it = 0;; ++it) {
+    __builtin_amdgcn_s_sleep(2);
+    const int32_t err = __hip_atomic_load(&w.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target || err != 0) return;
+    if (wall_clock64() - t0 > w.spin_ticks || it > kSpinIterCap) {
+      set_error(w.ctl, kErrSpinTimeout);
+      return;
+    }
+  }
+}
+
+// Leaf tickets are (leaf, stripe) pairs, a leaf's stripes top to bottom on
+// consecutive tickets.  A leaf of one stripe is solved by one workgroup with
+// its pointers in LDS when they fit.  The stripes of a taller leaf run on as
+// many workgroups as take their tickets, chained through the leaf ring like
+// the sweep's stripes; each writes its pointer words to the leaf's global
+// scratch, and every stripe but the last then counts itself done in
+// leaf_done (after a release fence).  The workgroup of the last stripe waits
+// for that count (its stripes were dequeued before it, so they run) and
+// walks the path back, copying each stripe's pointer block from global
+// scratch into LDS while the recurrence wave walks the one before, when two
+// blocks fit there.
 template <typename T, int D, int CM>
 __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
     const T* __restrict__ X, const T* __restrict__ Y, Work w, int64_t lds_leaf_bytes, const void* Xorig,
@@ -994,30 +1106,40 @@ __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
   extern __shared__ __align__(16) unsigned char lds_raw[];  // pointers and bottom row when they fit
   __shared__ T cring[kCostRing * kWave];
   __shared__ T bring[2 * kPhase];
-  __shared__ int sh_ticket;
+  __shared__ int sh_ticket, sh_cnt;
+  __shared__ double2 sh_acc[kLeafThreads / kWave];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
   if (wave == 0) __builtin_amdgcn_s_setprio(3);  // the recurrence wave sets the pace
   Ctl* ctl = w.ctl;
   const int n_leaf = clamp_count(ctl, ctl->n_leaf, w.caps.leaf);
-  (void)lds_leaf_bytes;
+  const int n_tk = clamp_count(ctl, ctl->leaf_stripes, w.caps.leaf_tk);
 
-  for (int iter = 0; iter <= n_leaf; ++iter) {  // each iteration consumes one ticket
+  for (int iter = 0; iter <= n_tk; ++iter) {  // each iteration consumes one ticket
     if (threadIdx.x == 0) sh_ticket = call_failed(w) ? -1 : atomicAdd(&ctl->leaf_ticket, 1);
     lds_barrier();
     const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
     lds_barrier();
-    if (tk >= n_leaf || tk < 0) break;
-    const LeafDesc Lf = w.leaves[tk];
+    if (tk >= n_tk || tk < 0) break;
+    const int2 lt = w.leaf_tk[tk];
+    const int li = __builtin_amdgcn_readfirstlane(lt.x), st = __builtin_amdgcn_readfirstlane(lt.y);
+    if (li < 0 || li >= n_leaf) {
+      if (threadIdx.x == 0) set_error(ctl, kErrBadLeaf);
+      continue;
+    }
+    const LeafDesc Lf = w.leaves[li];
     if (Lf.pair < 0 || Lf.pair >= w.n_pairs) {
       if (threadIdx.x == 0) set_error(ctl, kErrBadLeaf);
       continue;
     }
     const PairDesc pd = w.pairs[Lf.pair];
     const int Mb = Lf.i1 - Lf.i0 + 1, Nb = Lf.j1 - Lf.j0 + 1;
-    // a leaf lies inside its pair and is non-empty; refuse anything else
+    // a leaf lies inside its pair and is non-empty, its stripe count and
+    // this ticket's stripe agree with its shape; refuse anything else
+    const int nst = __builtin_amdgcn_readfirstlane(Lf.n_stripes);
     if (Mb < 1 || Nb < 1 || Lf.i0 < pd.x_off || Lf.j0 < pd.y_off || Lf.i1 >= pd.x_off + pd.M ||
-        Lf.j1 >= pd.y_off + pd.N) {
+        Lf.j1 >= pd.y_off + pd.N || nst != (min(Mb, Nb) + kWave - 1) / kWave || st < 0 || st >= nst ||
+        Lf.stripe_off + st != tk || (nst > 1 && Lf.scratch_off < 0)) {
       if (threadIdx.x == 0) set_error(ctl, kErrBadLeaf);
       continue;
     }
@@ -1035,21 +1157,59 @@ __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
     const T* __restrict__ ColSrc = S.tr ? Xs : Ys;
     const float* __restrict__ RowN = S.tr ? w.Yn : w.Xn;
     const float* __restrict__ ColN = S.tr ? w.Xn : w.Yn;
-    const int64_t bpw = (int64_t)((S.R + kWave - 1) / kWave) * S.Wm * kWave;
+    const int64_t bpw = (int64_t)nst * S.Wm * kWave;
     const int64_t e = (int64_t)(Lf.i1 - pd.x_off) + (Lf.j1 - pd.y_off);
     const int64_t slot_end = pd.pbase + e;  // the block's last cell sits on diagonal e
     T fend;
     int cnt_written = 0;
-    if (Lf.scratch_off < 0) {
+    if (nst == 1 && Lf.scratch_off < 0) {
       uint32_t* bp = reinterpret_cast<uint32_t*>(lds_raw);
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
-                                  wave, lane);
+                                  wave, lane, 0, 0, LeafRing{nullptr, 0u}, w);
       if (wave == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath, lane);
-    } else {
+    } else if (nst == 1) {
       uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
-                                  wave, lane);
+                                  wave, lane, 0, 0, LeafRing{nullptr, 0u}, w);
       if (wave == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath, lane);
+    } else {
+      // one stripe of a taller leaf; ids of the leaf ring: 0xFF << 24 | (ticket + 1),
+      // unique within a call and never 0 (the ring is cleared when the call starts)
+      uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
+      const LeafRing rg{w.leaf_ring + Lf.ring_off * kCellWords<T>, (0xFFu << 24) | (uint32_t)(Lf.stripe_off + 1)};
+      fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, nullptr, cring, bring, wave, lane, st, st, rg,
+                                  w);
+      if (wave == 0) {
+        wait_vmem();       // this wave's pointer words (and published cells) are written
+        __threadfence();   // and visible to the other workgroups of the leaf
+      }
+      if (st < nst - 1) {
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&w.leaf_done[li], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        continue;  // the last stripe's workgroup walks the path
+      }
+      if (wave == 0) wait_count(&w.leaf_done[li], nst - 1, w);
+      __syncthreads();
+      __threadfence();  // the other stripes' pointer words, read below
+      const int64_t blk = (int64_t)S.Wm * kWave;  // words of one stripe's pointer block
+      uint32_t* buf = reinterpret_cast<uint32_t*>(lds_raw);
+      if (2 * blk * 4 <= lds_leaf_bytes) {
+        LeafWalk k;
+        if (wave == 0) k = walk_begin(S, Lf, pd, slot_end);
+        for (int64_t u = threadIdx.x; u < blk; u += blockDim.x) buf[((nst - 1) & 1) * blk + u] = bp[(nst - 1) * blk + u];
+        __syncthreads();
+        for (int s = nst - 1; s >= 0; --s) {
+          if (wave == 0) {
+            walk_rows(buf + (s & 1) * blk, s, k, w.tpath, lane);
+          } else if (s > 0) {
+            for (int64_t u = threadIdx.x - kWave; u < blk; u += blockDim.x - kWave)
+              buf[((s - 1) & 1) * blk + u] = bp[(s - 1) * blk + u];
+          }
+          __syncthreads();
+        }
+        if (wave == 0) cnt_written = walk_row0(k, w.tpath, lane);
+      } else if (wave == 0) {
+        cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath, lane);
+      }
     }
 
     if (wave == 0) {
@@ -1059,26 +1219,38 @@ __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
         atomicAdd((unsigned long long*)&ctl->leaf_cells, (unsigned long long)((int64_t)S.R * S.Cc));
         if (Lf.first && Lf.i1 == pd.x_off + pd.M - 1 && Lf.j1 == pd.y_off + pd.N - 1)
           w.smin[Lf.pair] = (double)fend;
+        sh_cnt = cnt_written;
       }
-      // FP64 cost of the cells this leaf wrote, from the caller's inputs
-      cnt_written = __shfl(cnt_written, 0);
-      wait_vmem();  // lane 0's path cells are written before the wave reads them
-      double2 acc = make_double2(0.0, 0.0);
-      for (int q = lane; q < cnt_written; q += kWave) {
-        const int2 cell = w.tpath[slot_end - cnt_written + 1 + q];
-        const int64_t gi = pd.x_off + cell.x, gj = pd.y_off + cell.y;
-        const double c = in_f64 ? path_cell_cost<is_cos(CM)>(static_cast<const double*>(Xorig) + gi * d,
-                                                              static_cast<const double*>(Yorig) + gj * d, d)
-                                : path_cell_cost<is_cos(CM)>(static_cast<const float*>(Xorig) + gi * d,
-                                                              static_cast<const float*>(Yorig) + gj * d, d);
-        acc = two_sum_acc(acc, c);
-      }
-      // fixed-order tree reduction over the wave
-      for (int off = 1; off < kWave; off <<= 1) {
-        const double2 other = make_double2(__shfl_xor(acc.x, off), __shfl_xor(acc.y, off));
-        acc = ((lane & off) == 0) ? dd_add(acc, other) : dd_add(other, acc);
-      }
-      if (lane == 0) w.leaf_cost[tk] = acc;
+      wait_vmem();  // the path cells of the walk are written before the other waves read them
+    }
+    __syncthreads();
+    // FP64 cost of the cells this leaf wrote, from the caller's inputs, by
+    // every wave: thread u takes cells u, u + blockDim.x, ... (cells read
+    // past this CU's L1, which may hold an older copy of their lines)
+    const int nc = __builtin_amdgcn_readfirstlane(sh_cnt);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = threadIdx.x; q < nc; q += blockDim.x) {
+      const uint64_t cw = __hip_atomic_load(reinterpret_cast<const uint64_t*>(w.tpath + (slot_end - nc + 1 + q)),
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int2 cell = make_int2((int)(uint32_t)cw, (int)(uint32_t)(cw >> 32));
+      const int64_t gi = pd.x_off + cell.x, gj = pd.y_off + cell.y;
+      const double c = in_f64 ? path_cell_cost<is_cos(CM)>(static_cast<const double*>(Xorig) + gi * d,
+                                                            static_cast<const double*>(Yorig) + gj * d, d)
+                              : path_cell_cost<is_cos(CM)>(static_cast<const float*>(Xorig) + gi * d,
+                                                            static_cast<const float*>(Yorig) + gj * d, d);
+      acc = two_sum_acc(acc, c);
+    }
+    // fixed-order tree reduction over each wave, then over the waves in order
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double2 other = make_double2(__shfl_xor(acc.x, off), __shfl_xor(acc.y, off));
+      acc = ((lane & off) == 0) ? dd_add(acc, other) : dd_add(other, acc);
+    }
+    if (lane == 0) sh_acc[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double2 tot = sh_acc[0];
+      for (int v = 1; v < kLeafThreads / kWave; ++v) tot = dd_add(tot, sh_acc[v]);
+      w.leaf_cost[li] = tot;
     }
   }
 }

@@ -57,6 +57,8 @@ inline int cpu_update_dpp(int old, int src, int ctrl) {
 #define __HIP_MEMORY_SCOPE_WORKGROUP 1
 #define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
 #define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
+#define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_SEQ_CST)
+#define __threadfence() std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_s_waitcnt(x) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_wave_barrier() cpu_wave_barrier->arrive_and_wait()
 #define __builtin_amdgcn_s_setprio(n) ((void)0)

@@ -351,3 +351,21 @@ def test_wave_model_gram_cosine(model_exe, wave_exe, M, N, d, m, prec):
     assert oracle.path_cost(X, Y, path, cost="cosine") == pytest.approx(cost, rel=1e-12)
     print("rel", (cost - c_ref) / c_ref)
     assert -1e-12 <= (cost - c_ref) / c_ref <= (BF16_REL_TOL if prec == 2 else 1e-5)
+
+
+@pytest.mark.parametrize("M,N,d,fam", [(200, 230, 4, "normal"), (230, 200, 1, "int3"), (100, 3200, 2, "normal"),
+                                       (3100, 90, 1, "int3")])
+def test_wave_model_leaf_on_several_workgroups(wave_exe, M, N, d, fam):
+    # one leaf (m = 500) whose stripes run on the model's two workgroups,
+    # chained through the leaf ring: four stripes (ring rows reused, walk
+    # through pointer blocks copied into LDS two at a time), and a leaf so
+    # wide that two pointer blocks do not fit the LDS (walk from global
+    # scratch); continuous and tie-heavy integer frames
+    X, Y = synth.random_pair(9300 + M + N, M, N, d, fam)
+    r = run_model(wave_exe, [(X, Y)], 500)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    assert r["polls"] > 0
+    cost, path = r["results"][0]
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * c_ref
