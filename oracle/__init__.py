@@ -64,6 +64,10 @@ def load(path: str):
     L.dtwo_linmdtw.argtypes = [dp, i64, dp, i64, i32, i32, dp, ip, i64, lp, dp, lp, ip, i64, lp]
     L.dtwo_path_cost.restype = ctypes.c_double
     L.dtwo_path_cost.argtypes = [dp, i64, dp, i64, i32, ip, i64]
+    L.dtwo_tie_pivot.restype = ctypes.c_int
+    L.dtwo_tie_pivot.argtypes = [dp, dp, i32, i64, i64, i64, i64, ctypes.c_double, lp, lp, dp]
+    L.dtwo_linmdtw_tie.restype = ctypes.c_int
+    L.dtwo_linmdtw_tie.argtypes = [dp, i64, dp, i64, i32, i32, dp, ip, i64, lp, lp, ip, i64, lp]
     return L
 
 
@@ -219,6 +223,36 @@ def linmdtw(X, Y, min_block: int = 500, pivots_cap: int = 1 << 16, L=None, cost=
         raise RuntimeError(f"dtwo_linmdtw failed: {rc}")
     return dict(cost=cost.value, path=path[: n.value].copy(), s_min=smin.value,
                 cells=cells.value, pivots=piv[: npiv.value].copy())
+
+
+def tie_pivot(X, Y, i0, j0, i1, j1, f0, L=None, cost="euclidean"):
+    """One tie-exact split of a block whose origin holds f0: (row, diagonal,
+    accumulated cost) of the pivot, in the block's local coordinates."""
+    X, Y = _as2d(X), _as2d(Y)
+    a, k, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    with _CostScope(L or lib(), cost) as lb:
+        rc = lb.dtwo_tie_pivot(_dp(X), _dp(Y), X.shape[1], i0, j0, i1, j1, float(f0), ctypes.byref(a),
+                               ctypes.byref(k), ctypes.byref(f))
+    if rc:
+        raise RuntimeError(f"dtwo_tie_pivot failed: {rc}")
+    return a.value, k.value, f.value
+
+
+def linmdtw_tie(X, Y, min_block: int = 500, pivots_cap: int = 1 << 16, L=None, cost="euclidean"):
+    """Tie-exact divide and conquer: returns dict(cost, path, cells, pivots)."""
+    X, Y = _as2d(X), _as2d(Y)
+    M, d = X.shape
+    N = Y.shape[0]
+    c = ctypes.c_double()
+    cells, n, npiv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    path = np.zeros((M + N - 1, 2), dtype=np.int32)
+    piv = np.zeros((pivots_cap, 2), dtype=np.int32)
+    with _CostScope(L or lib(), cost) as lb:
+        rc = lb.dtwo_linmdtw_tie(_dp(X), M, _dp(Y), N, d, min_block, ctypes.byref(c), _ip(path), M + N - 1,
+                                 ctypes.byref(n), ctypes.byref(cells), _ip(piv), pivots_cap, ctypes.byref(npiv))
+    if rc:
+        raise RuntimeError(f"dtwo_linmdtw_tie failed: {rc}")
+    return dict(cost=c.value, path=path[: n.value].copy(), cells=cells.value, pivots=piv[: npiv.value].copy())
 
 
 def path_cost(X, Y, path, L=None, cost="euclidean") -> float:

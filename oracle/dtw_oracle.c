@@ -524,6 +524,176 @@ int dtwo_linmdtw(const double* X, int64_t M, const double* Y, int64_t N, int32_t
   return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Tie-exact divide and conquer (an addition to the paper's method; the
+ * paper breaks split ties arbitrarily, Sec. 3.2).  A split is chosen so that
+ * the concatenated path equals the textbook backtrace (Sec. 2.1, ties DIAG,
+ * UP, LEFT) on every input:
+ *  - the block's table is filled forward from its origin, whose accumulated
+ *    cost f0 is given (the value the whole problem's table holds there), so
+ *    every cell on the textbook path holds exactly its value in the whole
+ *    table;
+ *  - each cell carries a label: on local diagonals kf-1 and kf (kf = ceil(K/2),
+ *    K diagonals) the cell itself, past them the label of the predecessor
+ *    its backpointer names.  The end cell's label is the last cell of the
+ *    backtrace with a + b <= kf: the pivot;
+ *  - the left child keeps f0, the right child starts from the pivot's value.
+ * A cell off the textbook path can hold a larger value in a child's table
+ * than in the whole table, never a smaller one, so no backpointer on the path
+ * changes (the tie order is the same everywhere). */
+
+/* Forward table of the block rows i0..i1, columns j0..j1 with F(origin) =
+ * f0, labels as above; returns the pivot (local row a, local diagonal k) and
+ * its accumulated cost.  Requires Mb + Nb - 1 >= 4. */
+int dtwo_tie_pivot(const double* X, const double* Y, int32_t d, int64_t i0, int64_t j0, int64_t i1,
+                   int64_t j1, double f0, int64_t* piv_a, int64_t* piv_k, double* piv_f) {
+  const int64_t Mb = i1 - i0 + 1, Nb = j1 - j0 + 1;
+  if (!X || !Y || d < 1 || Mb < 1 || Nb < 1 || Mb + Nb - 1 < 4 || !piv_a || !piv_k || !piv_f) return -1;
+  const int64_t K = Mb + Nb - 1, kf = (K + 1) / 2;
+  double* F = (double*)malloc(sizeof(double) * (size_t)(Mb * Nb));
+  int64_t* lab = (int64_t*)malloc(sizeof(int64_t) * (size_t)(Mb * Nb));
+  if (!F || !lab) { free(F); free(lab); return -3; }
+  for (int64_t a = 0; a < Mb; ++a) {
+    for (int64_t b = 0; b < Nb; ++b) {
+      const double c = dtwo_frame_cost(X + (i0 + a) * d, Y + (j0 + b) * d, d);
+      double f;
+      int64_t from; /* index of the predecessor the backpointer names */
+      if (a == 0 && b == 0) {
+        f = f0;
+        from = -1;
+      } else if (a == 0) {
+        f = F[b - 1] + c;
+        from = b - 1;
+      } else if (b == 0) {
+        f = F[(a - 1) * Nb] + c;
+        from = (a - 1) * Nb;
+      } else {
+        const double dg = F[(a - 1) * Nb + (b - 1)], up = F[(a - 1) * Nb + b], lf = F[a * Nb + (b - 1)];
+        if (dg <= up && dg <= lf) { f = dg + c; from = (a - 1) * Nb + (b - 1); }
+        else if (up <= lf) { f = up + c; from = (a - 1) * Nb + b; }
+        else { f = lf + c; from = a * Nb + (b - 1); }
+      }
+      F[a * Nb + b] = f;
+      /* label: a cell on diagonal kf-1 or kf names itself (2a + [on kf]) */
+      if (a + b == kf - 1 || a + b == kf) lab[a * Nb + b] = 2 * a + (a + b == kf);
+      else lab[a * Nb + b] = from >= 0 ? lab[from] : -1;
+    }
+  }
+  const int64_t L = lab[Mb * Nb - 1];
+  int rc = 0;
+  if (L < 0) rc = -1;
+  else {
+    *piv_a = L / 2;
+    *piv_k = kf - 1 + (L % 2);
+    *piv_f = F[*piv_a * Nb + (*piv_k - *piv_a)];
+  }
+  free(F);
+  free(lab);
+  return rc;
+}
+
+/* Textbook table and backtrace of a block whose origin holds f0 (the segment
+ * of the whole problem's textbook path through that block). */
+static int full_block_from(const double* X, const double* Y, int32_t d, int64_t i0, int64_t j0, int64_t Mb,
+                           int64_t Nb, double f0, int32_t* seg, int64_t* n) {
+  double* F = (double*)malloc(sizeof(double) * (size_t)(Mb * Nb));
+  unsigned char* P = (unsigned char*)malloc((size_t)(Mb * Nb));
+  if (!F || !P) { free(F); free(P); return -3; }
+  for (int64_t a = 0; a < Mb; ++a)
+    for (int64_t b = 0; b < Nb; ++b) {
+      const double c = dtwo_frame_cost(X + (i0 + a) * d, Y + (j0 + b) * d, d);
+      double f;
+      unsigned char p = MOVE_DIAG;
+      if (a == 0 && b == 0) f = f0;
+      else if (a == 0) { f = F[b - 1] + c; p = MOVE_LEFT; }
+      else if (b == 0) { f = F[(a - 1) * Nb] + c; p = MOVE_UP; }
+      else {
+        const double dg = F[(a - 1) * Nb + (b - 1)], up = F[(a - 1) * Nb + b], lf = F[a * Nb + (b - 1)];
+        if (dg <= up && dg <= lf) { f = dg + c; p = MOVE_DIAG; }
+        else if (up <= lf) { f = up + c; p = MOVE_UP; }
+        else { f = lf + c; p = MOVE_LEFT; }
+      }
+      F[a * Nb + b] = f;
+      P[a * Nb + b] = p;
+    }
+  int64_t len = 0, a = Mb - 1, b = Nb - 1;
+  for (;;) {
+    seg[2 * len] = (int32_t)(i0 + a);
+    seg[2 * len + 1] = (int32_t)(j0 + b);
+    ++len;
+    if (a == 0 && b == 0) break;
+    const unsigned char p = P[a * Nb + b];
+    if (p == MOVE_DIAG) { --a; --b; }
+    else if (p == MOVE_UP) --a;
+    else --b;
+  }
+  for (int64_t u = 0, v = len - 1; u < v; ++u, --v) {
+    const int32_t ti = seg[2 * u], tj = seg[2 * u + 1];
+    seg[2 * u] = seg[2 * v];
+    seg[2 * u + 1] = seg[2 * v + 1];
+    seg[2 * v] = ti;
+    seg[2 * v + 1] = tj;
+  }
+  *n = len;
+  free(F);
+  free(P);
+  return 0;
+}
+
+static void tie_rec(rec_state* st, int64_t i0, int64_t j0, int64_t i1, int64_t j1, double f0) {
+  if (st->err) return;
+  const int64_t Mb = i1 - i0 + 1, Nb = j1 - j0 + 1;
+  if (Mb < st->m || Nb < st->m) {
+    int32_t* seg = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(Mb + Nb - 1));
+    if (!seg) { st->err = -3; return; }
+    int64_t n = 0;
+    const int rc = full_block_from(st->X, st->Y, st->d, i0, j0, Mb, Nb, f0, seg, &n);
+    if (rc) { free(seg); st->err = rc; return; }
+    st->cells += Mb * Nb;
+    append_segment(st, seg, n);
+    free(seg);
+    return;
+  }
+  int64_t pa = 0, pk = 0;
+  double pf = 0.0;
+  const int rc = dtwo_tie_pivot(st->X, st->Y, st->d, i0, j0, i1, j1, f0, &pa, &pk, &pf);
+  if (rc) { st->err = rc; return; }
+  st->cells += Mb * Nb;
+  const int64_t pi = i0 + pa, pj = j0 + (pk - pa);
+  if (st->piv && st->n_piv < st->piv_cap) {
+    st->piv[2 * st->n_piv] = (int32_t)pi;
+    st->piv[2 * st->n_piv + 1] = (int32_t)pj;
+  }
+  ++st->n_piv;
+  tie_rec(st, i0, j0, pi, pj, f0);
+  tie_rec(st, pi, pj, i1, j1, pf);
+}
+
+int dtwo_linmdtw_tie(const double* X, int64_t M, const double* Y, int64_t N, int32_t d, int32_t min_block,
+                     double* cost, int32_t* path, int64_t path_cap, int64_t* path_len, int64_t* cells,
+                     int32_t* pivots, int64_t pivots_cap, int64_t* n_pivots) {
+  if (!X || !Y || M < 1 || N < 1 || d < 1 || min_block < 3 || !cost || !path || !path_len) return -1;
+  if (path_cap < M + N - 1) return -2;
+  rec_state st;
+  memset(&st, 0, sizeof(st));
+  st.X = X;
+  st.Y = Y;
+  st.d = d;
+  st.m = min_block;
+  st.path = path;
+  st.cap = path_cap;
+  st.piv = pivots;
+  st.piv_cap = pivots ? pivots_cap : 0;
+  tie_rec(&st, 0, 0, M - 1, N - 1, dtwo_frame_cost(X, Y, d));
+  if (st.err) return st.err;
+  *path_len = st.len;
+  *cost = dtwo_path_cost(X, M, Y, N, d, path, st.len);
+  if (cells) *cells = st.cells;
+  if (n_pivots) *n_pivots = st.n_piv;
+  if (pivots && st.n_piv > pivots_cap) return -2;
+  return 0;
+}
+
 /* Eq. 1 evaluated along a path, after checking the path definition of
  * Sec. 2.1 (start, end, allowed steps). */
 double dtwo_path_cost(const double* X, int64_t M, const double* Y, int64_t N, int32_t d,

@@ -105,6 +105,23 @@ int dtwo_linmdtw(const double* X, int64_t M, const double* Y, int64_t N, int32_t
                  int64_t* path_len, double* s_min, int64_t* cells,
                  int32_t* pivots, int64_t pivots_cap, int64_t* n_pivots);
 
+/* Tie-exact divide and conquer (not in the paper, whose split ties are
+ * broken arbitrarily): the recursion of Algorithm 2 with the split taken from
+ * a forward table that carries, per cell, the last cell of its backtrace
+ * (ties DIAG, UP, LEFT) on local diagonal kf-1 or kf, kf = ceil(K/2); each
+ * block's table starts from the accumulated cost its origin holds in the
+ * whole problem's table.  The returned path equals dtwo_full's on every input.
+ * dtwo_tie_pivot: one split of the block rows i0..i1, columns j0..j1 whose
+ *   origin holds f0: pivot local row *piv_a on local diagonal *piv_k, and its
+ *   accumulated cost *piv_f.  Requires Mb + Nb - 1 >= 4.
+ * dtwo_linmdtw_tie: the whole recursion (cutoff as dtwo_linmdtw); cells
+ *   counts every full block table and leaf table; pivots as dtwo_linmdtw. */
+int dtwo_tie_pivot(const double* X, const double* Y, int32_t d, int64_t i0, int64_t j0, int64_t i1,
+                   int64_t j1, double f0, int64_t* piv_a, int64_t* piv_k, double* piv_f);
+int dtwo_linmdtw_tie(const double* X, int64_t M, const double* Y, int64_t N, int32_t d, int32_t min_block,
+                     double* cost, int32_t* path, int64_t path_cap, int64_t* path_len, int64_t* cells,
+                     int32_t* pivots, int64_t pivots_cap, int64_t* n_pivots);
+
 /* Sequential FP64 sum of C along a given path, in path order (the cost that
  * Eq. 1 assigns to a warping path).  Returns NaN when the path is not a valid
  * warping path for M x N (Sec. 2.1 definition). */

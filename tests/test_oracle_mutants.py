@@ -43,6 +43,11 @@ MUTANTS = {
     "cosine_unnormalised_x": ("double xt = nx > 0.0 ? x[t] / nx : 0.0;", "double xt = x[t];"),
     "cosine_distance_not_complemented": ("double c = 1.0 - s;", "double c = s;"),
     "cosine_zero_frame_nan": ("double yt = ny > 0.0 ? y[t] / ny : 0.0;", "double yt = y[t] / ny;"),
+    "tie_label_up_before_diag": ("if (dg <= up && dg <= lf) { f = dg + c; from = (a - 1) * Nb + (b - 1); }",
+                                 "if (dg < up && dg < lf) { f = dg + c; from = (a - 1) * Nb + (b - 1); }"),
+    "tie_label_drops_diagonal_bit": ("lab[a * Nb + b] = 2 * a + (a + b == kf);", "lab[a * Nb + b] = 2 * a;"),
+    "tie_label_not_inherited": ("else lab[a * Nb + b] = from >= 0 ? lab[from] : -1;",
+                                "else lab[a * Nb + b] = from >= 0 ? 2 * (from / Nb) : -1;"),
     "path_cost_scaled": ("s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d);",
                           "s += dtwo_frame_cost(X + (int64_t)i * d, Y + (int64_t)j * d, d) * 1.0000001;"),
 }
@@ -126,6 +131,18 @@ CHECKS = textwrap.dedent(r'''
         c, p = oracle.full(X, Y, L=L, cost="cosine")
         b, bp, _ = brute_dtw(X, Y, cost=cpy)
         check("cos_brute", abs(c - b) <= 1e-12 * max(1, b) and p.tolist() == [list(q) for q in bp])
+    # tie-exact recursion: the textbook path on tie-heavy inputs, and its
+    # top split on the textbook path
+    for s in range(6):
+        X, Y = synth.random_pair(7300 + s, 20 + 3 * s, 31 - 2 * s, 1, "int3")
+        c, p, F = oracle.full(X, Y, return_table=True, L=L)
+        for m in (3, 6):
+            check("tie_exact", oracle.linmdtw_tie(X, Y, min_block=m, L=L)["path"].tolist() == p.tolist())
+        M, N = X.shape[0], Y.shape[0]
+        kf = (M + N) // 2
+        a, k, f = oracle.tie_pivot(X, Y, 0, 0, M - 1, N - 1, F[0, 0], L=L)
+        last = [tuple(q) for q in p.tolist() if q[0] + q[1] <= kf][-1]
+        check("tie_pivot", (a, k - a) == last and f == F[last])
     # pivot tie rule on an all-tie input (every split cost is 0)
     Z = np.zeros((40, 1)); W = np.zeros((33, 1))
     r = oracle.linmdtw(Z, W, min_block=3, L=L)

@@ -490,3 +490,69 @@ def test_path_cost_rejects_invalid_paths():
     assert math.isnan(oracle.path_cost(X, Y, [[0, 1], [1, 2], [2, 3], [3, 3]]))
     c, p = oracle.full(X, Y)
     assert oracle.path_cost(X, Y, p) == c
+
+
+# ------------------------------------------- tie-exact divide and conquer (not in the paper)
+#
+# The split of each block is read from labels carried by a forward table
+# that starts from the origin's accumulated cost in the whole problem; the
+# concatenated path must be the textbook backtrace (ties DIAG, UP, LEFT) on
+# every input, also where exact ties make Algorithm 2's split ambiguous.
+
+def _last_cell_at_or_before(path, kf):
+    cells = [tuple(c) for c in path.tolist() if c[0] + c[1] <= kf]
+    return cells[-1]
+
+
+@pytest.mark.parametrize("fam,d", [("int3", 1), ("normal", 3), ("int3", 2)])
+def test_tie_pivot_is_the_textbook_paths_cell(fam, d):
+    # the label read at the end cell names the textbook path's last cell on
+    # or before diagonal kf, and its accumulated cost is the table's, bit for bit
+    for seed in range(40):
+        rng = np.random.default_rng(7000 + seed)
+        M, N = (int(v) for v in rng.integers(3, 40, 2))
+        X, Y = synth.random_pair(7000 + seed, M, N, d, fam)
+        c, p, F = oracle.full(X, Y, return_table=True)
+        K = M + N - 1
+        kf = (K + 1) // 2
+        a, k, f = oracle.tie_pivot(X, Y, 0, 0, M - 1, N - 1, F[0, 0])
+        assert (a, k - a) == _last_cell_at_or_before(p, kf)
+        assert k in (kf - 1, kf)
+        assert f == F[a, k - a]
+
+
+def test_tie_pivot_of_a_child_block_keeps_the_whole_tables_values():
+    # the right child of the top split starts from the pivot's value; its own
+    # pivot is again a textbook path cell whose value equals the whole
+    # table's (a child's table can only be larger off the path)
+    for seed in range(30):
+        X, Y = synth.random_pair(7100 + seed, 45, 38, 1, "int3")
+        c, p, F = oracle.full(X, Y, return_table=True)
+        a, k, f = oracle.tie_pivot(X, Y, 0, 0, 44, 37, F[0, 0])
+        i0, j0 = a, k - a
+        a2, k2, f2 = oracle.tie_pivot(X, Y, i0, j0, 44, 37, f)
+        cell = (i0 + a2, j0 + k2 - a2)
+        assert cell in [tuple(q) for q in p.tolist()]
+        assert f2 == F[cell]
+
+
+@pytest.mark.parametrize("fam,d,m", [("int3", 1, 3), ("int3", 1, 8), ("int3", 2, 5), ("normal", 3, 3),
+                                     ("normal", 4, 16), ("zeros", 2, 4)])
+def test_tie_exact_recursion_equals_textbook(fam, d, m):
+    differs = 0
+    for seed in range(60):
+        rng = np.random.default_rng(7200 + seed)
+        M, N = (int(v) for v in rng.integers(3, 70, 2))
+        if fam == "zeros":  # every frame cost 0: every path is optimal
+            X, Y = np.zeros((M, d)), np.zeros((N, d))
+        else:
+            X, Y = synth.random_pair(7200 + seed, M, N, d, fam)
+        c, p = oracle.full(X, Y)
+        r = oracle.linmdtw_tie(X, Y, min_block=m)
+        assert r["path"].tolist() == p.tolist()
+        assert r["cost"] == oracle.path_cost(X, Y, p)
+        differs += oracle.linmdtw(X, Y, min_block=m)["path"].tolist() != p.tolist()
+    if fam != "normal":
+        # the inputs do exercise ties: Algorithm 2's own split leaves the
+        # textbook path on some of them
+        assert differs > 0
