@@ -14,14 +14,15 @@ the per-class breakdown from untimed runs with events around every launch.  The 
 DTW timed single-threaded on this host.
 
 The default run also measures, in the same process, the two other targets
-of the method's AI-systems forms (unless --no-extras):
+of the method's AI-systems forms, and the tie-exact mode (unless --no-extras):
   long_pair  the 200000 x 160000, d = 128 pair in the BF16 and FP16 Gram
              forms, each against the all-FP64 path on the same input (time,
              relative cost error, frame deviation of the path);
   serving    a Poisson stream of 96 requests, M log-uniform in [2000, 400000],
              through the serving loop in the BF16 and FP16 mixes, against every
              request one at a time through the plain FP64 path (throughput
-             ratio, p50/p99 latency, largest relative cost error).
+             ratio, p50/p99 latency, largest relative cost error);
+  tie_exact  the headline pair with tie-exact splits beside the default ones.
 
 Other workloads (--config): 1 = 500 x 400 FP64 latency; 3 = 200000 x 160000,
 d = 128, BF16 Gram cost on the matrix cores; 4 = 512 pairs in one batched
@@ -448,6 +449,34 @@ def long_pair_summary(args):
     return out
 
 
+def tie_exact_summary(args):
+    """The headline pair in tie-exact mode (FP64; the split read from labels of
+    a forward sweep over each whole block): its time beside the default
+    split's, and whether the two paths agree (the chroma-like frames are
+    continuous, so no exact tie separates them)."""
+    import torch
+
+    from paper_2008_02734_amd import dtw, synth
+
+    W = WORKLOADS[2]
+    M, N, d = W["M"], W["N"], W["d"]
+    X, Y = synth.make_pair(2, 0, M, N, d, W["family"])
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    out = {"workload": W["name"] + ", tie-exact splits"}
+    paths = {}
+    for tie in (False, True):
+        al = dtw.Aligner(M, N, d, torch.float64, "fp64", W["m"], device="cuda:0", tie_exact=tie)
+        al.opts.profile = 2
+        ms, lat, stats = timed_steps(lambda: al.run(Xd, Yd, stats=True), 5, 1)
+        key = "tie_exact" if tie else "default"
+        out[key] = {"ms": ms, "gcups": M * N / (ms * 1e-3) / 1e9, "sweep_ms": float(np.mean([q["ms_sweep"] for q in stats])),
+                    "sweep_cells": int(stats[-1]["sweep_cells"]), "levels": int(stats[-1]["levels"])}
+        paths[key] = al.path[: int(al.plen.item())].cpu().numpy()
+    out["same_path"] = bool(paths["default"].tolist() == paths["tie_exact"].tolist())
+    out["slowdown"] = out["tie_exact"]["ms"] / out["default"]["ms"]
+    return out
+
+
 def cpu_record(cells, cpu_s, sample, whole):
     """The cpu_baseline object: the oracle's rate on `sample`.  `whole` says
     whether the sample is the entire workload; if not, the rate is the
@@ -518,6 +547,7 @@ def main():
             out["long_pair"] = long_pair_summary(args)
             out["serving"], _ = serving_summary(args, args.requests, args.serving_m_hi,
                                                 [("bf16_mix", "bf16"), ("fp16_mix", "fp16")])
+            out["tie_exact"] = tie_exact_summary(args)
     elif args.config == 4:
         out = bench_batched(args)
     elif args.config == 5:

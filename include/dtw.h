@@ -101,7 +101,17 @@ typedef struct dtw_opts {
                               error 9, and every other wait of the call ends at once       */
   int32_t cost;            /* dtw_cost, default DTW_COST_EUCLIDEAN; every precision
                               takes either                                               */
-  int32_t reserved[2];     /* must be zero                                                */
+  int32_t tie_exact;       /* 1: tie-exact splits (DTW_PREC_FP64 only, else
+                              DTW_ERR_UNSUPPORTED; not in the paper, whose split ties are
+                              broken arbitrarily, Sec. 3.2).  Each split is read from labels
+                              that a forward sweep over the whole block carries, and each
+                              block's table starts from its origin's value in the whole
+                              table, so the path equals the textbook backtrace (Sec. 2.1,
+                              ties DIAG, UP, LEFT) on every input, exact ties included; the
+                              sweep of a split covers the whole block in one chain of
+                              stripes instead of two half chains.  0: the split of
+                              Algorithm 2 (default)                                       */
+  int32_t reserved[1];     /* must be zero                                                */
 } dtw_opts;
 
 typedef struct dtw_stats {

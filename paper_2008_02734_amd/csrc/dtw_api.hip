@@ -112,7 +112,7 @@ struct Layout {
   int cbytes = 8;  // bytes of the compute type
   int D = 0;       // padded frame stride of the compute copies
   Region ctl, pairs, subs0, subs1, piv_key, piv_pos, smin, passes, tickets, hist, chunk_sub, bandF, bandC,
-      bandB, ring, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, leaf_tk, leaf_ring, leaf_done, xconv,
+      bandB, ring, lring, leaves, leaf_scratch, tpath, cnt, poff, lidx, leaf_cost, leaf_tk, leaf_ring, leaf_done, xconv,
       yconv, xnorm, ynorm, nonfinite;
   size_t total = 0;
 };
@@ -133,7 +133,7 @@ int frame_width(int d, int precision) {
 
 // Xrows / Yrows: frames of X / Y that the compute copies must cover.
 Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vector<int64_t>& Ns, int d,
-                   int in_dtype, int precision, int m, int64_t Xrows, int64_t Yrows, int cost) {
+                   int in_dtype, int precision, int m, int64_t Xrows, int64_t Yrows, int cost, int tie) {
   Layout L;
   L.n_pairs = n_pairs;
   int64_t K0sum = 0, Msum = 0, Nsum = 0, Mmax = 0, sub = 0, leaf = 0;
@@ -187,6 +187,7 @@ Layout plan_layout(int n_pairs, const std::vector<int64_t>& Ms, const std::vecto
   put(L, L.bandC, 8 * c.band);
   put(L, L.bandB, 8 * c.band);
   put(L, L.ring, (size_t)L.cbytes * 2 * c.ring);  // cells of 2 (FP64) or 1 (FP32) 8-byte words
+  if (tie) put(L, L.lring, 8 * (size_t)c.ring);     // tie-exact mode: a label word per cell
   put(L, L.leaves, sizeof(LeafDesc) * c.leaf);
   put(L, L.leaf_scratch, 4 * c.leaf_words);
   put(L, L.tpath, 8 * c.pslots);
@@ -215,9 +216,10 @@ T* at(void* base, const Region& r) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + r.off);
 }
 
-Work make_work(const Layout& L, void* ws, int d, int m, int precision, int cost) {
+Work make_work(const Layout& L, void* ws, int d, int m, int precision, int cost, int tie) {
   Work w{};
   w.cost = cost;
+  w.tie = tie;
   w.ctl = at<Ctl>(ws, L.ctl);
   w.pairs = at<PairDesc>(ws, L.pairs);
   w.n_pairs = L.n_pairs;
@@ -237,6 +239,7 @@ Work make_work(const Layout& L, void* ws, int d, int m, int precision, int cost)
   w.bandC = at<double>(ws, L.bandC);
   w.bandB = at<double>(ws, L.bandB);
   w.ring = at<uint64_t>(ws, L.ring);
+  w.lring = tie ? at<uint64_t>(ws, L.lring) : nullptr;
   w.ring_words = L.cbytes / 4;
   w.leaves = at<LeafDesc>(ws, L.leaves);
   w.leaf_scratch = at<uint32_t>(ws, L.leaf_scratch);
@@ -269,7 +272,9 @@ dtw_status read_opts(const dtw_opts* o, dtw_opts* out) {
   if (out->min_block < 3 || out->min_block > kMaxMinBlock) return DTW_ERR_INVALID_ARG;
   if (out->wait_limit_us < 0) return DTW_ERR_INVALID_ARG;
   if (out->cost != DTW_COST_EUCLIDEAN && out->cost != DTW_COST_COSINE) return DTW_ERR_INVALID_ARG;
-  for (int i = 0; i < 2; ++i)
+  if (out->tie_exact != 0 && out->tie_exact != 1) return DTW_ERR_INVALID_ARG;
+  if (out->tie_exact && out->precision != DTW_PREC_FP64) return DTW_ERR_UNSUPPORTED;
+  for (int i = 0; i < 1; ++i)
     if (out->reserved[i] != 0) return DTW_ERR_INVALID_ARG;
   return DTW_OK;
 }
@@ -410,7 +415,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
     Ntot = std::max(Ntot, yo[b + 1]);
   }
   const int m = opts.min_block;
-  Layout L = plan_layout(n_pairs, Ms, Ns, d, in_dtype, opts.precision, m, Mtot, Ntot, opts.cost);
+  Layout L = plan_layout(n_pairs, Ms, Ns, d, in_dtype, opts.precision, m, Mtot, Ntot, opts.cost, opts.tie_exact);
   if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
   const bool f32 = opts.precision != DTW_PREC_FP64;  // FP32 recurrence (FP32 and Gram forms)
   const int in_f64 = in_dtype == DTW_F64;
@@ -433,7 +438,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
 
   Profiler prof;
   HIP_TRY(prof.init(opts.profile != 0 && stats != nullptr, opts.profile == 2, st));
-  Work w = make_work(L, ws, d, m, opts.precision, opts.cost);
+  Work w = make_work(L, ws, d, m, opts.precision, opts.cost, opts.tie_exact);
   if (device_error_word) *device_error_word = &w.ctl->error;
   w.X = X;
   w.Y = Y;
@@ -451,7 +456,7 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
     PROF_TRY(prof, kProfPlan, launch_plan(w, lvl, final_level, lds_leaf_bytes, st));
     if (final_level) break;
     PROF_TRY(prof, kProfSweep, launch_pass(w, lvl, pass_grid, st));
-    PROF_TRY(prof, kProfSplit, launch_combine(w, comb_grid, st));
+    if (!opts.tie_exact) PROF_TRY(prof, kProfSplit, launch_combine(w, comb_grid, st));  // tie-exact: the sweep names the split
   }
   PROF_TRY(prof, kProfLeaf, launch_leaf(w, I.cus, lds_leaf_bytes, X, Y, in_f64, st));
   PROF_TRY(prof, kProfOther,
@@ -617,7 +622,7 @@ dtw_status dtw_workspace_size(int64_t M, int64_t N, int32_t d, int32_t in_dtype,
   if (in_dtype != DTW_F64 && in_dtype != DTW_F32) return DTW_ERR_INVALID_ARG;
   if (frame_width(d, opts.precision) == 0) return DTW_ERR_UNSUPPORTED;
   std::vector<int64_t> Ms{M}, Ns{N};
-  *bytes = plan_layout(1, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, M, N, opts.cost).total;
+  *bytes = plan_layout(1, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, M, N, opts.cost, opts.tie_exact).total;
   return DTW_OK;
 }
 
@@ -676,7 +681,7 @@ dtw_status dtw_workspace_size_batched(int32_t B, const int64_t* x_offsets, const
     Xrows = std::max(Xrows, x_offsets[b + 1]);
     Yrows = std::max(Yrows, y_offsets[b + 1]);
   }
-  *bytes = plan_layout(B, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, Xrows, Yrows, opts.cost).total;
+  *bytes = plan_layout(B, Ms, Ns, d, in_dtype, opts.precision, opts.min_block, Xrows, Yrows, opts.cost, opts.tie_exact).total;
   return DTW_OK;
 }
 
@@ -703,15 +708,15 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype, i
   const int in_f64 = in_dtype == DTW_F64;
   std::vector<int64_t> Ms{Mb}, Ns{Nb};
   // same layout as dtw_workspace_size(i1+1, j1+1, d, in_dtype, opts with this precision)
-  Layout L = plan_layout(1, Ms, Ns, d, in_dtype, precision, 500, i1 + 1, j1 + 1, DTW_COST_EUCLIDEAN);
+  Layout L = plan_layout(1, Ms, Ns, d, in_dtype, precision, 500, i1 + 1, j1 + 1, DTW_COST_EUCLIDEAN, 0);
   {
     std::vector<int64_t> Mf{i1 + 1}, Nf{j1 + 1};
-    Layout Lf = plan_layout(1, Mf, Nf, d, in_dtype, precision, 500, i1 + 1, j1 + 1, DTW_COST_EUCLIDEAN);
+    Layout Lf = plan_layout(1, Mf, Nf, d, in_dtype, precision, 500, i1 + 1, j1 + 1, DTW_COST_EUCLIDEAN, 0);
     if (Lf.total > L.total) L = Lf;
   }
   if (ws_bytes < L.total) return DTW_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  Work w = make_work(L, workspace, d, 500, precision, DTW_COST_EUCLIDEAN);
+  Work w = make_work(L, workspace, d, 500, precision, DTW_COST_EUCLIDEAN, 0);
   HIP_TRY(stage_inputs(L, workspace, X, Y, in_f64, i1 + 1, j1 + 1, d, precision, DTW_COST_EUCLIDEAN, w, st));
   w.bandC = nullptr;
   DevInfo& I = dev_info();

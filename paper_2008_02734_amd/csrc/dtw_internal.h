@@ -54,6 +54,7 @@ struct Block {
   int32_t i0, j0, i1, j1;  // inclusive, global frame indices
   int32_t pair;
   int32_t pad;
+  double f0;  // tie-exact mode: accumulated cost of the block's origin in the whole table (NaN: its own cost)
 };
 
 struct PairDesc {
@@ -74,7 +75,8 @@ struct PassDesc {
   int32_t n_stripes;  // ceil(n_rows / 64)
   int32_t L;          // band stride: min(Mb, Nb) >= longest band diagonal
   int32_t raw;        // 1: band written in the sweep's own coordinates (dtw_diag)
-  int32_t pad;
+  int32_t tie;        // 1: tie-exact forward sweep of the whole block with labels
+  double f0;          // tie-exact: value of the origin cell (NaN: its own cost)
   int64_t band_off;   // element offset of the block's 3*L band slots
   int64_t ring_off;   // cell offset of the kRing boundary rows (kRing*Nb cells)
 };
@@ -87,6 +89,7 @@ struct LeafDesc {
   int32_t stripe_off;      // first leaf-stripe ticket of the leaf
   int32_t n_stripes;       // ceil(R / 64) stripes of the shorter side
   int64_t ring_off;        // first cell of its min(n_stripes - 1, kRing) boundary rows in the leaf ring
+  double f0;               // tie-exact mode: value of the leaf's origin cell (NaN: its own cost)
 };
 
 // Device control block.
@@ -151,6 +154,7 @@ struct Work {
   int32_t d;
   int32_t precision;
   int32_t cost;         // DTW_COST_EUCLIDEAN or DTW_COST_COSINE
+  int32_t tie;          // 1: tie-exact splits (FP64)
   const void* X;        // compute-type copies (or the caller's arrays); bf16 in the Gram form
   const void* Y;
   const float* Xn;      // Gram form: squared norms of the bf16 frames, FP32
@@ -168,6 +172,7 @@ struct Work {
   double* bandC;        // frame cost on the band
   double* bandB;        // backward accumulated cost on the band
   uint64_t* ring;       // boundary-row cells of the sweeps (words of value half + writer id)
+  uint64_t* lring;      // tie-exact mode: the labels of those cells (label + writer id), one word each
   int32_t ring_words;   // words per ring cell: 2 for FP64 values, 1 for FP32
   LeafDesc* leaves;
   uint32_t* leaf_scratch;

@@ -44,6 +44,8 @@ __global__ void init_kernel(Work w) {
   }
   // boundary-row cells: writer id 0, which no stripe has
   for (int64_t u = tid; u < w.caps.ring * w.ring_words; u += nt) w.ring[u] = 0ull;
+  if (w.lring)
+    for (int64_t u = tid; u < w.caps.ring; u += nt) w.lring[u] = 0ull;
   for (int64_t u = tid; u < w.caps.pslots; u += nt) w.cnt[u] = 0;
   for (int64_t u = tid; u < w.caps.leaf_ring * w.ring_words; u += nt) w.leaf_ring[u] = 0ull;
   for (int64_t u = tid; u < w.caps.leaf; u += nt) w.leaf_done[u] = 0;
@@ -84,14 +86,14 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
   for (int64_t tile = 0; tile < n_cand; tile += nt) {
     const int64_t ci = tile + tid;
     const bool valid = ci < n_cand;
-    Block c = {0, 0, 0, 0, 0, 0};
+    Block c = {0, 0, 0, 0, 0, 0, __builtin_nan("")};
     bool is_leaf = false;
     int64_t words = 0, nst = 0, lcells = 0;
     if (valid) {
       if (level == 0) {
         const PairDesc pd = w.pairs[ci];
         c = Block{(int32_t)pd.x_off, (int32_t)pd.y_off, (int32_t)(pd.x_off + pd.M - 1),
-                  (int32_t)(pd.y_off + pd.N - 1), (int32_t)ci, 0};
+                  (int32_t)(pd.y_off + pd.N - 1), (int32_t)ci, 0, __builtin_nan("")};
       } else {
         const int s = (int)(ci >> 1);
         const Block pb = prev[s];
@@ -108,14 +110,24 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
         }
         const int k = kf - 2 + q;
         int pi = pb.i0 + ar, pj = pb.j0 + (k - ar);
+        bool piv_ok = pos != ~0ull;
         if (q < 0 || q > 2 || pi < pb.i0 || pi > pb.i1 || pj < pb.j0 || pj > pb.j1) {
           // a pivot outside its block would make an empty child
           set_error(ctl, kErrBadPivot);
           pi = pb.i0 + (Mb - 1) / 2;
           pj = pb.j0 + (Nb - 1) / 2;
+          piv_ok = false;
         }
-        c = ((ci & 1) == 0) ? Block{pb.i0, pb.j0, pi, pj, pb.pair, 0}
-                            : Block{pi, pj, pb.i1, pb.j1, pb.pair, 0};
+        // tie-exact mode: the right child starts from the pivot's value,
+        // which the parent's forward sweep left in its band (row q)
+        double f_piv = __builtin_nan("");
+        if (w.tie && (ci & 1) == 1 && piv_ok) {
+          const PassDesc& PP = w.passes[2 * s];
+          const int lo = max(0, k - (Nb - 1));
+          f_piv = w.bandF[PP.band_off + (int64_t)q * PP.L + ((pi - pb.i0) - lo)];
+        }
+        c = ((ci & 1) == 0) ? Block{pb.i0, pb.j0, pi, pj, pb.pair, 0, pb.f0}
+                            : Block{pi, pj, pb.i1, pb.j1, pb.pair, 0, f_piv};
       }
       const int64_t Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
       is_leaf = (Mb < m) || (Nb < m);
@@ -157,6 +169,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
         L.stripe_off = (int32_t)so;
         L.n_stripes = (int32_t)nst;
         L.ring_off = ro;
+        L.f0 = c.f0;
         w.leaves[li] = L;
         // the leaf's tickets: its stripes top to bottom, consecutive, so a
         // stripe only waits on stripes of lower tickets
@@ -188,7 +201,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
     const int64_t s = tile + tid;
     const bool valid = s < n_sub_run;
     int64_t nchunk = 0, ring_e = 0;
-    Block c = {0, 0, 0, 0, 0, 0};
+    Block c = {0, 0, 0, 0, 0, 0, __builtin_nan("")};
     if (valid) {
       c = cur[s];
       const int64_t Mb = c.i1 - c.i0 + 1, Nb = c.j1 - c.j0 + 1;
@@ -206,6 +219,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       const int kb = kf + ((K % 2) == 0 ? 1 : 0);
       PassDesc P;
       P.raw = 0;
+      P.tie = w.tie;
+      P.f0 = c.f0;
       P.i0 = c.i0; P.j0 = c.j0; P.i1 = c.i1; P.j1 = c.j1;
       P.Mb = Mb; P.Nb = Nb;
       P.kf = kf;
@@ -219,9 +234,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       for (int dir = 0; dir < 2; ++dir) {
         P.dir = dir;
         P.ring_off = ring0 + dir * (int64_t)kRing * Nb;
-        P.kstop = dir ? kb : kf;
+        // tie-exact mode: one forward sweep over the whole block, no backward sweep
+        P.kstop = w.tie ? (dir ? 0 : K - 1) : (dir ? kb : kf);
         P.n_rows = min(Mb - 1, P.kstop) + 1;
-        P.n_stripes = ok ? (P.n_rows + kWave - 1) / kWave : 0;
+        P.n_stripes = (ok && !(w.tie && dir)) ? (P.n_rows + kWave - 1) / kWave : 0;
         w.passes[2 * s + dir] = P;
         atomicMax(&s_max_stripes, P.n_stripes);
       }
@@ -230,7 +246,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
       w.piv_key[s] = ~0ull;
       w.piv_pos[s] = ~0ull;
       atomicAdd((unsigned long long*)&ctl->cells,
-                (unsigned long long)(cells_upto(Mb, Nb, kf) + cells_upto(Mb, Nb, kb)));
+                (unsigned long long)(w.tie ? cells_upto(Mb, Nb, K - 1) : cells_upto(Mb, Nb, kf) + cells_upto(Mb, Nb, kb)));
     }
     chunk_base += tc;
     ring_base += tr;
@@ -631,6 +647,8 @@ __global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, in
   P.kstop = kstop;
   P.kf = kstop;
   P.raw = 1;
+  P.tie = 0;
+  P.f0 = __builtin_nan("");
   P.n_rows = min(P.Mb - 1, kstop) + 1;
   P.n_stripes = (P.n_rows + kWave - 1) / kWave;
   P.L = P.Mb;

@@ -63,7 +63,8 @@ size_t elem_bytes(int32_t in_dtype) { return in_dtype == DTW_F64 ? 8 : 4; }
 
 bool same_class(const dtw_request& a, const dtw_request& b) {
   return a.d == b.d && a.in_dtype == b.in_dtype && a.opts.precision == b.opts.precision &&
-         a.opts.min_block == b.opts.min_block && a.opts.cost == b.opts.cost;
+         a.opts.min_block == b.opts.min_block && a.opts.cost == b.opts.cost &&
+         a.opts.tie_exact == b.opts.tie_exact;
 }
 
 // Footprint of a batch made of `reqs`; fills the plan's offsets.  Returns

@@ -295,6 +295,115 @@ __device__ __forceinline__ void publish(int t, int lane, const T* cring, uint64_
   }
 }
 
+// ----------------------------------------------------------------- tie-exact sweep
+//
+// Tie-exact mode (FP64; not in the paper, whose split ties are broken
+// arbitrarily): one forward sweep over the whole block, from its origin's
+// value in the whole problem's table (PassDesc.f0), with a label per cell: on
+// local diagonals kf-1 and kf the cell itself (2a + [on kf]), past them the
+// label of the predecessor the DIAG > UP > LEFT backpointer names.  The
+// block's last cell writes its label as the split (piv_pos, in the band-row
+// form q = 1 + [on kf], row a) and its value (piv_key); diagonals kf-1 and
+// kf go to the band, where the planner reads the pivot's value.  Labels
+// travel between stripes through a second ring, `lring`, one word per cell
+// (the label and the writer's id), published beside the values.
+
+__device__ __forceinline__ int wave_shr1_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, kDppWaveShr1, 0xf, 0xf, false);
+}
+
+// Lane 63's labels of the steps g0..t, as publish<T> does for its values:
+// lane 16 + i stores the label of step g0 + i from labh.
+__device__ __forceinline__ void publish_labels(int t, int lane, const int* labh, uint64_t* lring_out, uint32_t tag,
+                                               int pub_max) {
+  const int i = lane - kPubGroup;
+  const int st = (t & ~(kPubGroup - 1)) + i;
+  const int col = st - (kWave - 1);
+  if (i >= 0 && i < kPubGroup && st <= t && col >= 0 && col <= pub_max)
+    __hip_atomic_store(lring_out + col, ((uint64_t)tag << 32) | (uint32_t)labh[st & (kCostRing - 1)],
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll a value word and (want_b) a label word together until both carry
+// `tag`; bounded like poll_word.
+__device__ __forceinline__ void poll_pair(const uint64_t* pa, const uint64_t* pb, bool want_b, uint32_t tag,
+                                          const Work& w, uint64_t& va, uint64_t& vb) {
+  va = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  vb = want_b ? __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ((uint64_t)tag << 32);
+  if ((uint32_t)(va >> 32) == tag && (uint32_t)(vb >> 32) == tag) return;
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t it = 0;; ++it) {
+    __builtin_amdgcn_s_sleep(1);
+    const int32_t err = __hip_atomic_load(&w.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    va = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (want_b) vb = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (((uint32_t)(va >> 32) == tag && (uint32_t)(vb >> 32) == tag) || err != 0) return;
+    if (wall_clock64() - t0 > w.spin_ticks || it > kSpinIterCap) {
+      set_error(w.ctl, kErrSpinTimeout);
+      return;
+    }
+  }
+}
+
+// The recurrence wave of a tie-exact stripe: one step at a time, the value
+// unpredicated as in the fast path (cells before a lane's row hold +inf or
+// NaN, which v_min passes over) and the label chosen by equality with the
+// minimum (a NaN or +inf operand never equals the finite minimum of a cell).
+template <typename T>
+__device__ void tie_recurrence(const PassDesc& P, const Work& w, int p, int s, int a0, int Lr, int n_steps,
+                               int n_phases, bool has_succ, int pub_max, T* cring, const T* bring, const int* blab,
+                               int* labh, uint64_t* ring_out, uint64_t* lring_out, uint32_t tag_out, int lane) {
+  const T INF = inf_t<T>();
+  const int a = a0 + lane;
+  const int bmax = (lane <= Lr) ? min(P.Nb - 1, P.kstop - a) : -1;
+  const int kf = P.kf;
+  T f = INF;                                        // own F(a, b-1)
+  T up_prev = (s == 0 && lane == 0) ? T(0) : INF;   // F(a-1, b-1): 0 before the origin
+  int lab = 0, lab_up_prev = 0;
+  lds_barrier();  // phase -1: first costs and boundary chunk
+  // the origin holds its value in the whole table: the cost slot of lane 0,
+  // step 0 takes it, so that F(origin) = 0 + f0 exactly
+  if (s == 0 && lane == 0 && P.f0 == P.f0) cring[0] = (T)P.f0;
+  for (int k = 0; k < n_phases; ++k) {
+    const int t0 = k * kPhase;
+    const int t1 = min(t0 + kPhase, n_steps);
+    for (int t = t0; t < t1; ++t) {
+      T* const hp = cring + (t & (kCostRing - 1)) * kWave + lane;
+      const T c = *hp;
+      const T up = wave_shr1(bring[t & (2 * kPhase - 1)], f);
+      const int lu = wave_shr1_i(blab[t & (2 * kPhase - 1)], lab);
+      const T m = min_t(min_t(up_prev, f), up);
+      lab = (up_prev == m) ? lab_up_prev : ((up == m) ? lu : lab);  // DIAG, then UP, then LEFT
+      f = m + c;
+      up_prev = up;
+      lab_up_prev = lu;
+      const int b = t - lane;
+      const int kd = a0 + t;  // local diagonal of every lane's cell at this step
+      if (kd == kf - 1 || kd == kf) {
+        lab = 2 * a + (kd == kf ? 1 : 0);
+        if (b >= 0 && b <= bmax) {
+          const int lo = max(0, kd - (P.Nb - 1));
+          w.bandF[P.band_off + (int64_t)(kd - (kf - 2)) * P.L + (a - lo)] = (double)f;
+        }
+      }
+      if (a == P.Mb - 1 && b == P.Nb - 1) {  // the block's last cell
+        w.piv_pos[p >> 1] = ((uint64_t)(1 + (lab & 1)) << 32) | (uint32_t)(lab >> 1);
+        w.piv_key[p >> 1] = (uint64_t)__double_as_longlong((double)f);
+      }
+      *hp = f;  // the history: this step's value in the slot whose cost was just read
+      if (lane == kWave - 1) labh[t & (kCostRing - 1)] = lab;
+      if ((t & (kPubGroup - 1)) == kPubGroup - 1 || t == n_steps - 1) {
+        __builtin_amdgcn_wave_barrier();  // lane 63's value and label read by the publishing lanes
+        if (has_succ) {
+          publish<T>(t, lane, cring, ring_out, tag_out, pub_max);
+          publish_labels(t, lane, labh, lring_out, tag_out, pub_max);
+        }
+      }
+    }
+    lds_barrier();
+  }
+}
+
 // Gram-form producer (dtw_gram.h), BF16 frames for kBf16, else FP16.  The
 // X operand is either held in registers (kXRegs: each lane's slices of its
 // row's frame) or staged in LDS at the start of a stripe by the NPW producer
@@ -418,12 +527,15 @@ constexpr bool kStageY = !is_gram(CM) && (D <= 32);
 template <typename T, int CM, int D>
 constexpr bool kPassStagesRows = (!is_gram(CM) && D >= 64) || kStageY<T, CM, D>;
 
-template <typename T, int D, int CM>
+template <typename T, int D, int CM, bool kTie = false>
 __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
   __shared__ T bring[2 * kPhase];         // bottom row of the stripe above, [column & 63]
   __shared__ int sh_ticket;
+  constexpr bool kTieOk = kTie && sizeof(T) == 8 && !is_gram(CM);  // tie-exact mode: FP64 sweeps only
+  __shared__ int blab[kTieOk ? 2 * kPhase : 1];  // labels of the bottom row above (tie-exact mode)
+  __shared__ int labh[kTieOk ? kCostRing : 1];   // lane 63's labels by step (tie-exact mode)
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
   // the recurrence wave issues first on its SIMD: its dependency chain sets the pace
@@ -469,8 +581,20 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
     uint64_t* ring_out = ring + (int64_t)(s % kRing) * P.Nb * kCW;
     const uint64_t* ring_in = ring + (int64_t)((s + kRing - 1) % kRing) * P.Nb * kCW;
     const uint32_t tag_out = ring_tag(level, s), tag_in = ring_tag(level, s - 1);
+    constexpr bool tie = kTieOk;
+    if ((P.tie != 0) != kTieOk) {
+      if (threadIdx.x == 0) set_error(ctl, kErrBadPass);
+      continue;
+    }
 
-    if (wave == 0) {
+    if (wave == 0 && tie) {
+      if constexpr (kTieOk) {
+        stage_barrier<kPassStagesRows<T, CM, D>>();
+        uint64_t* lring = w.lring + P.ring_off;
+        tie_recurrence<T>(P, w, p, s, a0, Lr, n_steps, n_phases, has_succ, pub_max, cring, bring, blab, labh,
+                          ring_out, lring + (int64_t)(s % kRing) * P.Nb, tag_out, lane);
+      }
+    } else if (wave == 0) {
       // ------------------------------------------------ recurrence
       //
       // Before a lane reaches its row (b < 0) its value is +inf (or a NaN
@@ -665,6 +789,30 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
     } else {
       // ------------------------------------------------ boundary input
       stage_barrier<kPassStagesRows<T, CM, D>>();
+      if (tie) {
+        // tie-exact mode: the value words as below, and lanes 0..kPhase-1 the
+        // label of column lane of the chunk, polled together
+        const uint64_t* lring_in = w.lring + P.ring_off + (int64_t)((s + kRing - 1) % kRing) * P.Nb;
+        for (int k = -1; k < n_phases; ++k) {
+          const int col = (k + 1) * kPhase + lane / kCW;
+          const int colL = (k + 1) * kPhase + lane;
+          if (lane < kPhase * kCW) {
+            uint32_t half = (kCW == 2) ? ((lane % 2) ? 0x7FF00000u : 0u) : 0x7F800000u;  // a half of +inf
+            int lb = 0;
+            if (has_pred && col <= need_max) {
+              uint64_t va, vb;
+              poll_pair(ring_in + (int64_t)col * kCW + lane % kCW, lring_in + colL,
+                        lane < kPhase && colL <= need_max, tag_in, w, va, vb);
+              half = (uint32_t)va;
+              lb = (int)(uint32_t)vb;
+            }
+            reinterpret_cast<uint32_t*>(bring)[(col & (2 * kPhase - 1)) * kCW + lane % kCW] = half;
+            if (lane < kPhase) blab[colL & (2 * kPhase - 1)] = lb;
+          }
+          lds_barrier();
+        }
+        continue;
+      }
       // lanes 0..kPhase*kW-1: word lane % kW of column lane / kW of the chunk
       for (int k = -1; k < n_phases; ++k) {
         const int col = (k + 1) * kPhase + lane / kCW;
@@ -705,6 +853,7 @@ __global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && si
 struct LeafShape {
   bool tr;
   int R, Cc, r0, c0, Wm;
+  double f0;  // tie-exact mode: value of the leaf's origin in the whole table (NaN: its own cost)
 };
 
 // Lane 48+u stores step g0+u's value of lane 63 (column g0+u-63 of the
@@ -749,6 +898,9 @@ __device__ __forceinline__ T leaf_recurrence(const LeafShape& S, int sw, int Lr,
   T up_prev = (sw == 0 && lane == 0) ? T(0) : INF;
   uint32_t word = 0;
   lds_barrier();  // phase -1
+  // tie-exact mode: the origin holds its value in the whole table (cost slot
+  // of lane 0, step 0), so that F(origin) = 0 + f0 exactly
+  if (sw == 0 && lane == 0 && S.f0 == S.f0) cring[0] = (T)S.f0;
   for (int k = 0; k < n_phases; ++k) {
     const int t0 = k * kPhase;
     T* const hp = cring + (t0 & (kCostRing - 1)) * kWave + lane;  // the phase's slots, also the history
@@ -1150,6 +1302,7 @@ __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
     S.r0 = S.tr ? Lf.j0 : Lf.i0;
     S.c0 = S.tr ? Lf.i0 : Lf.j0;
     S.Wm = (S.Cc + kWave - 1 + 15) / 16;
+    S.f0 = Lf.f0;
     // in the Gram form X and Y are the 16-bit frames, reached through w.X / w.Y
     const T* __restrict__ Xs = is_gram(CM) ? static_cast<const T*>(w.X) : X;
     const T* __restrict__ Ys = is_gram(CM) ? static_cast<const T*>(w.Y) : Y;
@@ -1328,6 +1481,16 @@ hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st) {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<float, D_, kCostEuclid>, grid, pass_threads(kCostEuclid), 0,
                                                              st, static_cast<const float*>(w.X),
                                                              static_cast<const float*>(w.Y), w, level))
+  } else if (w.tie && w.cost == DTW_COST_COSINE) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostCosine, true>, grid,
+                                                             pass_threads(kCostCosine), 0, st,
+                                                             static_cast<const double*>(w.X),
+                                                             static_cast<const double*>(w.Y), w, level))
+  } else if (w.tie) {
+    DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostEuclid, true>, grid,
+                                                             pass_threads(kCostEuclid), 0, st,
+                                                             static_cast<const double*>(w.X),
+                                                             static_cast<const double*>(w.Y), w, level))
   } else if (w.cost == DTW_COST_COSINE) {
     DTW_DISPATCH_DMAX(pick_dmax(w.d), return launch_checked(&pass_kernel<double, D_, kCostCosine>, grid, pass_threads(kCostCosine), 0,
                                                              st, static_cast<const double*>(w.X),

@@ -33,7 +33,8 @@ class DtwError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("min_block", ctypes.c_int32),
                 ("validate_finite", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("wait_limit_us", ctypes.c_int32), ("cost", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("wait_limit_us", ctypes.c_int32), ("cost", ctypes.c_int32), ("tie_exact", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -98,7 +99,7 @@ COST = {"euclidean": 0, "cosine": 1}
 
 
 def make_opts(precision="fp64", min_block=500, validate_finite=False, profile=False, wait_limit_us=0,
-              cost="euclidean"):
+              cost="euclidean", tie_exact=False):
     o = Opts()
     lib().dtw_default_opts(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -106,6 +107,7 @@ def make_opts(precision="fp64", min_block=500, validate_finite=False, profile=Fa
     o.validate_finite = 1 if validate_finite else 0
     o.profile = int(profile) if not isinstance(profile, bool) else (1 if profile else 0)
     o.wait_limit_us = int(wait_limit_us)
+    o.tie_exact = 1 if tie_exact else 0
     if isinstance(cost, str):
         o.cost = COST[cost]
     elif isinstance(cost, int):
@@ -156,8 +158,9 @@ def _dev(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def workspace_size(M, N, d, dtype=torch.float64, precision="fp64", min_block=500, cost="euclidean"):
-    o = make_opts(precision, min_block, cost=cost)
+def workspace_size(M, N, d, dtype=torch.float64, precision="fp64", min_block=500, cost="euclidean",
+                   tie_exact=False):
+    o = make_opts(precision, min_block, cost=cost, tie_exact=tie_exact)
     n = ctypes.c_size_t()
     code = DTW_F64 if dtype == torch.float64 else DTW_F32
     _check(lib().dtw_workspace_size(M, N, d, code, ctypes.byref(o), ctypes.byref(n)), "dtw_workspace_size")
@@ -168,10 +171,10 @@ class Aligner:
     """Reusable buffers for repeated alignments of one problem shape."""
 
     def __init__(self, M, N, d, dtype=torch.float64, precision="fp64", min_block=500, device="cuda",
-                 wait_limit_us=0, cost="euclidean"):
+                 wait_limit_us=0, cost="euclidean", tie_exact=False):
         self.M, self.N, self.d, self.dtype = M, N, d, dtype
-        self.opts = make_opts(precision, min_block, wait_limit_us=wait_limit_us, cost=cost)
-        self.ws_bytes = workspace_size(M, N, d, dtype, precision, min_block, cost)
+        self.opts = make_opts(precision, min_block, wait_limit_us=wait_limit_us, cost=cost, tie_exact=tie_exact)
+        self.ws_bytes = workspace_size(M, N, d, dtype, precision, min_block, cost, tie_exact)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.cost = torch.empty(1, dtype=torch.float64, device=device)
         self.cap = M + N - 1
@@ -200,7 +203,7 @@ class Aligner:
 
 
 def align(X, Y, precision="fp64", min_block=500, validate_finite=False, stream=None, wait_limit_us=0,
-          cost="euclidean"):
+          cost="euclidean", tie_exact=False):
     """Optimal warping path of X (M x d) and Y (N x d), device tensors.
 
     Returns (cost: float, path: int32 tensor [K, 2] on the device, stats: dict).
@@ -210,7 +213,8 @@ def align(X, Y, precision="fp64", min_block=500, validate_finite=False, stream=N
         raise ValueError("X and Y must be 2-D with equal dtype and feature dimension")
     M, d = X.shape
     N = Y.shape[0]
-    al = Aligner(M, N, d, X.dtype, precision, min_block, device=X.device, wait_limit_us=wait_limit_us, cost=cost)
+    al = Aligner(M, N, d, X.dtype, precision, min_block, device=X.device, wait_limit_us=wait_limit_us, cost=cost,
+                 tie_exact=tie_exact)
     al.opts.validate_finite = 1 if validate_finite else 0
     st = al.run(X, Y, stats=True, stream=stream)
     n = int(st["path_len"])
@@ -244,7 +248,7 @@ class BatchAligner:
     """Reusable packed inputs and buffers for repeated batched alignments of
     one fixed set of pairs (dtw_align_batched)."""
 
-    def __init__(self, Xs, Ys, precision="fp64", min_block=500, profile=False, cost="euclidean"):
+    def __init__(self, Xs, Ys, precision="fp64", min_block=500, profile=False, cost="euclidean", tie_exact=False):
         self.B = len(Xs)
         dev = Xs[0].device
         self.d = Xs[0].shape[1]
@@ -258,7 +262,7 @@ class BatchAligner:
         self.Yp = torch.cat(list(Ys)).contiguous()
         arr = lambda v: (ctypes.c_int64 * len(v))(*v)
         self.xo_a, self.yo_a, self.po_a = arr(xo), arr(yo), arr(po)
-        self.opts = make_opts(precision, min_block, profile=profile, cost=cost)
+        self.opts = make_opts(precision, min_block, profile=profile, cost=cost, tie_exact=tie_exact)
         n = ctypes.c_size_t()
         _check(lib().dtw_workspace_size_batched(self.B, self.xo_a, self.yo_a, self.d, _dtype_code(self.Xp),
                                                 ctypes.byref(self.opts), ctypes.byref(n)),
@@ -285,10 +289,10 @@ class BatchAligner:
         return [self.paths[self.po[b]:self.po[b] + lens_h[b]] for b in range(self.B)]
 
 
-def align_batched(Xs, Ys, precision="fp64", min_block=500, stream=None, cost="euclidean"):
+def align_batched(Xs, Ys, precision="fp64", min_block=500, stream=None, cost="euclidean", tie_exact=False):
     """Align B independent pairs in one call.  Returns (costs [B] float64 tensor,
     list of path tensors, stats dict)."""
-    ba = BatchAligner(Xs, Ys, precision, min_block, cost=cost)
+    ba = BatchAligner(Xs, Ys, precision, min_block, cost=cost, tie_exact=tie_exact)
     st = ba.run(stream)
     return ba.costs, ba.path_list(), st
 
@@ -374,7 +378,7 @@ class Server:
         self._h = h
         self._live = {}
 
-    def submit(self, X, Y, precision="fp64", min_block=500, cost="euclidean"):
+    def submit(self, X, Y, precision="fp64", min_block=500, cost="euclidean", tie_exact=False):
         if X.dtype != Y.dtype or X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
             raise ValueError("X and Y must be 2-D with equal dtype and feature dimension")
         torch.cuda.current_stream(X.device).synchronize()  # inputs written before the server's stream reads them
@@ -383,7 +387,8 @@ class Server:
         out_cost = torch.empty(1, dtype=torch.float64, device=X.device)
         path = torch.empty((M + N - 1, 2), dtype=torch.int32, device=X.device)
         plen = torch.empty(1, dtype=torch.int64, device=X.device)
-        r = Request(_dev(X).value, M, _dev(Y).value, N, d, _dtype_code(X), make_opts(precision, min_block, cost=cost),
+        r = Request(_dev(X).value, M, _dev(Y).value, N, d, _dtype_code(X), make_opts(precision, min_block, cost=cost,
+                                                                                 tie_exact=tie_exact),
                     out_cost.data_ptr(), path.data_ptr(), M + N - 1, plen.data_ptr())
         tk = ctypes.c_uint64()
         _check(_server_lib().dtw_server_submit(self._h, ctypes.byref(r), ctypes.byref(tk)), "dtw_server_submit")

@@ -67,7 +67,8 @@ int main(int argc, char** argv) {
   dtw_default_opts(&o);
   o.min_block = hdr[2];
   o.precision = hdr[3] & 0xff;
-  o.cost = hdr[3] >> 8;  // the frame cost rides in the precision word's second byte
+  o.cost = (hdr[3] >> 8) & 0xff;  // the frame cost rides in the precision word's second byte
+  o.tie_exact = hdr[3] >> 16;      // and the tie-exact flag in its third
   size_t ws = 0;
   int rc = (B == 1) ? dtw_workspace_size(xo[1], yo[1], d, DTW_F64, &o, &ws)
                     : dtw_workspace_size_batched(B, xo.data(), yo.data(), d, DTW_F64, &o, &ws);

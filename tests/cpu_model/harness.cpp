@@ -216,6 +216,7 @@ static void model_check_leaves(const Work& w) {
 
 template <typename T>
 static void model_pass(const Work& w) {
+  MODEL_CHECK(!w.tie);  // the tie-exact sweep runs only in the build of the real kernels
   Ctl* ctl = w.ctl;
   const int n_t = ctl->n_tickets, n_pass = ctl->n_pass;
   MODEL_CHECK(n_pass >= 0 && n_pass <= 2 * w.caps.sub);
@@ -410,6 +411,10 @@ hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostCosine), [&] { pass_kernel<float, D_, kCostCosine>((const float*)w.X, (const float*)w.Y, w, level); })))
   } else if (w.precision == DTW_PREC_FP32) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostEuclid), [&] { pass_kernel<float, D_, kCostEuclid>((const float*)w.X, (const float*)w.Y, w, level); })))
+  } else if (w.tie && w.cost == DTW_COST_COSINE) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostCosine), [&] { pass_kernel<double, D_, kCostCosine, true>((const double*)w.X, (const double*)w.Y, w, level); })))
+  } else if (w.tie) {
+    MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostEuclid), [&] { pass_kernel<double, D_, kCostEuclid, true>((const double*)w.X, (const double*)w.Y, w, level); })))
   } else if (w.cost == DTW_COST_COSINE) {
     MODEL_DISPATCH(pick_dmax(w.d), (cpu_launch(2, pass_threads(kCostCosine), [&] { pass_kernel<double, D_, kCostCosine>((const double*)w.X, (const double*)w.Y, w, level); })))
   } else {

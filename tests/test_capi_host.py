@@ -64,7 +64,15 @@ def test_argument_errors_before_any_device_work():
     assert _align(L, opts=bad) == -1
     bad = dtw.make_opts(cost=5)
     assert _align(L, opts=bad) == -1      # unknown frame cost
+    bad = dtw.make_opts()
+    bad.tie_exact = 2
+    assert _align(L, opts=bad) == -1      # tie_exact is 0 or 1
     n = ctypes.c_size_t()
+    for prec in ("fp32", "bf16", "fp16"):  # tie-exact splits: FP64 only
+        o = dtw.make_opts(precision=prec, tie_exact=True)
+        assert L.dtw_workspace_size(100, 80, 12, 0, ctypes.byref(o), ctypes.byref(n)) == -8
+    o = dtw.make_opts(tie_exact=True)
+    assert L.dtw_workspace_size(100, 80, 12, 0, ctypes.byref(o), ctypes.byref(n)) == 0 and n.value > 0
     for prec in ("fp64", "fp32", "bf16", "fp16"):  # every precision takes the cosine cost
         o = dtw.make_opts(precision=prec, cost="cosine")
         assert L.dtw_workspace_size(100, 80, 128, 0, ctypes.byref(o), ctypes.byref(n)) == 0 and n.value > 0

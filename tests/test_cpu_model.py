@@ -90,12 +90,12 @@ def wave_exe(tmp_path_factory):
     return _build_model(tmp_path_factory.mktemp("cpu_model_wave"), wave=True)
 
 
-def run_model(exe, pairs, m, precision=0, env=None, cost=0):
+def run_model(exe, pairs, m, precision=0, env=None, cost=0, tie=0):
     d = pairs[0][0].shape[1]
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
         with open(fin, "wb") as f:
-            f.write(struct.pack("4i", len(pairs), d, m, precision | (cost << 8)))
+            f.write(struct.pack("4i", len(pairs), d, m, precision | (cost << 8) | (tie << 16)))
             for X, Y in pairs:
                 f.write(struct.pack("2q", X.shape[0], Y.shape[0]))
             for X, _ in pairs:
@@ -369,3 +369,21 @@ def test_wave_model_leaf_on_several_workgroups(wave_exe, M, N, d, fam):
     c_ref, p_ref = oracle.full(X, Y)
     assert path.tolist() == p_ref.tolist()
     assert abs(cost - c_ref) <= 1e-12 * c_ref
+
+
+@pytest.mark.parametrize("M,N,d,fam,m", [(150, 120, 1, "int3", 16), (130, 200, 1, "int3", 8), (90, 75, 2, "int3", 3),
+                                         (200, 170, 3, "normal", 16), (140, 100, 1, "int3", 500),
+                                         (260, 90, 1, "int3", 32)])
+def test_wave_model_tie_exact(wave_exe, M, N, d, fam, m):
+    # tie-exact mode: the real kernels (labelled forward sweeps chained over
+    # several stripes, leaves from their origin's value) give the oracle's
+    # textbook path bit for bit, also on tie-heavy integer frames where the
+    # split of Algorithm 2 leaves it
+    X, Y = synth.random_pair(9400 + M + N, M, N, d, fam)
+    r = run_model(wave_exe, [(X, Y)], m, tie=1)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    cost, path = r["results"][0]
+    c_ref, p_ref = oracle.full(X, Y)
+    assert path.tolist() == p_ref.tolist()
+    assert abs(cost - c_ref) <= 1e-12 * max(c_ref, 1.0)
+    assert oracle.linmdtw_tie(X, Y, min_block=m)["path"].tolist() == p_ref.tolist()

@@ -1,0 +1,118 @@
+"""GPU parity of the tie-exact mode (FP64, not in the paper) against the
+oracle: the path equals the textbook backtrace (ties DIAG, UP, LEFT) bit for
+bit on every input, including tie-heavy integer frames where the split of
+Algorithm 2 leaves it, and the cost is the textbook optimum.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2008_02734_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dtw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_02734_amd import dtw as mod
+    mod.lib()
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", torch.float64)
+
+
+def run(dtw, X, Y, m, cost="euclidean"):
+    al = dtw.Aligner(X.shape[0], Y.shape[0], X.shape[1], torch.float64, "fp64", m, cost=cost, tie_exact=True)
+    st = al.run(dev(X), dev(Y), stats=True)
+    n = int(st["path_len"])
+    return float(al.cost.item()), al.path[:n].cpu().numpy(), st
+
+
+CASES = [  # (M, N, d, family, m): tie-heavy integer frames, and continuous ones
+    (600, 500, 1, "int3", 500),    # one leaf of several stripes, walked from its origin
+    (2000, 1700, 1, "int3", 500),  # splits: chained labelled sweeps, children from the pivot's value
+    (1500, 2100, 2, "int3", 64),   # N > M, many levels
+    (3000, 2400, 1, "int3", 128),
+    (2500, 2000, 12, "normal", 500),
+    (700, 650, 1, "int3", 3),      # the smallest cutoff
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_tie_exact_equals_textbook(dtw, case):
+    M, N, d, fam, m = CASES[case]
+    X, Y = synth.random_pair(9500 + case, M, N, d, fam)
+    c, p, st = run(dtw, X, Y, m)
+    assert st["device_error"] == 0
+    c_ref, p_ref = oracle.full(X, Y)
+    assert p.tolist() == p_ref.tolist()
+    assert abs(c - c_ref) <= 1e-12 * max(c_ref, 1.0)
+    if st["levels"] > 0:
+        assert abs(st["s_min"] - c_ref) <= 1e-12 * max(c_ref, 1.0)
+    if fam == "int3":
+        # the inputs do exercise ties: the default split leaves the textbook path
+        cd, pd, _ = dtw.align(dev(X), dev(Y), min_block=m)
+        assert cd == pytest.approx(c_ref, rel=1e-12)
+
+
+def test_tie_exact_default_split_differs_on_ties(dtw):
+    # a tie-heavy pair on which the oracle's port of Algorithm 2 leaves the
+    # textbook path (seed chosen so by the oracle alone): the default mode
+    # gives that port's path (optimal, not the textbook one), tie-exact mode
+    # the textbook one
+    X, Y = synth.random_pair(9602, 2000, 1700, 1, "int3")
+    c_ref, p_ref = oracle.full(X, Y)
+    lin = oracle.linmdtw(X, Y, min_block=500)
+    assert lin["path"].tolist() != p_ref.tolist()
+    c_def, p_def, _ = dtw.align(dev(X), dev(Y), min_block=500)
+    _, p_tie, _ = run(dtw, X, Y, 500)
+    assert p_def.cpu().numpy().tolist() == lin["path"].tolist()
+    assert c_def == c_ref
+    assert p_tie.tolist() == p_ref.tolist()
+
+
+def test_tie_exact_all_zero_costs(dtw):
+    # every frame cost 0: every warping path is optimal, and the textbook
+    # backtrace is the diagonal-first one
+    X, Y = np.zeros((900, 3)), np.zeros((700, 3))
+    c, p, st = run(dtw, X, Y, 64)
+    c_ref, p_ref = oracle.full(X, Y)
+    assert st["device_error"] == 0 and c == 0.0
+    assert p.tolist() == p_ref.tolist()
+
+
+def test_tie_exact_cosine(dtw):
+    # the cosine cost on d = 5 rectified chroma frames, which has exact ties
+    X, Y = synth.make_pair(11, 3, 1400, 1100, 5, "chroma")
+    c, p, st = run(dtw, X, Y, 64, cost="cosine")
+    c_ref, p_ref = oracle.full(X, Y, cost="cosine")
+    assert st["device_error"] == 0
+    assert p.tolist() == p_ref.tolist()
+    assert abs(c - c_ref) <= 1e-12 * max(c_ref, 1.0)
+
+
+def test_tie_exact_batched_equals_single(dtw):
+    pairs = [synth.random_pair(9700 + b, 300 + 97 * b, 260 + 61 * b, 1, "int3") for b in range(5)]
+    costs, paths, st = dtw.align_batched([dev(X) for X, _ in pairs], [dev(Y) for _, Y in pairs], min_block=64,
+                                         tie_exact=True)
+    for b, (X, Y) in enumerate(pairs):
+        c_ref, p_ref = oracle.full(X, Y)
+        assert paths[b].cpu().numpy().tolist() == p_ref.tolist()
+        assert abs(float(costs[b]) - c_ref) <= 1e-12 * max(c_ref, 1.0)
+
+
+def test_tie_exact_full_size_pair(dtw):
+    # the 20000 x 16000, d = 12 chroma-like pair: continuous frames have no
+    # exact tie that separates the modes, so both give the same path; the
+    # tie-exact path is a valid warping path of the oracle's FP64 cost
+    X, Y = synth.make_pair(2, 0, 20000, 16000, 12, "chroma")
+    c, p, st = run(dtw, X, Y, 500)
+    cd, pd, _ = dtw.align(dev(X), dev(Y), min_block=500)
+    assert st["device_error"] == 0
+    assert p.tolist() == pd.cpu().numpy().tolist()
+    assert oracle.path_cost(X, Y, p) == pytest.approx(c, rel=1e-12)
