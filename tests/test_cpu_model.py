@@ -203,7 +203,7 @@ def test_wave_model_single_stripe_case_has_no_wait(wave_exe):
     assert r["rc"] == 0 and r["device_error"] == 0, r
     assert r["polls"] == 0
     assert r["results"][0][1].tolist() == oracle.full(X, Y)[1].tolist()
-    X2, Y2 = synth.random_pair(8001, 130, 90, 5, "normal")
+    X2, Y2 = synth.random_pair(8001, 70, 50, 5, "normal")
     r2 = run_model(wave_exe, [(X2, Y2)], 3)
     assert r2["rc"] == 0 and r2["polls"] > 0
 
@@ -314,8 +314,7 @@ def test_wave_model_diag_bitwise(wave_exe, M, N, d, block, rev, ks):
     assert np.array_equal(out[ok].view(np.int64), ref[ok].view(np.int64))
 
 
-@pytest.mark.parametrize("M,N,d,m,prec", [(130, 90, 12, 16, 0), (90, 110, 5, 8, 0), (80, 70, 64, 16, 0),
-                                          (100, 80, 12, 16, 1)])
+@pytest.mark.parametrize("M,N,d,m,prec", [(90, 110, 5, 8, 0), (100, 80, 12, 16, 1)])
 def test_wave_model_cosine(model_exe, wave_exe, M, N, d, m, prec):
     # the cosine frame cost (Sec. 4.1): the real kernels lane by lane give the
     # oracle's textbook path under the cosine cost in FP64, and the FP32 form
@@ -334,7 +333,7 @@ def test_wave_model_cosine(model_exe, wave_exe, M, N, d, m, prec):
             assert (cost - c_ref) / c_ref <= 1e-5 and cost >= c_ref * (1 - 1e-12)
 
 
-@pytest.mark.parametrize("M,N,d,m,prec", [(90, 70, 64, 16, 2), (80, 75, 128, 16, 3), (100, 60, 40, 500, 3)])
+@pytest.mark.parametrize("M,N,d,m,prec", [(90, 70, 64, 16, 2), (80, 75, 128, 16, 3)])
 def test_wave_model_gram_cosine(model_exe, wave_exe, M, N, d, m, prec):
     # the cosine cost on the matrix-core tile: frames normalised in FP64 at
     # staging, rounded to bf16/fp16, cost max(0, 1 - dot).  The real kernels
@@ -353,8 +352,7 @@ def test_wave_model_gram_cosine(model_exe, wave_exe, M, N, d, m, prec):
     assert -1e-12 <= (cost - c_ref) / c_ref <= (BF16_REL_TOL if prec == 2 else 1e-5)
 
 
-@pytest.mark.parametrize("M,N,d,fam", [(200, 230, 4, "normal"), (230, 200, 1, "int3"), (100, 3200, 2, "normal"),
-                                       (3100, 90, 1, "int3")])
+@pytest.mark.parametrize("M,N,d,fam", [(200, 230, 4, "normal"), (3100, 90, 1, "int3")])
 def test_wave_model_leaf_on_several_workgroups(wave_exe, M, N, d, fam):
     # one leaf (m = 500) whose stripes run on the model's two workgroups,
     # chained through the leaf ring: four stripes (ring rows reused, walk
@@ -371,9 +369,7 @@ def test_wave_model_leaf_on_several_workgroups(wave_exe, M, N, d, fam):
     assert abs(cost - c_ref) <= 1e-12 * c_ref
 
 
-@pytest.mark.parametrize("M,N,d,fam,m", [(150, 120, 1, "int3", 16), (130, 200, 1, "int3", 8), (90, 75, 2, "int3", 3),
-                                         (200, 170, 3, "normal", 16), (140, 100, 1, "int3", 500),
-                                         (260, 90, 1, "int3", 32)])
+@pytest.mark.parametrize("M,N,d,fam,m", [(150, 120, 1, "int3", 16), (70, 60, 2, "int3", 3), (260, 90, 1, "int3", 32)])
 def test_wave_model_tie_exact(wave_exe, M, N, d, fam, m):
     # tie-exact mode: the real kernels (labelled forward sweeps chained over
     # several stripes, leaves from their origin's value) give the oracle's
