@@ -203,7 +203,7 @@ def test_wave_model_single_stripe_case_has_no_wait(wave_exe):
     assert r["rc"] == 0 and r["device_error"] == 0, r
     assert r["polls"] == 0
     assert r["results"][0][1].tolist() == oracle.full(X, Y)[1].tolist()
-    X2, Y2 = synth.random_pair(8001, 70, 50, 5, "normal")
+    X2, Y2 = synth.random_pair(8001, 90, 60, 5, "normal")  # forward sweep to diagonal 75: two stripes
     r2 = run_model(wave_exe, [(X2, Y2)], 3)
     assert r2["rc"] == 0 and r2["polls"] > 0
 
