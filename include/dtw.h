@@ -222,6 +222,19 @@ dtw_status dtw_diag(const void* X, const void* Y, int32_t d, int32_t in_dtype,
                     int64_t kstop, int32_t precision, void* workspace, size_t ws_bytes,
                     double* out, void* stream);
 
+/* Replay of repeated calls.  A dtw_align call whose arguments (device,
+ * pointers, sizes, options) all equal an earlier call's is recorded once into
+ * a HIP graph (recording runs nothing) and from then on replayed with one
+ * graph launch on `stream`; the first sighting of a set of arguments runs
+ * launch by launch, so one-off calls never pay the recording.  Calls with
+ * opts->profile and stats, dtw_align_noalloc, the batched and the serving
+ * forms always run launch by launch.  Results are those of the launch-by-
+ * launch sequence (the same kernels with the same arguments); the inputs are
+ * read when the replay runs.  Up to 16 graphs are kept (least recently used
+ * first out); DTW_GRAPHS=0 in the environment turns replay off.
+ * dtw_graph_count: graphs currently kept (a diagnostic). */
+int32_t dtw_graph_count(void);
+
 /* Device-side consistency code of the latest dtw_align, dtw_align_batched or
  * dtw_diag call that ran in `workspace` (device pointer).  The call's kernels
  * write the code, so it is valid once `stream` has completed that call: this

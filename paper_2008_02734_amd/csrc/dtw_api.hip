@@ -20,6 +20,7 @@ hipError_t launch_leaf(const Work& w, int grid, int64_t lds_leaf_bytes, const vo
                        hipStream_t st);
 hipError_t leaf_lds_setup(int64_t lds_max, int64_t* dyn_f64, int64_t* dyn_f32);
 hipError_t launch_init(const Work& w, hipStream_t st);
+hipError_t launch_store_pair(PairDesc* dst, const PairDesc& v, hipStream_t st);
 hipError_t launch_plan(const Work& w, int level, int final_level, int64_t lds_leaf_bytes, hipStream_t st);
 hipError_t launch_combine(const Work& w, int grid, hipStream_t st);
 hipError_t launch_assemble(const Work& w, int32_t* poff, int32_t* lidx, double* costs, int64_t* lens,
@@ -381,11 +382,110 @@ hipError_t stage_inputs(const Layout& L, void* ws, const void* X, const void* Y,
   return e;
 }
 
+// ----------------------------------------------------------------- graphs
+//
+// The launch sequence of a one-pair call is fixed by its arguments (the
+// recursion depth bound lmax, the kernels and their parameters follow from
+// the shapes and options; every decision inside is made on the device).  A
+// call whose every kernel argument (pointers, sizes, options, device) was
+// seen before is recorded once into a graph on a library stream (recording
+// runs nothing) and from then on replayed with one launch on the caller's
+// stream.  A first sighting runs eagerly, so one-off calls never pay the
+// recording.  DTW_GRAPHS=0 in the environment turns replay off.
+struct GraphKey {
+  int dev;
+  const void *X, *Y, *ws;
+  size_t ws_bytes;
+  double* costs;
+  int32_t* paths;
+  int64_t* lens;
+  int64_t path_cap, M, N;
+  int32_t d, in_dtype;
+  dtw_opts opts;
+  bool same(const GraphKey& o) const {
+    return dev == o.dev && X == o.X && Y == o.Y && ws == o.ws && ws_bytes == o.ws_bytes && costs == o.costs &&
+           paths == o.paths && lens == o.lens && path_cap == o.path_cap && M == o.M && N == o.N && d == o.d &&
+           in_dtype == o.in_dtype && memcmp(&opts, &o.opts, sizeof(dtw_opts)) == 0;
+  }
+};
+
+struct GraphCache {
+  struct Entry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  static constexpr size_t kMaxGraphs = 16, kMaxSeen = 64;
+  std::mutex mu;
+  std::vector<Entry> graphs;
+  std::vector<GraphKey> seen;
+  uint64_t clock = 0;
+  hipStream_t rec[64] = {};  // per device: the stream calls are recorded on
+};
+GraphCache& graph_cache() {
+  static GraphCache c;
+  return c;
+}
+
+// The replayable graph of `key`, recording it with `enqueue` when the key
+// was seen before; *exec stays null when the call should run eagerly.
+template <typename F>
+dtw_status graph_for(const GraphKey& key, F&& enqueue, hipGraphExec_t* exec) {
+  *exec = nullptr;
+  GraphCache& c = graph_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  ++c.clock;
+  for (auto& e : c.graphs)
+    if (e.key.same(key)) {
+      e.used = c.clock;
+      *exec = e.exec;
+      return DTW_OK;
+    }
+  bool seen = false;
+  for (auto& k : c.seen) seen = seen || k.same(key);
+  if (!seen) {
+    if (c.seen.size() >= GraphCache::kMaxSeen) c.seen.erase(c.seen.begin());
+    c.seen.push_back(key);
+    return DTW_OK;
+  }
+  if (key.dev < 0 || key.dev >= 64) return DTW_OK;
+  if (!c.rec[key.dev]) HIP_TRY(hipStreamCreateWithFlags(&c.rec[key.dev], hipStreamNonBlocking));
+  hipStream_t rs = c.rec[key.dev];
+  if (hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return DTW_OK;  // no recording on this device: the call runs eagerly
+  }
+  const dtw_status rc = enqueue(rs);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(rs, &g);
+  if (rc != DTW_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HIP_TRY(ee);
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIP_TRY(ei);
+  if (c.graphs.size() >= GraphCache::kMaxGraphs) {
+    size_t lru = 0;
+    for (size_t i = 1; i < c.graphs.size(); ++i)
+      if (c.graphs[i].used < c.graphs[lru].used) lru = i;
+    HIP_TRY(hipDeviceSynchronize());  // the evicted graph may still be running
+    HIP_TRY(hipGraphExecDestroy(c.graphs[lru].exec));
+    c.graphs.erase(c.graphs.begin() + (ptrdiff_t)lru);
+  }
+  c.graphs.push_back({key, x, c.clock});
+  *exec = x;
+  return DTW_OK;
+}
+
 // Core of dtw_align and dtw_align_batched.
 dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, const int64_t* yo, int d,
                int in_dtype, const dtw_opts* opts_in, void* ws, size_t ws_bytes, double* costs,
                int32_t* paths, const int64_t* path_offsets, int64_t path_cap_single, int64_t* lens,
-               dtw_stats* stats, hipStream_t st, int32_t** device_error_word = nullptr) {
+               dtw_stats* stats, hipStream_t st, int32_t** device_error_word = nullptr,
+               bool allow_graph = false) {
   dtw_opts opts;
   dtw_status rc = read_opts(opts_in, &opts);
   if (rc != DTW_OK) return rc;
@@ -443,24 +543,43 @@ dtw_status run(int n_pairs, const void* X, const void* Y, const int64_t* xo, con
   w.X = X;
   w.Y = Y;
   w.spin_ticks = wait_ticks(I, opts.wait_limit_us);
-  PROF_TRY(prof, kProfOther, stage_inputs(L, ws, X, Y, in_f64, Mtot, Ntot, d, opts.precision, opts.cost, w, st));
-  HIP_TRY(hipMemcpyAsync(at<void>(ws, L.pairs), pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, st));
-  PROF_TRY(prof, kProfOther, launch_init(w, st));
-
   // resident sweep workgroups per CU: two of 10 waves, or four of the Gram form's 4
   const int pass_grid = I.cus * std::max(1, env_int("DTW_PASS_WG_PER_CU", is_gram_precision(opts.precision) ? 4 : 2));
   const int comb_grid = I.cus * 4;
   const int64_t lds_leaf_bytes = I.leaf_dyn[f32 ? 1 : 0];
-  for (int lvl = 0; lvl <= L.lmax; ++lvl) {
-    const int final_level = (lvl == L.lmax) ? 1 : 0;
-    PROF_TRY(prof, kProfPlan, launch_plan(w, lvl, final_level, lds_leaf_bytes, st));
-    if (final_level) break;
-    PROF_TRY(prof, kProfSweep, launch_pass(w, lvl, pass_grid, st));
-    if (!opts.tie_exact) PROF_TRY(prof, kProfSplit, launch_combine(w, comb_grid, st));  // tie-exact: the sweep names the split
+  PairDesc* pairs_dev = at<PairDesc>(ws, L.pairs);
+  auto enqueue = [&](hipStream_t q, Profiler& pr) -> dtw_status {
+    PROF_TRY(pr, kProfOther, stage_inputs(L, ws, X, Y, in_f64, Mtot, Ntot, d, opts.precision, opts.cost, w, q));
+    if (n_pairs == 1) HIP_TRY(launch_store_pair(pairs_dev, pd[0], q));
+    else HIP_TRY(hipMemcpyAsync(pairs_dev, pd.data(), sizeof(PairDesc) * n_pairs, hipMemcpyHostToDevice, q));
+    PROF_TRY(pr, kProfOther, launch_init(w, q));
+    for (int lvl = 0; lvl <= L.lmax; ++lvl) {
+      const int final_level = (lvl == L.lmax) ? 1 : 0;
+      PROF_TRY(pr, kProfPlan, launch_plan(w, lvl, final_level, lds_leaf_bytes, q));
+      if (final_level) break;
+      PROF_TRY(pr, kProfSweep, launch_pass(w, lvl, pass_grid, q));
+      if (!opts.tie_exact) PROF_TRY(pr, kProfSplit, launch_combine(w, comb_grid, q));  // tie-exact: the sweep names the split
+    }
+    PROF_TRY(pr, kProfLeaf, launch_leaf(w, I.cus, lds_leaf_bytes, X, Y, in_f64, q));
+    PROF_TRY(pr, kProfOther,
+             launch_assemble(w, at<int32_t>(ws, L.poff), at<int32_t>(ws, L.lidx), costs, lens, paths, I.cus * 2, q));
+    return DTW_OK;
+  };
+  hipGraphExec_t exec = nullptr;
+  if (allow_graph && n_pairs == 1 && !prof.on && env_int("DTW_GRAPHS", 1) != 0) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const GraphKey key{dev, X, Y, ws, ws_bytes, costs, paths, lens, path_cap_single, Ms[0], Ns[0], d, in_dtype, opts};
+    Profiler off;
+    rc = graph_for(key, [&](hipStream_t rs) { return enqueue(rs, off); }, &exec);
+    if (rc != DTW_OK) return rc;
   }
-  PROF_TRY(prof, kProfLeaf, launch_leaf(w, I.cus, lds_leaf_bytes, X, Y, in_f64, st));
-  PROF_TRY(prof, kProfOther,
-           launch_assemble(w, at<int32_t>(ws, L.poff), at<int32_t>(ws, L.lidx), costs, lens, paths, I.cus * 2, st));
+  if (exec) {
+    HIP_TRY(hipGraphLaunch(exec, st));
+  } else {
+    rc = enqueue(st, prof);
+    if (rc != DTW_OK) return rc;
+  }
 
   if (stats) {
     Ctl c{};
@@ -633,7 +752,7 @@ dtw_status dtw_align(const void* X, int64_t M, const void* Y, int64_t N, int32_t
   if (M < 1 || N < 1) return DTW_ERR_INVALID_ARG;
   const int64_t xo[2] = {0, M}, yo[2] = {0, N};
   return run(1, X, Y, xo, yo, d, in_dtype, opts, workspace, ws_bytes, cost_out, path_out, nullptr, path_cap,
-             path_len_out, stats, (hipStream_t)stream);
+             path_len_out, stats, (hipStream_t)stream, nullptr, /*allow_graph=*/true);
 }
 
 dtw_status dtw_align_noalloc(const void* X, int64_t M, const void* Y, int64_t N, int32_t d, int32_t in_dtype,
@@ -651,6 +770,12 @@ dtw_status dtw_align_noalloc(const void* X, int64_t M, const void* Y, int64_t N,
   const int64_t xo[2] = {0, M}, yo[2] = {0, N};
   return run(1, X, Y, xo, yo, d, in_dtype, opts, ws, (size_t)DTW_NOALLOC_SCRATCH_BYTES, cost_out, path_out,
              nullptr, path_cap, path_len_out, stats, (hipStream_t)stream);
+}
+
+int32_t dtw_graph_count(void) {
+  GraphCache& c = graph_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  return (int32_t)c.graphs.size();
 }
 
 dtw_status dtw_device_error(const void* workspace, int32_t* code, void* stream) {

@@ -636,6 +636,13 @@ __global__ __launch_bounds__(256) void gram_stage_kernel(const TI* __restrict__ 
   }
 }
 
+// The pair descriptor of a one-pair call, taken by value: a launch instead
+// of a host-to-device copy, so that the call's sequence reads no host memory
+// and can be replayed from a graph.
+__global__ void store_pair_kernel(PairDesc* dst, PairDesc v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+
 __global__ void diag_setup_kernel(Work w, int32_t i0, int32_t j0, int32_t i1, int32_t j1, int32_t dir,
                                   int32_t kstop) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -670,6 +677,9 @@ namespace dtw {
 
 hipError_t launch_pass(const Work& w, int level, int grid, hipStream_t st);
 
+hipError_t launch_store_pair(PairDesc* dst, const PairDesc& v, hipStream_t st) {
+  return launch_checked(&store_pair_kernel, 1, 64, 0, st, dst, v);
+}
 hipError_t launch_init(const Work& w, hipStream_t st) {
   return launch_checked(&init_kernel, 256, 256, 0, st, w);
 }

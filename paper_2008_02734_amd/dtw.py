@@ -69,6 +69,8 @@ def lib():
         vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
         i64p = ctypes.POINTER(ctypes.c_int64)
         L.dtw_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.dtw_graph_count.restype = i32
+        L.dtw_graph_count.argtypes = []
         L.dtw_default_opts.restype = None
         L.dtw_status_string.argtypes = [i32]
         L.dtw_status_string.restype = ctypes.c_char_p
@@ -128,6 +130,11 @@ class DeviceError(DtwError):
     def __init__(self, code, what=""):
         self.code = code
         super().__init__(-9, f"{what}: device error {code}")
+
+
+def graph_count():
+    """Graphs the library keeps for replaying repeated dtw_align calls."""
+    return int(lib().dtw_graph_count())
 
 
 def device_error(ws, stream=None):

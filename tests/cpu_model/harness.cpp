@@ -470,6 +470,10 @@ hipError_t leaf_lds_setup(int64_t, int64_t* dyn_f64, int64_t* dyn_f32) {
   return hipSuccess;
 }
 
+hipError_t launch_store_pair(PairDesc* dst, const PairDesc& v, hipStream_t) {
+  cpu_launch(1, 64, [&] { store_pair_kernel(dst, v); });
+  return hipSuccess;
+}
 hipError_t launch_init(const Work& w, hipStream_t) {
   MODEL_LAUNCH_CHECK(&tag_init, 256, 256, 0);
   cpu_launch(2, 64, [&] { init_kernel(w); });

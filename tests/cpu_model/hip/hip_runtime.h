@@ -106,6 +106,19 @@ inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 template <class T>
 inline hipError_t hipGetSymbolAddress(void** p, T* sym) { *p = (void*)sym; return hipSuccess; }
 inline hipError_t hipGetLastError() { return hipSuccess; }
+// Graphs: the model records nothing, so a capture never begins and every
+// call runs eagerly.
+typedef void* hipGraph_t;
+typedef void* hipGraphExec_t;
+enum { hipStreamNonBlocking = 1, hipStreamCaptureModeThreadLocal = 1, hipErrorNotSupported = 801 };
+inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = nullptr; return hipSuccess; }
+inline hipError_t hipStreamBeginCapture(hipStream_t, int) { return hipErrorNotSupported; }
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = nullptr; return hipErrorNotSupported; }
+inline hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, void*, size_t) { return hipErrorNotSupported; }
+inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
+inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
+inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
 typedef int* hipEvent_t;
 inline hipError_t hipEventCreate(hipEvent_t* e) { static int dummy; *e = &dummy; return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
