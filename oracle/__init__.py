@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "dtw_oracle.c")
 _LIB = os.path.join(_HERE, "libdtw_oracle.so")
 
 GCC_CMD = [
-    "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+    "gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
     "-fno-fast-math", "-Wall", "-Wextra", _SRC, "-o", _LIB, "-lm",
 ]
 
