@@ -364,9 +364,69 @@ __device__ void tie_recurrence(const PassDesc& P, const Work& w, int p, int s, i
   // the origin holds its value in the whole table: the cost slot of lane 0,
   // step 0 takes it, so that F(origin) = 0 + f0 exactly
   if (s == 0 && lane == 0 && P.f0 == P.f0) cring[0] = (T)P.f0;
+  // the step of the block's last cell (in the last stripe only)
+  const int t_end = (a0 + kWave >= P.Mb) ? (P.Mb - 1 - a0) + (P.Nb - 1) : -1;
   for (int k = 0; k < n_phases; ++k) {
     const int t0 = k * kPhase;
     const int t1 = min(t0 + kPhase, n_steps);
+    // a phase that holds neither the label diagonals nor the last cell runs
+    // as the fast path does: operands loaded one group of steps ahead, lane
+    // 63's labels kept in registers and written out once per group
+    const bool plain = t1 == t0 + kPhase && !(a0 + t0 <= kf && a0 + t1 - 1 >= kf - 1) &&
+                       !(t_end >= t0 && t_end < t1);
+    if (plain) {
+      T* const hp = cring + (t0 & (kCostRing - 1)) * kWave + lane;
+      const T* bp = bring + in_vgpr(t0 & (2 * kPhase - 1));
+      const int* lp = blab + (t0 & (2 * kPhase - 1));
+      constexpr int G = kStepGroup;
+      T cb[2][G], bb[2][G];
+      int lb[2][G];
+      int labw[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        cb[0][i] = hp[i * kWave];
+        bb[0][i] = bp[i];
+        lb[0][i] = lp[i];
+      }
+#pragma unroll
+      for (int g = 0; g < kPhase / G; ++g) {
+        if (g + 1 < kPhase / G) {
+#pragma unroll
+          for (int i = 0; i < G; ++i) {
+            cb[(g + 1) & 1][i] = hp[((g + 1) * G + i) * kWave];
+            bb[(g + 1) & 1][i] = bp[(g + 1) * G + i];
+            lb[(g + 1) & 1][i] = lp[(g + 1) * G + i];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          const int u = g * G + i;
+          const T up = wave_shr1(bb[g & 1][i], f);
+          const int lu = wave_shr1_i(lb[g & 1][i], lab);
+          const T m = min_t(min_t(up_prev, f), up);
+          lab = (up_prev == m) ? lab_up_prev : ((up == m) ? lu : lab);  // DIAG, then UP, then LEFT
+          f = m + cb[g & 1][i];
+          up_prev = up;
+          lab_up_prev = lu;
+          hp[u * kWave] = f;  // the history, in the slot whose cost was read a group ago
+          labw[i] = lab;
+          if (i == G - 1 && lane == kWave - 1) {
+            static_assert(G == 4, "one 16-byte label store per group");
+            *reinterpret_cast<int4*>(labh + ((t0 + u - (G - 1)) & (kCostRing - 1))) =
+                make_int4(labw[0], labw[1], labw[2], labw[3]);
+          }
+          if ((u & (kPubGroup - 1)) == kPubGroup - 1) {
+            __builtin_amdgcn_wave_barrier();  // lane 63's values and labels read by the publishing lanes
+            if (has_succ) {
+              publish<T>(t0 + u, lane, cring, ring_out, tag_out, pub_max);
+              publish_labels(t0 + u, lane, labh, lring_out, tag_out, pub_max);
+            }
+          }
+        }
+      }
+      lds_barrier();
+      continue;
+    }
     for (int t = t0; t < t1; ++t) {
       T* const hp = cring + (t & (kCostRing - 1)) * kWave + lane;
       const T c = *hp;
@@ -528,14 +588,14 @@ template <typename T, int CM, int D>
 constexpr bool kPassStagesRows = (!is_gram(CM) && D >= 64) || kStageY<T, CM, D>;
 
 template <typename T, int D, int CM, bool kTie = false>
-__global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
+__global__ __launch_bounds__(pass_threads(CM), (is_gram(CM) ? 4 : kTie ? 2 : (D >= 32 && sizeof(T) == 8) ? 3 : D == 32 ? 4 : 5)) void pass_kernel(const T* __restrict__ X, const T* __restrict__ Y, Work w,
                                                             int level) {
   __shared__ T cring[kCostRing * kWave];  // frame costs, [slot][lane]
   __shared__ T bring[2 * kPhase];         // bottom row of the stripe above, [column & 63]
   __shared__ int sh_ticket;
   constexpr bool kTieOk = kTie && sizeof(T) == 8 && !is_gram(CM);  // tie-exact mode: FP64 sweeps only
   __shared__ int blab[kTieOk ? 2 * kPhase : 1];  // labels of the bottom row above (tie-exact mode)
-  __shared__ int labh[kTieOk ? kCostRing : 1];   // lane 63's labels by step (tie-exact mode)
+  __shared__ __align__(16) int labh[kTieOk ? kCostRing : 1];  // lane 63's labels by step (tie-exact mode)
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
   // the recurrence wave issues first on its SIMD: its dependency chain sets the pace

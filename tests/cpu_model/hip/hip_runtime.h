@@ -43,6 +43,8 @@ inline void __syncthreads() { cpu_block_barrier->arrive_and_wait(); }
 
 struct int2 { int x, y; };
 struct uint4 { unsigned x, y, z, w; };
+struct alignas(16) int4 { int x, y, z, w; };
+inline int4 make_int4(int a, int b, int c, int d) { return int4{a, b, c, d}; }
 struct double2 { double x, y; };
 inline int2 make_int2(int a, int b) { return int2{a, b}; }
 inline double2 make_double2(double a, double b) { return double2{a, b}; }
