@@ -221,6 +221,7 @@ Work make_work(const Layout& L, void* ws, int d, int m, int precision, int cost,
   Work w{};
   w.cost = cost;
   w.tie = tie;
+  w.leaf_split = L.n_pairs <= kLeafSplitPairs ? 1 : 0;
   w.ctl = at<Ctl>(ws, L.ctl);
   w.pairs = at<PairDesc>(ws, L.pairs);
   w.n_pairs = L.n_pairs;

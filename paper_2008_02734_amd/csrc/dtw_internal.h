@@ -24,6 +24,10 @@ constexpr uint32_t kSpinIterCap = 1u << 26;  // polls before a wait gives up
 // waves and one boundary-input wave; phases of kPhase steps between barriers.
 constexpr int kProducers = 8;
 constexpr int kLeafThreads = kWave * (kProducers + 2);
+// Calls with at most this many pairs run a leaf's stripes on several
+// workgroups (latency); larger batches keep one workgroup per leaf, their
+// many leaves already filling the GPU (throughput).
+constexpr int kLeafSplitPairs = 16;
 constexpr int kPhase = 32;
 constexpr int kCostRing = 128;  // LDS cost slots, indexed by step
 constexpr int kPubGroup = 16;   // steps per bottom-row publication (sweep and leaf)
@@ -88,6 +92,8 @@ struct LeafDesc {
   int64_t scratch_off;     // word offset in leaf scratch, or -1 when it fits in LDS
   int32_t stripe_off;      // first leaf-stripe ticket of the leaf
   int32_t n_stripes;       // ceil(R / 64) stripes of the shorter side
+  int32_t split;           // 1: its stripes run on several workgroups (one ticket each); 0: one workgroup
+  int32_t pad;
   int64_t ring_off;        // first cell of its min(n_stripes - 1, kRing) boundary rows in the leaf ring
   double f0;               // tie-exact mode: value of the leaf's origin cell (NaN: its own cost)
 };
@@ -155,6 +161,7 @@ struct Work {
   int32_t precision;
   int32_t cost;         // DTW_COST_EUCLIDEAN or DTW_COST_COSINE
   int32_t tie;          // 1: tie-exact splits (FP64)
+  int32_t leaf_split;   // 1: a leaf's stripes run on several workgroups (calls with few pairs)
   const void* X;        // compute-type copies (or the caller's arrays); bf16 in the Gram form
   const void* Y;
   const float* Xn;      // Gram form: squared norms of the bf16 frames, FP32

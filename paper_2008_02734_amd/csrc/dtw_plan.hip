@@ -139,11 +139,13 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
         // are in global scratch and its stripes hand their bottom rows over
         // through (n_stripes - 1) rows of the leaf ring.
         const int64_t R = min(Mb, Nb), Cc = max(Mb, Nb);
-        nst = (R + kWave - 1) / kWave;
-        const int64_t bpw = nst * ((Cc + kWave - 1 + 15) / 16) * kWave;
+        const int64_t stripes = (R + kWave - 1) / kWave;
+        const bool split = w.leaf_split && stripes > 1;
+        nst = split ? stripes : 1;  // tickets of the leaf
+        const int64_t bpw = stripes * ((Cc + kWave - 1 + 15) / 16) * kWave;
         const int64_t need = bpw + 2 * Cc;
-        if (nst > 1 || need * 4 > lds_leaf_bytes) words = need;
-        lcells = min(nst - 1, (int64_t)kRing) * Cc;
+        if (split || need * 4 > lds_leaf_bytes) words = need;
+        lcells = split ? min(stripes - 1, (int64_t)kRing) * Cc : 0;
       }
     }
     int64_t tot_leaf, tot_sub, tot_words;
@@ -167,7 +169,9 @@ __global__ __launch_bounds__(1024) void plan_kernel(Work w, int level, int final
         L.first = (c.i0 == pd.x_off && c.j0 == pd.y_off) ? 1 : 0;
         L.scratch_off = words ? words_base + wrank : -1;
         L.stripe_off = (int32_t)so;
-        L.n_stripes = (int32_t)nst;
+        L.n_stripes = (int32_t)((min(c.i1 - c.i0, c.j1 - c.j0) + kWave) / kWave);
+        L.split = nst > 1 ? 1 : 0;
+        L.pad = 0;
         L.ring_off = ro;
         L.f0 = c.f0;
         w.leaves[li] = L;

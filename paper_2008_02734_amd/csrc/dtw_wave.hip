@@ -1301,8 +1301,9 @@ __device__ __forceinline__ void wait_count(const int32_t* p, int32_t target, con
 }
 
 // Leaf tickets are (leaf, stripe) pairs, a leaf's stripes top to bottom on
-// consecutive tickets.  A leaf of one stripe is solved by one workgroup with
-// its pointers in LDS when they fit.  The stripes of a taller leaf run on as
+// consecutive tickets.  A leaf of one ticket (one stripe, or any leaf of a
+// call with many pairs) is solved by one workgroup, stripe after stripe, with
+// its pointers in LDS when they fit.  The stripes of a split leaf run on as
 // many workgroups as take their tickets, chained through the leaf ring like
 // the sweep's stripes; each writes its pointer words to the leaf's global
 // scratch, and every stripe but the last then counts itself done in
@@ -1349,9 +1350,11 @@ __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
     // a leaf lies inside its pair and is non-empty, its stripe count and
     // this ticket's stripe agree with its shape; refuse anything else
     const int nst = __builtin_amdgcn_readfirstlane(Lf.n_stripes);
+    const bool split = __builtin_amdgcn_readfirstlane(Lf.split) != 0;
+    const int ntk = split ? nst : 1;  // tickets of the leaf
     if (Mb < 1 || Nb < 1 || Lf.i0 < pd.x_off || Lf.j0 < pd.y_off || Lf.i1 >= pd.x_off + pd.M ||
-        Lf.j1 >= pd.y_off + pd.N || nst != (min(Mb, Nb) + kWave - 1) / kWave || st < 0 || st >= nst ||
-        Lf.stripe_off + st != tk || (nst > 1 && Lf.scratch_off < 0)) {
+        Lf.j1 >= pd.y_off + pd.N || nst != (min(Mb, Nb) + kWave - 1) / kWave || st < 0 || st >= ntk ||
+        Lf.stripe_off + st != tk || (split && (nst < 2 || Lf.scratch_off < 0))) {
       if (threadIdx.x == 0) set_error(ctl, kErrBadLeaf);
       continue;
     }
@@ -1375,15 +1378,16 @@ __global__ __launch_bounds__(kLeafThreads, 3) void leaf_kernel(
     const int64_t slot_end = pd.pbase + e;  // the block's last cell sits on diagonal e
     T fend;
     int cnt_written = 0;
-    if (nst == 1 && Lf.scratch_off < 0) {
+    if (!split && Lf.scratch_off < 0) {
+      // the whole leaf on this workgroup, stripes one after another, pointers in LDS
       uint32_t* bp = reinterpret_cast<uint32_t*>(lds_raw);
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
-                                  wave, lane, 0, 0, LeafRing{nullptr, 0u}, w);
+                                  wave, lane, 0, nst - 1, LeafRing{nullptr, 0u}, w);
       if (wave == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath, lane);
-    } else if (nst == 1) {
+    } else if (!split) {
       uint32_t* bp = w.leaf_scratch + Lf.scratch_off;
       fend = leaf_sweep<T, D, CM>(RowSrc, ColSrc, RowN, ColN, S, bp, reinterpret_cast<T*>(bp + bpw), cring, bring,
-                                  wave, lane, 0, 0, LeafRing{nullptr, 0u}, w);
+                                  wave, lane, 0, nst - 1, LeafRing{nullptr, 0u}, w);
       if (wave == 0) cnt_written = leaf_backtrace(bp, S, Lf, pd, slot_end, w.tpath, lane);
     } else {
       // one stripe of a taller leaf; ids of the leaf ring: 0xFF << 24 | (ticket + 1),

@@ -202,14 +202,18 @@ static void model_check_leaves(const Work& w) {
     const int R = std::min(Mb, Nb), Cc = std::max(Mb, Nb);
     const int nst = (R + 63) / 64;
     MODEL_CHECK(Lf.n_stripes == nst);
-    MODEL_CHECK(Lf.stripe_off >= 0 && Lf.stripe_off + nst <= w.ctl->leaf_stripes);
-    for (int u = 0; u < nst; ++u) {
+    MODEL_CHECK(Lf.split == (w.leaf_split && nst > 1 ? 1 : 0));
+    const int ntk = Lf.split ? nst : 1;
+    MODEL_CHECK(Lf.stripe_off >= 0 && Lf.stripe_off + ntk <= w.ctl->leaf_stripes);
+    for (int u = 0; u < ntk; ++u) {
       const int2 t = w.leaf_tk[Lf.stripe_off + u];
       MODEL_CHECK(t.x == l && t.y == u);
     }
-    MODEL_CHECK(Lf.ring_off >= 0 && Lf.ring_off + (int64_t)std::min(nst - 1, kRing) * Cc <= w.ctl->leaf_ring_cells);
+    if (Lf.split) {
+      MODEL_CHECK(Lf.ring_off >= 0 && Lf.ring_off + (int64_t)std::min(nst - 1, kRing) * Cc <= w.ctl->leaf_ring_cells);
+      MODEL_CHECK(Lf.scratch_off >= 0);
+    }
     MODEL_CHECK(w.ctl->leaf_ring_cells <= w.caps.leaf_ring);
-    if (nst > 1) MODEL_CHECK(Lf.scratch_off >= 0);
   }
   MODEL_CHECK(w.ctl->leaf_stripes >= 0 && w.ctl->leaf_stripes <= w.caps.leaf_tk);
 }

@@ -383,3 +383,16 @@ def test_wave_model_tie_exact(wave_exe, M, N, d, fam, m):
     assert path.tolist() == p_ref.tolist()
     assert abs(cost - c_ref) <= 1e-12 * max(c_ref, 1.0)
     assert oracle.linmdtw_tie(X, Y, min_block=m)["path"].tolist() == p_ref.tolist()
+
+
+def test_wave_model_batch_keeps_leaves_on_one_workgroup(wave_exe):
+    # 18 pairs (more than a call splits leaves for): every leaf, two stripes
+    # tall, runs on one workgroup stripe after stripe; each pair's path is the
+    # oracle's textbook path
+    pairs = [synth.random_pair(9800 + b, 70 + 3 * b, 90 - 2 * b, 3, "normal") for b in range(18)]
+    r = run_model(wave_exe, pairs, 500)
+    assert r["rc"] == 0 and r["device_error"] == 0, r
+    for (X, Y), (cost, path) in zip(pairs, r["results"]):
+        c_ref, p_ref = oracle.full(X, Y)
+        assert path.tolist() == p_ref.tolist()
+        assert abs(cost - c_ref) <= 1e-12 * c_ref
