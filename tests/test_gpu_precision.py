@@ -299,3 +299,29 @@ def test_batch_full_size_fp32_sampled_against_oracle(dtw):
         check_path(p, *shapes[b])
         assert abs(costs[b] - oracle.path_cost(Xr, Yr, p)) <= 1e-12 * c_ref
         assert -1e-12 <= (costs[b] - c_ref) / c_ref <= FP32_REL_TOL
+
+
+def test_batch_full_size_fp32_every_pair_against_fp64(dtw):
+    # every one of the 512 pairs, at sizes the oracle's table cannot reach in
+    # the test: a valid warping path whose reported cost is the oracle's FP64
+    # cost of that path, no cheaper than the exact FP64 path of the same
+    # batch (its optimum) and within the FP32 tolerance of it; the FP64
+    # batch's own costs are the oracle's FP64 costs of its paths
+    shapes = synth.batch_shapes(512)
+    Xs, Ys = [], []
+    for p, (M, N) in enumerate(shapes):
+        X, Y = synth.make_pair(4, p, M, N, 24, "chroma")
+        Xs.append(X.astype(np.float32).astype(np.float64))
+        Ys.append(Y.astype(np.float32).astype(np.float64))
+    c32, p32, st32 = dtw.align_batched([dev(X, torch.float32) for X in Xs], [dev(Y, torch.float32) for Y in Ys],
+                                       precision="fp32")
+    c64, p64, st64 = dtw.align_batched([dev(X) for X in Xs], [dev(Y) for Y in Ys])
+    assert st32["device_error"] == 0 and st64["device_error"] == 0
+    c32, c64 = c32.cpu().numpy(), c64.cpu().numpy()
+    for b, (M, N) in enumerate(shapes):
+        q32, q64 = p32[b].cpu().numpy(), p64[b].cpu().numpy()
+        check_path(q32, M, N)
+        check_path(q64, M, N)
+        assert abs(c32[b] - oracle.path_cost(Xs[b], Ys[b], q32)) <= 1e-12 * c64[b]
+        assert abs(c64[b] - oracle.path_cost(Xs[b], Ys[b], q64)) <= 1e-12 * c64[b]
+        assert -1e-12 <= (c32[b] - c64[b]) / c64[b] <= FP32_REL_TOL, b
