@@ -116,3 +116,25 @@ def test_tie_exact_full_size_pair(dtw):
     assert st["device_error"] == 0
     assert p.tolist() == pd.cpu().numpy().tolist()
     assert oracle.path_cost(X, Y, p) == pytest.approx(c, rel=1e-12)
+
+
+def test_tie_exact_served(dtw):
+    # the serving loop keeps tie-exact requests apart from default ones (the
+    # split rule is part of a batch's class): tie-exact requests give the
+    # textbook path, default ones the port of Algorithm 2, on tie-heavy pairs
+    pairs = [synth.random_pair(9900 + i, 400 + 90 * i, 350 + 70 * i, 1, "int3") for i in range(6)]
+    srv = dtw.Server(pool_bytes=1 << 30, max_slots=2, max_batch=4)
+    try:
+        tks = [srv.submit(dev(X), dev(Y), min_block=64, tie_exact=(i % 2 == 0)) for i, (X, Y) in enumerate(pairs)]
+        res = [srv.wait(t) for t in tks]
+    finally:
+        srv.close()
+    for i, ((X, Y), r) in enumerate(zip(pairs, res)):
+        assert r["status"] == 0
+        c_ref, p_ref = oracle.full(X, Y)
+        p = r["path"].cpu().numpy()
+        if i % 2 == 0:
+            assert p.tolist() == p_ref.tolist()
+        else:
+            assert p.tolist() == oracle.linmdtw(X, Y, min_block=64)["path"].tolist()
+        assert abs(r["cost"] - c_ref) <= 1e-12 * max(c_ref, 1.0)
