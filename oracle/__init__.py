@@ -8,7 +8,11 @@ Contents:
   dtw_oracle.c  plain FP64 C: frame cost, textbook full-table DTW with
                 backpointers and backtrace (Sec. 2.1), DiagDTW (Algorithm 1),
                 linmdtw (Algorithm 2);
-  brute.py      enumeration of every warping path for M, N <= 8.
+  brute.py      enumeration of every warping path for M, N <= 8 (and of
+                every edit-distance lattice path for M, N <= 7);
+  edit_oracle.c, edit.py
+                the weighted edit distance: textbook table and backtrace,
+                and its linear-memory divide and conquer (own library).
 
 This module builds the C file with gcc (floating-point contraction off) and
 wraps it with ctypes.  All arrays are numpy float64 / int32 on the host.

@@ -118,3 +118,52 @@ def brute_dtw_f32(X, Y):
         if best is None or s < best:
             best = s
     return float(best)
+
+
+def brute_edit(a, b, sub=1, gap=1):
+    """Weighted edit distance by enumeration of every lattice path of nodes
+    (0,0) -> (M,N), M, N <= 7 (the moves of an (M+1) x (N+1) warping grid).
+    A DIAG move into node (i,j) costs 0 when a[i-1] == b[j-1], else `sub`;
+    UP and LEFT moves cost `gap`.  Returns (least cost, the minimiser whose
+    backward move sequence is smallest under DIAG < UP < LEFT, number of
+    optimal paths)."""
+    M, N = len(a), len(b)
+    if M > 7 or N > 7:
+        raise ValueError("brute force is limited to M, N <= 7")
+    rank = {DIAG: 0, UP: 1, LEFT: 2}
+    best, best_path, n_best = None, None, 0
+    for p in enumerate_paths(M + 1, N + 1):
+        s = 0
+        for q in range(1, len(p)):
+            (i, j), (pi, pj) = p[q], p[q - 1]
+            if (i - pi, j - pj) == (1, 1):
+                s += 0 if a[i - 1] == b[j - 1] else sub
+            else:
+                s += gap
+        if best is None or s < best:
+            best, best_path, n_best = s, p, 1
+        elif s == best:
+            n_best += 1
+            if [rank[m] for m in backward_moves(p)] < [rank[m] for m in backward_moves(best_path)]:
+                best_path = p
+    return best, best_path, n_best
+
+
+def brute_lcs(a, b):
+    """Length of a longest common subsequence, by trying every subsequence of
+    the shorter string (length <= 12) against the other."""
+    from itertools import combinations
+    if len(a) > len(b):
+        a, b = b, a
+    if len(a) > 12:
+        raise ValueError("brute force is limited to 12 characters")
+
+    def is_subseq(s, t):
+        it = iter(t)
+        return all(ch in it for ch in s)
+
+    for k in range(len(a), 0, -1):
+        for idx in combinations(range(len(a)), k):
+            if is_subseq([a[i] for i in idx], b):
+                return k
+    return 0

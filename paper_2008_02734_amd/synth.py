@@ -162,3 +162,35 @@ def batch_shapes(n_pairs=512, lo=1000, hi=30000, config_id=4):
                 break
         shapes.append((M, N))
     return shapes
+
+
+# ----------------------------------------------------------------- strings
+#
+# Byte strings for the edit-distance path: a is uniform over an alphabet of
+# `k` letters (bytes 0..k-1); b copies a through a mutation channel -- at
+# each position of a, with probability p/3 each, the letter is replaced by
+# a uniform letter, deleted, or preceded by an inserted uniform letter --
+# and is then cut to N letters or extended by uniform letters.  With p = 0
+# and N = M, b == a.  Seeds: np.random.default_rng([7, seed]).
+
+def string_pair(seed, M, N, k=4, p=0.1):
+    rng = np.random.default_rng([7, int(seed)])
+    a = rng.integers(0, k, M).astype(np.uint8)
+    u = rng.random(M)
+    kind = np.where(u < p / 3, 1, np.where(u < 2 * p / 3, 2, np.where(u < p, 3, 0)))
+    letters = rng.integers(0, k, M).astype(np.uint8)
+    extra = rng.integers(0, k, M).astype(np.uint8)
+    keep = kind != 2
+    sub = np.where(kind == 1, letters, a)
+    # an insertion puts `extra` before the position's own letter
+    ins = kind == 3
+    lens = keep.astype(np.int64) + ins
+    out = np.empty(int(lens.sum()), dtype=np.uint8)
+    pos = np.cumsum(lens) - lens
+    out[pos[ins]] = extra[ins]
+    out[(pos + ins)[keep]] = sub[keep]
+    if out.size >= N:
+        b = out[:N]
+    else:
+        b = np.concatenate([out, rng.integers(0, k, N - out.size).astype(np.uint8)])
+    return np.ascontiguousarray(a), np.ascontiguousarray(b)
