@@ -345,6 +345,56 @@ dtw_status dtw_server_wait(dtw_server* server, uint64_t ticket, dtw_result* resu
 /* Waits for every submitted request, then releases the pool and the streams. */
 dtw_status dtw_server_destroy(dtw_server* server);
 
+/* ------------------------------------------------------------------------
+ * Weighted edit distance in linear memory.  Sec. 6 names edit distance as a
+ * problem with the DTW dynamic-programming structure that alignment under
+ * memory limits would serve; the method of Sec. 3 is carried over to it:
+ *   - lattice: nodes (i, j), 0 <= i <= M, 0 <= j <= N, for byte strings a
+ *     (length M) and b (length N); a DIAG move into (i, j) costs 0 when
+ *     a[i-1] == b[j-1] and `sub` otherwise, UP and LEFT moves cost `gap`;
+ *     the distance is the least total cost of a path (0,0) -> (M, N);
+ *   - split on a node row (every path crosses it): with F the least cost
+ *     from a block's origin to each node of row mid and B the least cost
+ *     from there to the block's end, the smallest column minimising F + B
+ *     lies on an optimal path (the counterpart of Lemma 2, with nothing to
+ *     subtract because the costs sit on the moves);
+ *   - rows follow a fixed dyadic partition: block k of level L spans node
+ *     rows floor(k M / 2^L) .. floor((k+1) M / 2^L) and splits at
+ *     floor((2k+1) M / 2^(L+1)); levels split while ceil(M / 2^L) exceeds
+ *     leaf_rows, and the blocks of the first level that does not are solved
+ *     with a full table and a backtrace (ties DIAG, then UP, then LEFT).
+ * Working memory is O(M + N) (no M x N table).
+ *
+ * dtw_edit_workspace_size: bytes of device workspace for M x N and
+ * leaf_rows.  DTW_ERR_INVALID_ARG for bytes == NULL or sizes outside the
+ * limits of dtw_edit_align. */
+dtw_status dtw_edit_workspace_size(int64_t M, int64_t N, int32_t leaf_rows, size_t* bytes);
+
+/* Edit distance and an optimal alignment path.
+ *   a, b          device, M and N bytes (may be NULL when the length is 0)
+ *   sub, gap      move costs, 0 <= sub, gap <= 2^20, and
+ *                 (M + N + 1) * max(sub, gap) < 2^30
+ *   leaf_rows     2 .. 64: rows of the blocks solved with a full table
+ *   workspace     device, at least dtw_edit_workspace_size() bytes, any contents
+ *   dist_out      device, 1 int64: the distance, which is also the cost of the
+ *                 returned path; a negative value -code after a device-side
+ *                 error (1: a boundary wait expired, 2: an inconsistent block,
+ *                 3: the path's cost differs from the top split's minimum)
+ *   path_out      device, 2 * path_cap int32: the nodes (i, j) from (0, 0) to
+ *                 (M, N) in path order
+ *   path_cap      capacity in nodes, >= M + N + 1
+ *   path_len_out  device, 1 int64: node count (0 after a device-side error)
+ *   stream        hipStream_t or NULL
+ * 0 <= M, N <= 2^30.  Stream-ordered: returns before the work completes.
+ * The caller owns every buffer; the call allocates no device memory.  Errors
+ * before any work is enqueued: DTW_ERR_INVALID_ARG (sizes, costs, leaf_rows,
+ * null pointers), DTW_ERR_CAPACITY, DTW_ERR_WORKSPACE; DTW_ERR_HIP when a
+ * launch fails.  Calls that share a workspace must not overlap in time. */
+dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t N, int32_t sub,
+                          int32_t gap, int32_t leaf_rows, void* workspace, size_t ws_bytes,
+                          int64_t* dist_out, int32_t* path_out, int64_t path_cap,
+                          int64_t* path_len_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

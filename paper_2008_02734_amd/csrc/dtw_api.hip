@@ -650,6 +650,10 @@ hipError_t scratch_address(void** out) {
 
 namespace dtw {
 
+void note_hip_error(hipError_t e) { g_last_hip = (int32_t)e; }
+int64_t wall_ticks_per_ms() { return dev_info().wall_khz; }
+int device_cus() { return dev_info().cus; }
+
 // Compiled resources of each kernel, read once per device; the dynamic LDS
 // limit of the leaf kernels is set before their first launch (leaf_lds_setup)
 // and the cache entry is taken after that.

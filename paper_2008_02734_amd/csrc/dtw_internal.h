@@ -202,5 +202,11 @@ struct Work {
 // DTW_ERR_INTERNAL instead of enqueueing a launch the device cannot run).
 hipError_t check_launch(const void* fn, int grid, int threads, size_t dyn_lds);
 bool launch_rejected();
+// Record a failed HIP call's code for dtw_last_hip_error() (calling thread).
+void note_hip_error(hipError_t e);
+// Device wall-clock ticks per millisecond of the current device.
+int64_t wall_ticks_per_ms();
+// Compute units of the current device.
+int device_cus();
 
 }  // namespace dtw

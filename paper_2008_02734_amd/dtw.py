@@ -93,6 +93,10 @@ def lib():
         L.dtw_align_batched.argtypes = [i32, vp, i64p, vp, i64p, i32, i32, ctypes.POINTER(Opts), vp, sz, vp,
                                         vp, i64p, vp, ctypes.POINTER(Stats), vp]
         L.dtw_align_batched.restype = i32
+        L.dtw_edit_workspace_size.argtypes = [i64, i64, i32, ctypes.POINTER(sz)]
+        L.dtw_edit_workspace_size.restype = i32
+        L.dtw_edit_align.argtypes = [vp, i64, vp, i64, i32, i32, i32, vp, sz, vp, vp, i64, vp, vp]
+        L.dtw_edit_align.restype = i32
         _lib = L
     return _lib
 
@@ -434,3 +438,54 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- edit distance
+
+def edit_workspace_size(M, N, leaf_rows=64):
+    n = ctypes.c_size_t()
+    _check(lib().dtw_edit_workspace_size(int(M), int(N), int(leaf_rows), ctypes.byref(n)), "dtw_edit_workspace_size")
+    return n.value
+
+
+class EditAligner:
+    """Reusable workspace and outputs for edit-distance alignments of strings
+    of at most M and N bytes (dtw_edit_align)."""
+
+    def __init__(self, M, N, leaf_rows=64, device="cuda"):
+        self.M, self.N, self.leaf_rows = int(M), int(N), int(leaf_rows)
+        self.ws_bytes = edit_workspace_size(M, N, leaf_rows)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.dist = torch.empty(1, dtype=torch.int64, device=device)
+        self.path = torch.empty((self.M + self.N + 1, 2), dtype=torch.int32, device=device)
+        self.plen = torch.empty(1, dtype=torch.int64, device=device)
+
+    def run(self, a, b, sub=1, gap=1, stream=None):
+        """Enqueue one alignment of device uint8 tensors a (M) and b (N)."""
+        for t in (a, b):
+            if t.dtype != torch.uint8 or t.dim() != 1 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("a and b must be contiguous 1-D uint8 device tensors")
+        M, N = a.shape[0], b.shape[0]
+        if (M, N) != (self.M, self.N):
+            raise ValueError(f"sized for {self.M} x {self.N}, got {M} x {N}")
+        _check(lib().dtw_edit_align(ctypes.c_void_p(a.data_ptr() if M else 0), M,
+                                    ctypes.c_void_p(b.data_ptr() if N else 0), N, int(sub), int(gap),
+                                    self.leaf_rows, ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                    ctypes.c_void_p(self.dist.data_ptr()), ctypes.c_void_p(self.path.data_ptr()),
+                                    self.path.shape[0], ctypes.c_void_p(self.plen.data_ptr()), _stream_ptr(stream)),
+               "dtw_edit_align")
+
+
+def edit_align(a, b, sub=1, gap=1, leaf_rows=64, stream=None):
+    """Edit distance and an optimal alignment of device uint8 tensors a and b.
+
+    Returns (distance: int, path: int32 tensor [n, 2] of nodes (i, j) on the
+    device).  Synchronises the stream.  Raises DeviceError when the call's
+    kernels recorded a device-side error."""
+    al = EditAligner(a.shape[0], b.shape[0], leaf_rows, device=a.device)
+    al.run(a, b, sub, gap, stream)
+    d = int(al.dist.item())
+    n = int(al.plen.item())
+    if d < 0:
+        raise DeviceError(-d, "dtw_edit_align")
+    return d, al.path[:n]

@@ -1,0 +1,73 @@
+"""CPU model of the edit-distance kernels: the real dtw_edit.hip source (its
+kernels and host entry points) compiled for the host with AddressSanitizer
+and UndefinedBehaviorSanitizer against the thread-based HIP stand-in of
+tests/cpu_model, one OS thread per lane.  Blocks of a launch run one after
+another, so the persistent sweep's first workgroup takes every stripe in
+ticket order.  Results are compared with the oracle (edit distance of the
+textbook table, path of the linear-memory recursion), bit for bit."""
+import os
+import struct
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import edit
+from paper_2008_02734_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MODEL = os.path.join(ROOT, "tests", "cpu_model")
+CSRC = os.path.join(ROOT, "paper_2008_02734_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def edit_model(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("edit_model") / "edit_model")
+    subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-fno-omit-frame-pointer", "-Wno-unknown-pragmas", "-pthread", "-I", MODEL,
+                    "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-x", "c++",
+                    os.path.join(MODEL, "edit_driver.cpp"), "-o", exe], check=True)
+    return exe
+
+
+def run_edit_model(exe, a, b, sub, gap, leaf_rows):
+    with tempfile.TemporaryDirectory() as td:
+        fi, fo = os.path.join(td, "in"), os.path.join(td, "out")
+        with open(fi, "wb") as f:
+            f.write(struct.pack("2q4i", a.size, b.size, sub, gap, leaf_rows, 0))
+            f.write(a.tobytes())
+            f.write(b.tobytes())
+        r = subprocess.run([exe, fi, fo], capture_output=True, timeout=600,
+                           env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+        assert r.returncode == 0, r.stderr.decode()[-3000:]
+        buf = open(fo, "rb").read()
+    rc, levels = struct.unpack_from("2i", buf, 0)
+    dist, n = struct.unpack_from("2q", buf, 8)
+    path = np.frombuffer(buf[24:24 + 8 * n], dtype=np.int32).reshape(-1, 2) if rc == 0 else None
+    return rc, levels, dist, path
+
+
+# (M, N, sub, gap, leaf_rows): empty strings, one leaf, leaves of two rows,
+# several levels, and half sweeps of two stripes (more than 256 rows) whose
+# second stripe reads the first one's bottom row through the ring
+CASES = [(0, 5, 1, 1, 2), (5, 0, 1, 1, 2), (1, 1, 1, 1, 2), (7, 9, 1, 1, 2), (40, 33, 1, 1, 3),
+         (600, 90, 3, 2, 64), (90, 300, 1, 1, 5), (530, 41, 0, 1, 40)]
+
+
+@pytest.mark.parametrize("M,N,sub,gap,h", CASES)
+def test_edit_model_equals_oracle(edit_model, M, N, sub, gap, h):
+    a, b = synth.string_pair(8000 + M + N, M, N, k=4, p=0.2)
+    rc, levels, dist, path = run_edit_model(edit_model, a, b, sub, gap, h)
+    assert rc == 0
+    assert levels == edit.levels(M, h)
+    assert dist == edit.full(a, b, sub, gap)[0]
+    assert path.tolist() == edit.linear(a, b, sub, gap, leaf_rows=h)["path"].tolist()
+
+
+def test_edit_model_rejects_bad_arguments(edit_model):
+    a, b = synth.string_pair(1, 10, 10)
+    assert run_edit_model(edit_model, a, b, 1, 1, 1)[0] == -1    # leaf_rows below 2
+    assert run_edit_model(edit_model, a, b, 1, 1, 65)[0] == -1   # above one wave
+    assert run_edit_model(edit_model, a, b, -1, 1, 8)[0] == -1   # negative cost
+    assert run_edit_model(edit_model, a, b, 1 << 21, 1, 8)[0] == -1
