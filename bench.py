@@ -24,9 +24,14 @@ of the method's AI-systems forms, and the tie-exact mode (unless --no-extras):
              ratio, p50/p99 latency, largest relative cost error);
   tie_exact  the headline pair with tie-exact splits beside the default ones.
 
+  edit_distance  the config-6 edit-distance workload (below).
+
 Other workloads (--config): 1 = 500 x 400 FP64 latency; 3 = 200000 x 160000,
 d = 128, BF16 Gram cost on the matrix cores; 4 = 512 pairs in one batched
-call, d = 24, FP32; 5 = the serving stream alone (also an all-FP32 mix).
+call, d = 24, FP32; 5 = the serving stream alone (also an all-FP32 mix);
+6 = edit distance of two 200000 x 160000 byte strings (dtw_edit_align), with
+its own roofline (the integer sweep) and CPU baseline (the oracle's
+recursion on a leading block).
 """
 import argparse
 import json
@@ -477,6 +482,131 @@ def tie_exact_summary(args):
     return out
 
 
+# Edit distance (config 6): two byte strings over 4 letters, b from a
+# through a 10% mutation channel (substitutions, deletions, insertions),
+# unit costs, leaves of 64 rows.  The sweep is pure 32-bit integer VALU work
+# (no packed form of 32-bit integer add or min: 16 lanes per SIMD per cycle)
+# at 6 slots per cell: letter compare, cost select, two adds, two mins.
+EDIT = dict(name="edit distance, 200000x160000 byte strings over 4 letters (b = a through 10% substitutions/"
+                 "deletions/insertions), unit costs, linear-memory row-split recursion with 64-row leaves",
+            M=200000, N=160000, k=4, p=0.1, sub=1, gap=1, leaf_rows=64, seed=6)
+EDIT_SLOTS_PER_CELL = 6
+INT32_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def edit_roofline(stats, traffic=None):
+    sweep_ms = float(np.mean([s["sweep_ms"] for s in stats]))
+    st = stats[-1]
+    achieved = st["sweep_cells"] / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
+    peak = INT32_SLOTS_PER_S / EDIT_SLOTS_PER_CELL / 1e9
+    return {"bound": "alu", "kernel": "ed_sweep_kernel (edit-distance wavefront sweep)", "achieved": achieved,
+            "peak": peak, "unit": "Gcells/s", "frac": (achieved / peak) if achieved else None, "traffic": traffic,
+            "launches_per_step": st["levels"], "sweep_cells_per_step": st["sweep_cells"],
+            "avg_sweep_launch_ms": sweep_ms / max(1, st["levels"])}
+
+
+def edit_run(steps, warmup):
+    """Time dtw_edit_align on the config-6 strings; returns the record body and
+    the host strings (for the parity check and the CPU sample)."""
+    import torch
+
+    from paper_2008_02734_amd import dtw, synth
+    E = EDIT
+    M, N = E["M"], E["N"]
+    a, b = synth.string_pair(E["seed"], M, N, k=E["k"], p=E["p"])
+    da, db = torch.from_numpy(a).to("cuda:0"), torch.from_numpy(b).to("cuda:0")
+    al = dtw.EditAligner(M, N, E["leaf_rows"], device="cuda:0")
+    stream = torch.cuda.current_stream()
+    ms, lat, stats = timed_steps(lambda: al.run(da, db, E["sub"], E["gap"], stream=stream, stats=True), steps, warmup)
+    st = stats[-1]
+    assert all(s["device_error"] == 0 for s in stats), st
+    n = int(al.plen.item())
+    body = {"ms": ms, "gcups": M * N / (ms * 1e-3) / 1e9, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "distance": int(al.dist.item()), "path_nodes": n,
+            "sweep_ms": float(np.mean([s["sweep_ms"] for s in stats])),
+            "cells_processed": st["sweep_cells"] + st["leaf_cells"],
+            "processed_gcups": (st["sweep_cells"] + st["leaf_cells"]) / (ms * 1e-3) / 1e9,
+            "levels": st["levels"], "roofline": edit_roofline(stats, measured_edit_traffic())}
+    return body, a, b, al.path[:n].cpu().numpy()
+
+
+def edit_checks(a, b, dist, path, with_cpu=True):
+    """Parity of the returned path and the CPU baseline: the path's cost (the
+    oracle's, move by move) equals the distance; the oracle's recursion on the
+    leading 40000 x 32000 block gives that block's distance and is the CPU
+    sample (single thread; its rate taken as the workload's)."""
+    from oracle import edit
+    E = EDIT
+    out = {"path_cost_equals_distance": edit.path_cost(a, b, path, E["sub"], E["gap"]) == dist}
+    if with_cpu:
+        Ms, Ns = 40000, 32000
+        t = time.perf_counter()
+        r = edit.linear(a[:Ms], b[:Ns], E["sub"], E["gap"], E["leaf_rows"])
+        cpu_s = time.perf_counter() - t
+        flags = [f for f in edit.GCC_CMD if f.startswith(("-O", "-std"))]
+        out["cpu_baseline"] = {"value": Ms * Ns / cpu_s / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's linear-memory recursion (edo_linear) on the leading "
+                                         f"{Ms}x{Ns} block, single thread, {cpu_s:.1f} s; its rate taken as "
+                                         f"the workload's", "sample_s": cpu_s, "extrapolated": True,
+                               "oracle_build": "gcc " + " ".join(flags) + " (oracle/edit_oracle.c, untuned)"}
+        out["_block"] = (Ms, Ns, r)
+    return out
+
+
+def edit_summary(args):
+    """Default-run sub-object: the config-6 edit-distance workload."""
+    body, a, b, path = edit_run(5, 1)
+    chk = edit_checks(a, b, body["distance"], path, with_cpu=False)
+    body["workload"] = EDIT["name"]
+    body["path_cost_equals_distance"] = chk["path_cost_equals_distance"]
+    return body
+
+
+def bench_edit(args):
+    import torch
+
+    from paper_2008_02734_amd import dtw
+    E = EDIT
+    body, a, b, path = edit_run(args.steps, args.warmup)
+    out = base_record(args, body["gcups"], body["ms"], "int32",
+                      {"workload": E["name"], "M": E["M"], "N": E["N"], "alphabet": E["k"], "mutation": E["p"],
+                       "sub": E["sub"], "gap": E["gap"], "leaf_rows": E["leaf_rows"], "seed": [7, E["seed"]]})
+    out["metric"] = "edit-distance DP cells/sec (GCUPS, M*N per alignment) + fraction of VALU roofline"
+    out.update({k: v for k, v in body.items() if k not in ("ms", "gcups")})
+    chk = edit_checks(a, b, body["distance"], path, with_cpu=not args.no_cpu_baseline)
+    out["parity"] = {"path_cost_equals_distance": chk["path_cost_equals_distance"]}
+    if "_block" in chk:
+        # the GPU on the same leading block: distance and path equal the oracle's
+        Ms, Ns, r = chk["_block"]
+        da = torch.from_numpy(a[:Ms].copy()).cuda()
+        db = torch.from_numpy(b[:Ns].copy()).cuda()
+        d, p = dtw.edit_align(da, db, E["sub"], E["gap"], E["leaf_rows"])
+        out["parity"]["leading_block"] = f"{Ms}x{Ns}"
+        out["parity"]["block_distance_equal"] = d == r["dist"]
+        out["parity"]["block_path_equal"] = p.cpu().numpy().tolist() == r["path"].tolist()
+        out["cpu_baseline"] = chk["cpu_baseline"]
+    return out
+
+
+EDIT_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ed_sweep_kernel_200000x160000_hbm_traffic.txt")
+EDIT_SOURCE = os.path.join(ROOT, "paper_2008_02734_amd", "csrc", "dtw_edit.hip")
+
+
+def measured_edit_traffic():
+    """HBM bytes per edit sweep launch from the committed counter record, or
+    None when there is none or dtw_edit.hip has changed since it was taken."""
+    import hashlib
+    try:
+        txt = open(EDIT_TRAFFIC_RECORD).read()
+        rec = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line and " " not in line.split(": ")[0])
+        sha = hashlib.sha256(open(EDIT_SOURCE, "rb").read()).hexdigest()
+        if not sha.startswith(rec["kernel_source_sha256_prefix"].strip()):
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_record(cells, cpu_s, sample, whole):
     """The cpu_baseline object: the oracle's rate on `sample`.  `whole` says
     whether the sample is the entire workload; if not, the rate is the
@@ -548,6 +678,9 @@ def main():
             out["serving"], _ = serving_summary(args, args.requests, args.serving_m_hi,
                                                 [("bf16_mix", "bf16"), ("fp16_mix", "fp16")])
             out["tie_exact"] = tie_exact_summary(args)
+            out["edit_distance"] = edit_summary(args)
+    elif args.config == 6:
+        out = bench_edit(args)
     elif args.config == 4:
         out = bench_batched(args)
     elif args.config == 5:

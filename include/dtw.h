@@ -370,6 +370,16 @@ dtw_status dtw_server_destroy(dtw_server* server);
  * limits of dtw_edit_align. */
 dtw_status dtw_edit_workspace_size(int64_t M, int64_t N, int32_t leaf_rows, size_t* bytes);
 
+/* Optional host-side measurements of one dtw_edit_align call. */
+typedef struct dtw_edit_stats {
+  int32_t levels;        /* split levels (sweep launches)                          */
+  int32_t device_error;  /* 0, or the device-side code (see dist_out)              */
+  int64_t sweep_cells;   /* cells evaluated by the half sweeps of every level      */
+  int64_t leaf_cells;    /* cells of the leaf tables                               */
+  double sweep_ms;       /* summed duration of the sweep launches (HIP events)     */
+  double total_ms;       /* first launch of the call to its last (HIP events)      */
+} dtw_edit_stats;
+
 /* Edit distance and an optimal alignment path.
  *   a, b          device, M and N bytes (may be NULL when the length is 0)
  *   sub, gap      move costs, 0 <= sub, gap <= 2^20, and
@@ -384,8 +394,11 @@ dtw_status dtw_edit_workspace_size(int64_t M, int64_t N, int32_t leaf_rows, size
  *                 (M, N) in path order
  *   path_cap      capacity in nodes, >= M + N + 1
  *   path_len_out  device, 1 int64: node count (0 after a device-side error)
+ *   stats         host, may be NULL; when set, HIP events bracket every sweep
+ *                 launch and the call, and the call synchronises `stream`
  *   stream        hipStream_t or NULL
- * 0 <= M, N <= 2^30.  Stream-ordered: returns before the work completes.
+ * 0 <= M, N <= 2^30.  Stream-ordered: returns before the work completes
+ * (unless stats is set).
  * The caller owns every buffer; the call allocates no device memory.  Errors
  * before any work is enqueued: DTW_ERR_INVALID_ARG (sizes, costs, leaf_rows,
  * null pointers), DTW_ERR_CAPACITY, DTW_ERR_WORKSPACE; DTW_ERR_HIP when a
@@ -393,7 +406,7 @@ dtw_status dtw_edit_workspace_size(int64_t M, int64_t N, int32_t leaf_rows, size
 dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t N, int32_t sub,
                           int32_t gap, int32_t leaf_rows, void* workspace, size_t ws_bytes,
                           int64_t* dist_out, int32_t* path_out, int64_t path_cap,
-                          int64_t* path_len_out, void* stream);
+                          int64_t* path_len_out, dtw_edit_stats* stats, void* stream);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "dtw.h"
 #include "dtw_internal.h"
@@ -29,13 +30,18 @@
 namespace dtw {
 namespace edit {
 
-constexpr int kR = 4;                     // DP rows per lane in a sweep stripe
+#ifndef ED_ROWS_PER_LANE
+#define ED_ROWS_PER_LANE 4
+#endif
+constexpr int kR = ED_ROWS_PER_LANE;      // DP rows per lane in a sweep stripe
+
 constexpr int kStripeRows = kWave * kR;   // rows per sweep stripe
 constexpr int kPh = 64;                   // steps per phase: one staged column per lane
 constexpr uint32_t kBig = 1u << 30;       // above every distance: "no path"
 constexpr int kMaxLevels = 40;
 constexpr int kTile = 1024;               // path-assembly nodes per workgroup
 constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
 
 enum : int32_t { kEdErrSpin = 1, kEdErrBlock = 2, kEdErrMismatch = 3 };
 
@@ -44,6 +50,8 @@ struct Ctl {
   int32_t pad;
   uint64_t dist_leaves;    // sum of the leaves' end values = cost of the returned path
   int64_t dist_split;      // least F + B of the top split (-1 without a split)
+  uint64_t sweep_cells;    // cells evaluated by the sweeps
+  uint64_t leaf_cells;     // cells of the leaf tables
   int32_t ticket[kMaxLevels];
 };
 
@@ -68,6 +76,11 @@ struct Args {
 __device__ __forceinline__ uint32_t shr1(uint32_t old, uint32_t v) {
   // lane l takes lane l-1's v; lane 0 keeps `old`
   return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, kDppWaveShr1, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t shl1(uint32_t old, uint32_t v) {
+  // lane l takes lane l+1's v; lane 63 keeps `old`
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, kDppWaveShl1, 0xf, 0xf, false);
 }
 
 __device__ __forceinline__ int64_t row_at(int64_t k, int64_t M, int L) { return (k * M) >> L; }
@@ -111,8 +124,8 @@ __device__ __forceinline__ uint64_t poll_cell(const uint64_t* p, uint32_t tag, c
 // c = t - l + 1 of all four: the top row takes the row above from lane l-1
 // (DPP wave_shr:1; lane 0 from the staged row above the stripe), the others
 // from the row just updated in the same lane.  The column's letter travels
-// down the wave the same way.  Lanes left of column 1 hold values that are at
-// least kBig except the column-0 boundary, which they reach exactly.
+// down the wave the same way.  Cells left of column 1 hold values of at least
+// kBig except the column-0 boundary, which every row reaches exactly.
 //
 // Rows above the stripe come from the previous stripe through ring cells
 // (value | writer id << 32), staged one phase (64 steps) ahead into LDS; the
@@ -120,7 +133,7 @@ __device__ __forceinline__ uint64_t poll_cell(const uint64_t* p, uint32_t tag, c
 // stripe, to the level's F or B row.
 template <bool kFullOut>
 __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_str, int64_t i0, int64_t i1,
-                             int h, int j0, int w, uint2* feed, uint32_t* obuf) {
+                             int h, int j0, int w, uint2* feed) {
   const int lane = threadIdx.x;
   const uint32_t gap = g.gap, sub = g.sub;
   const int base = s * kStripeRows;
@@ -130,11 +143,11 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
     const int r = base + kR * lane + q + 1;
     x[q] = r <= h ? (uint32_t)(dir ? g.a[i1 - r] : g.a[i0 + r - 1]) : 0u;
   }
+  // v: each row's value of the previous step; u0: the row above row 0, one column back
   uint32_t v[kR];
-  uint32_t u0;
 #pragma unroll
   for (int q = 0; q < kR; ++q) v[q] = lane == 0 ? (uint32_t)(base + q + 1) * gap : kBig;
-  u0 = lane == 0 ? (uint32_t)base * gap : kBig;
+  uint32_t u0 = lane == 0 ? (uint32_t)base * gap : kBig;
 
   const int64_t region = 4 * ((int64_t)j0 + k);
   const uint64_t* rin = g.ring + region + (int64_t)(2 * dir + ((s + 1) & 1)) * (w + 1);
@@ -166,11 +179,11 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
     feed[(p * kPh + lane) & (2 * kPh - 1)] = make_uint2(top, ch);
   };
 
-  const int T = w + kWave - 1;  // lane 63 reaches column w at step w + 62
-  const int n_ph = (T + kPh - 1) / kPh;
   const int hl = min(h - base, kStripeRows);
-  const int lo = kFullOut ? kWave - 1 : (hl - 1) / kR;
+  const int lo = kFullOut ? kWave - 1 : (hl - 1) / kR;  // the stripe's last row: lane lo, row qo
   const int qo = kFullOut ? kR - 1 : (hl - 1) % kR;
+  const int T = w + lo;  // that row reaches column w at step T - 1
+  const int n_ph = (T + kPh - 1) / kPh;
   const bool last = s == n_str - 1;
   uint32_t* orow = (dir ? g.brow : g.frow) + (int64_t)j0 + k;
 
@@ -179,8 +192,7 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
   load_feed(0, cell, ch);
   store_feed(0, cell, ch);
   __builtin_amdgcn_wave_barrier();
-  uint32_t ych = 0;
-  const bool is_lo = lane == lo;
+  uint32_t ych = 0, acc = 0;
   for (int p = 0; p < n_ph; ++p) {
     const bool more = p + 1 < n_ph;
     if (more) load_feed(p + 1, cell, ch);
@@ -200,16 +212,17 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
         up = nv;
       }
       u0 = up0;
+      // the last row's value of this step enters at lane 63 and moves one lane
+      // down per step: after the phase, lane i holds step 64p + i's
       uint32_t vo = v[kR - 1];
       if (!kFullOut) {
 #pragma unroll
         for (int q = 0; q < kR - 1; ++q) vo = qo == q ? v[q] : vo;
+        vo = (uint32_t)__builtin_amdgcn_readlane((int)vo, lo);
       }
-      if (is_lo) obuf[i] = vo;  // the bottom row's value of this step
+      acc = shl1(vo, acc);
     }
-    __builtin_amdgcn_wave_barrier();
-    // lane i publishes the bottom row's value of step 64p + i: column 64p + i - lo + 1
-    const uint32_t outv = obuf[lane];
+    const uint32_t outv = acc;
     const int c = p * kPh + lane - lo + 1;
     if (c >= 1 && c <= w) {
       if (last)
@@ -228,7 +241,6 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
 // one that has not started.
 __global__ __launch_bounds__(kWave) void ed_sweep_kernel(Args g, int L, int n_sweeps, int max_str) {
   __shared__ uint2 feed[2 * kPh];
-  __shared__ uint32_t obuf[kPh];
   const int64_t n_tk = (int64_t)n_sweeps * max_str;
   for (;;) {
     int t = 0;
@@ -247,9 +259,9 @@ __global__ __launch_bounds__(kWave) void ed_sweep_kernel(Args g, int L, int n_sw
       continue;
     }
     if (h - s * kStripeRows >= kStripeRows)
-      sweep_stripe<true>(g, L, k, dir, s, n_str, i0, i1, h, bj.x, bj.y - bj.x, feed, obuf);
+      sweep_stripe<true>(g, L, k, dir, s, n_str, i0, i1, h, bj.x, bj.y - bj.x, feed);
     else
-      sweep_stripe<false>(g, L, k, dir, s, n_str, i0, i1, h, bj.x, bj.y - bj.x, feed, obuf);
+      sweep_stripe<false>(g, L, k, dir, s, n_str, i0, i1, h, bj.x, bj.y - bj.x, feed);
   }
 }
 
@@ -279,6 +291,9 @@ __global__ __launch_bounds__(256) void ed_split_kernel(Args g, int L) {
     nb[2 * k + 1] = make_int2(js, ok ? bj.y : 0);
     if (!ok) set_err(g.ctl, kEdErrBlock);
     if (L == 0) g.ctl->dist_split = ok ? (int64_t)(best >> 32) : -1;
+    // both half sweeps of the block: (i1 - i0) rows of w columns
+    const uint64_t rows = (uint64_t)(row_at(k + 1, g.M, L) - row_at(k, g.M, L));
+    __hip_atomic_fetch_add(&g.ctl->sweep_cells, rows * (uint64_t)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -345,7 +360,10 @@ __global__ __launch_bounds__(kWave) void ed_leaf_kernel(Args g) {
   }
   if ((T & 15) != 0 && lane < 4 * (T & 15)) msk[4 * (int64_t)(T & ~15) + lane] = mreg;
   const uint32_t endv = h >= 1 ? (uint32_t)__builtin_amdgcn_readlane((int)v, h - 1) : (uint32_t)w * gap;
-  if (lane == 0) __hip_atomic_fetch_add(&g.ctl->dist_leaves, (uint64_t)endv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0) {
+    __hip_atomic_fetch_add(&g.ctl->dist_leaves, (uint64_t)endv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&g.ctl->leaf_cells, (uint64_t)h * (uint64_t)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __threadfence();  // the masks this wave stored are read back below
 
   int r = h, c = w, cb = -kWave;
@@ -466,6 +484,8 @@ __global__ __launch_bounds__(256) void ed_init_kernel(Args g, int64_t ring_cells
       g.ctl->error = 0;
       g.ctl->dist_leaves = 0;
       g.ctl->dist_split = -1;
+      g.ctl->sweep_cells = 0;
+      g.ctl->leaf_cells = 0;
       g.blocks[0] = make_int2(0, (int)g.N);
     }
   }
@@ -547,7 +567,8 @@ dtw_status dtw_edit_workspace_size(int64_t M, int64_t N, int32_t leaf_rows, size
 
 dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t N, int32_t sub, int32_t gap,
                           int32_t leaf_rows, void* workspace, size_t ws_bytes, int64_t* dist_out,
-                          int32_t* path_out, int64_t path_cap, int64_t* path_len_out, void* stream) {
+                          int32_t* path_out, int64_t path_cap, int64_t* path_len_out, dtw_edit_stats* stats,
+                          void* stream) {
   const dtw_status st = check_sizes(M, N, sub, gap, leaf_rows);
   if (st != DTW_OK) return st;
   if ((M > 0 && !a) || (N > 0 && !b) || !workspace || !dist_out || !path_out || !path_len_out)
@@ -576,6 +597,20 @@ dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t
   g.spin_ticks = (uint64_t)std::max<int64_t>(1, wall_ticks_per_ms()) * 20000;  // 20 s
   const int cus = std::max(1, device_cus());
 
+  // with stats: events around every sweep launch (on `stream`) and around the call
+  std::vector<hipEvent_t> ev;
+  if (stats) {
+    ev.resize(2 * y.levels + 2);
+    for (auto& e : ev) ED_TRY(hipEventCreate(&e));
+    ED_TRY(hipEventRecord(ev[2 * y.levels], s));
+  }
+  struct EventGuard {
+    std::vector<hipEvent_t>& v;
+    ~EventGuard() {
+      for (auto e : v)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } guard{ev};
   const int64_t init_work = std::max(y.ring_cells, y.nodes);
   const int init_grid = (int)std::min<int64_t>(4 * cus, std::max<int64_t>(1, (init_work + 255) / 256));
   hipLaunchKernelGGL(ed_init_kernel, dim3(init_grid), dim3(256), 0, s, g, y.ring_cells, y.nodes);
@@ -586,8 +621,10 @@ dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t
     const int n_sweeps = 2 << L;
     const int64_t n_tk = (int64_t)n_sweeps * max_str;
     const int grid = (int)std::min<int64_t>(n_tk, (int64_t)cus * 32);
+    if (stats) ED_TRY(hipEventRecord(ev[2 * L], s));
     hipLaunchKernelGGL(ed_sweep_kernel, dim3(grid), dim3(kWave), 0, s, g, L, n_sweeps, max_str);
     ED_TRY(hipGetLastError());
+    if (stats) ED_TRY(hipEventRecord(ev[2 * L + 1], s));
     hipLaunchKernelGGL(ed_split_kernel, dim3(1 << L), dim3(256), 0, s, g, L);
     ED_TRY(hipGetLastError());
   }
@@ -598,6 +635,26 @@ dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t
   hipLaunchKernelGGL(ed_emit_kernel, dim3((unsigned)y.tiles), dim3(256), 0, s, g, y.nodes, (int)y.tiles, path_out,
                      path_len_out, dist_out);
   ED_TRY(hipGetLastError());
+  if (stats) {
+    ED_TRY(hipEventRecord(ev[2 * y.levels + 1], s));
+    edit::Ctl c{};
+    ED_TRY(hipMemcpyAsync(&c, g.ctl, sizeof c, hipMemcpyDeviceToHost, s));
+    ED_TRY(hipStreamSynchronize(s));
+    double sw = 0;
+    for (int L = 0; L < y.levels; ++L) {
+      float ms = 0;
+      ED_TRY(hipEventElapsedTime(&ms, ev[2 * L], ev[2 * L + 1]));
+      sw += ms;
+    }
+    float tot = 0;
+    ED_TRY(hipEventElapsedTime(&tot, ev[2 * y.levels], ev[2 * y.levels + 1]));
+    stats->levels = y.levels;
+    stats->device_error = c.error != 0 ? c.error : (y.levels > 0 && c.dist_split != (int64_t)c.dist_leaves ? kEdErrMismatch : 0);
+    stats->sweep_cells = (int64_t)c.sweep_cells;
+    stats->leaf_cells = (int64_t)c.leaf_cells;
+    stats->sweep_ms = sw;
+    stats->total_ms = tot;
+  }
   return DTW_OK;
 }
 

@@ -95,7 +95,8 @@ def lib():
         L.dtw_align_batched.restype = i32
         L.dtw_edit_workspace_size.argtypes = [i64, i64, i32, ctypes.POINTER(sz)]
         L.dtw_edit_workspace_size.restype = i32
-        L.dtw_edit_align.argtypes = [vp, i64, vp, i64, i32, i32, i32, vp, sz, vp, vp, i64, vp, vp]
+        L.dtw_edit_align.argtypes = [vp, i64, vp, i64, i32, i32, i32, vp, sz, vp, vp, i64, vp,
+                                     ctypes.POINTER(EditStats), vp]
         L.dtw_edit_align.restype = i32
         _lib = L
     return _lib
@@ -448,6 +449,14 @@ def edit_workspace_size(M, N, leaf_rows=64):
     return n.value
 
 
+class EditStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("device_error", ctypes.c_int32), ("sweep_cells", ctypes.c_int64),
+                ("leaf_cells", ctypes.c_int64), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class EditAligner:
     """Reusable workspace and outputs for edit-distance alignments of strings
     of at most M and N bytes (dtw_edit_align)."""
@@ -460,20 +469,24 @@ class EditAligner:
         self.path = torch.empty((self.M + self.N + 1, 2), dtype=torch.int32, device=device)
         self.plen = torch.empty(1, dtype=torch.int64, device=device)
 
-    def run(self, a, b, sub=1, gap=1, stream=None):
-        """Enqueue one alignment of device uint8 tensors a (M) and b (N)."""
+    def run(self, a, b, sub=1, gap=1, stream=None, stats=False):
+        """Enqueue one alignment of device uint8 tensors a (M) and b (N).  With
+        stats=True the call synchronises and returns the stats dict."""
         for t in (a, b):
             if t.dtype != torch.uint8 or t.dim() != 1 or not t.is_cuda or not t.is_contiguous():
                 raise ValueError("a and b must be contiguous 1-D uint8 device tensors")
         M, N = a.shape[0], b.shape[0]
+        st = EditStats()
         if (M, N) != (self.M, self.N):
             raise ValueError(f"sized for {self.M} x {self.N}, got {M} x {N}")
         _check(lib().dtw_edit_align(ctypes.c_void_p(a.data_ptr() if M else 0), M,
                                     ctypes.c_void_p(b.data_ptr() if N else 0), N, int(sub), int(gap),
                                     self.leaf_rows, ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
                                     ctypes.c_void_p(self.dist.data_ptr()), ctypes.c_void_p(self.path.data_ptr()),
-                                    self.path.shape[0], ctypes.c_void_p(self.plen.data_ptr()), _stream_ptr(stream)),
+                                    self.path.shape[0], ctypes.c_void_p(self.plen.data_ptr()),
+                                    ctypes.byref(st) if stats else None, _stream_ptr(stream)),
                "dtw_edit_align")
+        return st.to_dict() if stats else None
 
 
 def edit_align(a, b, sub=1, gap=1, leaf_rows=64, stream=None):

@@ -3,7 +3,8 @@
 // against the thread-based HIP stand-in, one OS thread per lane; blocks of a
 // launch run one after another.
 //   input : int64 M, N; int32 sub, gap, leaf_rows, pad; M bytes a; N bytes b
-//   output: int32 status, levels; int64 dist, len; len x 2 int32
+//   output: int32 status, levels; int64 dist, len, sweep cells, leaf cells;
+//           len x 2 int32
 #include <barrier>
 #include <cstdio>
 #include <cstdlib>
@@ -60,14 +61,17 @@ int main(int argc, char** argv) {
   std::vector<unsigned char> W(rc == 0 ? ws : 1);
   std::vector<int32_t> path(2 * (M + N + 1));
   int64_t dist = 0, len = 0;
+  dtw_edit_stats st{};
   if (rc == 0)
     rc = dtw_edit_align(M ? a.data() : nullptr, M, N ? b.data() : nullptr, N, p[0], p[1], p[2], W.data(), ws, &dist,
-                        path.data(), M + N + 1, &len, nullptr);
+                        path.data(), M + N + 1, &len, &st, nullptr);
   FILE* g = std::fopen(argv[2], "wb");
-  int32_t hdr[2] = {rc, dtw::edit::split_levels(M, p[2] < 2 ? 2 : p[2])};
+  int32_t hdr[2] = {rc, st.levels};
   std::fwrite(hdr, 4, 2, g);
   std::fwrite(&dist, 8, 1, g);
   std::fwrite(&len, 8, 1, g);
+  std::fwrite(&st.sweep_cells, 8, 1, g);
+  std::fwrite(&st.leaf_cells, 8, 1, g);
   if (rc == 0 && len > 0) std::fwrite(path.data(), 4, 2 * len, g);
   std::fclose(g);
   return 0;

@@ -125,6 +125,7 @@ typedef int* hipEvent_t;
 inline hipError_t hipEventCreate(hipEvent_t* e) { static int dummy; *e = &dummy; return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.f; return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
 
 // The model launches the 1024-thread kernels with fewer threads; they tile
 // over blockDim.x, so smaller blocks exercise more tiles.

@@ -40,9 +40,15 @@ inline uint64_t cpu_ballot(bool pred) {
 }
 
 inline int cpu_update_dpp(int old, int src, int ctrl) {
-  if (ctrl != 0x138) std::abort();  // only wave_shr:1 is used
-  const int v = cpu_wave_exchange(src, cpu_lane() - 1);
-  return cpu_lane() == 0 ? old : v;
+  if (ctrl == 0x138) {  // wave_shr:1: lane l takes lane l-1's value, lane 0 keeps old
+    const int v = cpu_wave_exchange(src, cpu_lane() - 1);
+    return cpu_lane() == 0 ? old : v;
+  }
+  if (ctrl == 0x130) {  // wave_shl:1: lane l takes lane l+1's value, lane 63 keeps old
+    const int v = cpu_wave_exchange(src, cpu_lane() + 1);
+    return cpu_lane() == 63 ? old : v;
+  }
+  std::abort();  // no other DPP control is used
 }
 
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) cpu_update_dpp((old), (src), (ctrl))

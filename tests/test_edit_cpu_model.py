@@ -43,9 +43,27 @@ def run_edit_model(exe, a, b, sub, gap, leaf_rows):
         assert r.returncode == 0, r.stderr.decode()[-3000:]
         buf = open(fo, "rb").read()
     rc, levels = struct.unpack_from("2i", buf, 0)
-    dist, n = struct.unpack_from("2q", buf, 8)
-    path = np.frombuffer(buf[24:24 + 8 * n], dtype=np.int32).reshape(-1, 2) if rc == 0 else None
+    dist, n, sweep_cells, leaf_cells = struct.unpack_from("4q", buf, 8)
+    path = np.frombuffer(buf[40:40 + 8 * n], dtype=np.int32).reshape(-1, 2) if rc == 0 else None
+    run_edit_model.cells = (sweep_cells, leaf_cells)
     return rc, levels, dist, path
+
+
+def oracle_cells(M, N, h, pivots):
+    """Sweep and leaf cells implied by the oracle's splits: block k of level L
+    spans rows floor(k M / 2^L) .. floor((k+1) M / 2^L); its half sweeps cover
+    all its rows times its columns, and the blocks of the last level are leaves."""
+    levels = edit.levels(M, h)
+    cols = {(0, 0): (0, N)}
+    sweep = 0
+    for L, k, mid, j in pivots.tolist():
+        j0, j1 = cols[(L, k)]
+        sweep += (((k + 1) * M >> L) - (k * M >> L)) * (j1 - j0)
+        cols[(L + 1, 2 * k)] = (j0, j)
+        cols[(L + 1, 2 * k + 1)] = (j, j1)
+    leaf = sum((((k + 1) * M >> levels) - (k * M >> levels)) * (cols[(levels, k)][1] - cols[(levels, k)][0])
+               for k in range(1 << levels))
+    return sweep, leaf
 
 
 # (M, N, sub, gap, leaf_rows): empty strings, one leaf, leaves of two rows,
@@ -62,7 +80,9 @@ def test_edit_model_equals_oracle(edit_model, M, N, sub, gap, h):
     assert rc == 0
     assert levels == edit.levels(M, h)
     assert dist == edit.full(a, b, sub, gap)[0]
-    assert path.tolist() == edit.linear(a, b, sub, gap, leaf_rows=h)["path"].tolist()
+    r = edit.linear(a, b, sub, gap, leaf_rows=h, pivots=True)
+    assert path.tolist() == r["path"].tolist()
+    assert run_edit_model.cells == oracle_cells(M, N, h, r["pivots"])
 
 
 def test_edit_model_rejects_bad_arguments(edit_model):
