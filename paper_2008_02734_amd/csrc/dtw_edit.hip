@@ -14,7 +14,7 @@
 //
 // Kernels per call: init; per split level a persistent sweep launch (all
 // forward and backward half sweeps of the level, one wave per stripe of 256
-// rows) and a split launch (argmin, child blocks); one leaf launch (full
+// rows, or 128 for M <= 65536) and a split launch (argmin, child blocks); one leaf launch (full
 // table of each block of at most 64 rows as backpointer masks, then the
 // walk back); two path-assembly launches.  Values are uint32 (every
 // distance is below 2^30).
@@ -30,13 +30,17 @@
 namespace dtw {
 namespace edit {
 
-#ifndef ED_ROWS_PER_LANE
-#define ED_ROWS_PER_LANE 4
+// DP rows per lane in a sweep stripe: 4 (256-row stripes) for tall problems,
+// 2 (128-row stripes, twice the stripes and waves) when M <= kSmallM
+#ifndef ED_SMALL_M
+#define ED_SMALL_M 65536
 #endif
-constexpr int kR = ED_ROWS_PER_LANE;      // DP rows per lane in a sweep stripe
+constexpr int64_t kSmallM = ED_SMALL_M;
 
-constexpr int kStripeRows = kWave * kR;   // rows per sweep stripe
-constexpr int kPh = 64;                   // steps per phase: one staged column per lane
+constexpr int kPh = 64;                   // leaf steps per staged letter block
+constexpr int kG = 64;                    // sweep steps per group: one staged column per lane
+static_assert(kG == kWave, "a group stages one column per lane and publishes one per lane");
+constexpr int kFeed = 2 * kG;            // LDS feed slots (by step): the group in use and the next
 constexpr uint32_t kBig = 1u << 30;       // above every distance: "no path"
 constexpr int kMaxLevels = 40;
 constexpr int kTile = 1024;               // path-assembly nodes per workgroup
@@ -117,25 +121,32 @@ __device__ __forceinline__ uint64_t poll_cell(const uint64_t* p, uint32_t tag, c
 
 // ------------------------------------------------------------------ sweeps
 //
-// One stripe of a half sweep: rows base+1 .. base+256 of the swept table
+// One stripe of a half sweep: rows base+1 .. base+64R of the swept table
 // (forward: node rows i0+1 .. mid from the origin (i0, j0); backward: the
 // reversed block from (i1, j1), its row r holding a[i1 - r]).  Lane l owns
-// rows base + 4l + 1 .. base + 4l + 4 and at step t updates column
-// c = t - l + 1 of all four: the top row takes the row above from lane l-1
+// rows base + Rl + 1 .. base + Rl + R and at step t updates column
+// c = t - l + 1 of all R: the top row takes the row above from lane l-1
 // (DPP wave_shr:1; lane 0 from the staged row above the stripe), the others
 // from the row just updated in the same lane.  The column's letter travels
 // down the wave the same way.  Cells left of column 1 hold values of at least
-// kBig except the column-0 boundary, which every row reaches exactly.
+// kBig except the column-0 boundary, which every row reaches exactly.  With
+// unit substitution cost the mismatch is added as a carry (5 VALU operations
+// per cell instead of 6).
 //
 // Rows above the stripe come from the previous stripe through ring cells
-// (value | writer id << 32), staged one phase (64 steps) ahead into LDS; the
-// stripe's own bottom row goes to the other ring row, or, for the last
-// stripe, to the level's F or B row.
-template <bool kFullOut>
+// (value | writer id << 32), staged one group (64 steps) ahead into LDS.  The
+// stripe's last row is collected without branches: each step's value enters
+// lane 63 and shifts one lane down (DPP wave_shl:1), so after a group lane i
+// holds step 64g + i's, and all lanes store them to the other ring row, or,
+// for the last stripe, to the level's F or B row.  (A masked store by the one
+// lane holding the last row put a branch into every step and kept the LDS
+// reads of later steps from being scheduled early.)
+template <int kR, bool kFullOut, bool kUnit>
 __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_str, int64_t i0, int64_t i1,
                              int h, int j0, int w, uint2* feed) {
   const int lane = threadIdx.x;
   const uint32_t gap = g.gap, sub = g.sub;
+  constexpr int kStripeRows = kWave * kR;
   const int base = s * kStripeRows;
   uint32_t x[kR];
 #pragma unroll
@@ -155,9 +166,10 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
   const uint32_t tag_in = cell_tag(L, s - 1), tag_out = cell_tag(L, s);
   const uint8_t* bb = g.b + j0;
 
-  // phase p uses columns 64p + 1 .. 64p + 64 at lane 0; lane i stages column 64p + i + 1
-  auto load_feed = [&](int p, uint64_t& cell, uint32_t& ch) {
-    const int c = p * kPh + lane + 1;
+  // group gi (steps 64 gi .. 64 gi + 63) uses columns 64 gi + 1 .. 64 gi + 64 at
+  // lane 0; lane i stages column 64 gi + i + 1 one group ahead
+  auto load_feed = [&](int gi, uint64_t& cell, uint32_t& ch) {
+    const int c = gi * kG + lane + 1;
     cell = 0;
     ch = 0;
     if (c <= w) {
@@ -165,8 +177,8 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
       if (s > 0) cell = __hip_atomic_load(rin + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
-  auto store_feed = [&](int p, uint64_t cell, uint32_t ch) {
-    const int c = p * kPh + lane + 1;
+  auto store_feed = [&](int gi, uint64_t cell, uint32_t ch) {
+    const int c = gi * kG + lane + 1;
     uint32_t top = kBig;
     if (c <= w) {
       if (s == 0) {
@@ -176,14 +188,14 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
         top = (uint32_t)cell;
       }
     }
-    feed[(p * kPh + lane) & (2 * kPh - 1)] = make_uint2(top, ch);
+    feed[(gi * kG + lane) & (kFeed - 1)] = make_uint2(top, ch);
   };
 
   const int hl = min(h - base, kStripeRows);
   const int lo = kFullOut ? kWave - 1 : (hl - 1) / kR;  // the stripe's last row: lane lo, row qo
   const int qo = kFullOut ? kR - 1 : (hl - 1) % kR;
   const int T = w + lo;  // that row reaches column w at step T - 1
-  const int n_ph = (T + kPh - 1) / kPh;
+  const int n_grp = (T + kG - 1) / kG;
   const bool last = s == n_str - 1;
   uint32_t* orow = (dir ? g.brow : g.frow) + (int64_t)j0 + k;
 
@@ -193,19 +205,20 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
   store_feed(0, cell, ch);
   __builtin_amdgcn_wave_barrier();
   uint32_t ych = 0, acc = 0;
-  for (int p = 0; p < n_ph; ++p) {
-    const bool more = p + 1 < n_ph;
-    if (more) load_feed(p + 1, cell, ch);
-    const uint2* fb = feed + ((p * kPh) & (2 * kPh - 1));
+  for (int gi = 0; gi < n_grp; ++gi) {
+    const bool more = gi + 1 < n_grp;
+    if (more) load_feed(gi + 1, cell, ch);
+    const uint2* fb = feed + ((gi * kG) & (kFeed - 1));
 #pragma unroll
-    for (int i = 0; i < kPh; ++i) {
+    for (int i = 0; i < kG; ++i) {
       const uint2 f = fb[i];
       ych = shr1(f.y, ych);
       const uint32_t up0 = shr1(f.x, v[kR - 1]);
       uint32_t up = up0, dg = u0;
 #pragma unroll
       for (int q = 0; q < kR; ++q) {
-        const uint32_t c = x[q] == ych ? 0u : sub;
+        // unit substitution cost: the mismatch bit is added as a carry
+        const uint32_t c = kUnit ? (uint32_t)(x[q] != ych) : (x[q] == ych ? 0u : sub);
         const uint32_t nv = min(min(up, v[q]) + gap, dg + c);
         dg = v[q];
         v[q] = nv;
@@ -213,7 +226,7 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
       }
       u0 = up0;
       // the last row's value of this step enters at lane 63 and moves one lane
-      // down per step: after the phase, lane i holds step 64p + i's
+      // down per step: after step t, lane l holds step t - 63 + l's
       uint32_t vo = v[kR - 1];
       if (!kFullOut) {
 #pragma unroll
@@ -222,15 +235,17 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
       }
       acc = shl1(vo, acc);
     }
-    const uint32_t outv = acc;
-    const int c = p * kPh + lane - lo + 1;
-    if (c >= 1 && c <= w) {
-      if (last)
-        orow[dir ? w - c : c] = outv;
-      else
-        __hip_atomic_store(rout + c, ((uint64_t)tag_out << 32) | outv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // lane i publishes step 64 gi + i's value: column 64 gi + i - lo + 1
+    {
+      const int c = gi * kG + lane - lo + 1;
+      if (c >= 1 && c <= w) {
+        if (last)
+          orow[dir ? w - c : c] = acc;
+        else
+          __hip_atomic_store(rout + c, ((uint64_t)tag_out << 32) | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    if (more) store_feed(p + 1, cell, ch);
+    if (more) store_feed(gi + 1, cell, ch);
     __builtin_amdgcn_wave_barrier();
   }
   if (last && lane == 0) orow[dir ? w : 0] = (uint32_t)h * gap;  // column 0: h gaps
@@ -239,8 +254,10 @@ __device__ void sweep_stripe(const Args& g, int L, int k, int dir, int s, int n_
 // Tickets are (sweep, stripe) in stripe-major order, so the stripe a ticket
 // waits for was dequeued earlier by a running workgroup: no ticket waits on
 // one that has not started.
+template <int kR>
 __global__ __launch_bounds__(kWave) void ed_sweep_kernel(Args g, int L, int n_sweeps, int max_str) {
-  __shared__ uint2 feed[2 * kPh];
+  constexpr int kStripeRows = kWave * kR;
+  __shared__ uint2 feed[kFeed];
   const int64_t n_tk = (int64_t)n_sweeps * max_str;
   for (;;) {
     int t = 0;
@@ -258,10 +275,19 @@ __global__ __launch_bounds__(kWave) void ed_sweep_kernel(Args g, int L, int n_sw
       if (threadIdx.x == 0) set_err(g.ctl, kEdErrBlock);
       continue;
     }
-    if (h - s * kStripeRows >= kStripeRows)
-      sweep_stripe<true>(g, L, k, dir, s, n_str, i0, i1, h, bj.x, bj.y - bj.x, feed);
-    else
-      sweep_stripe<false>(g, L, k, dir, s, n_str, i0, i1, h, bj.x, bj.y - bj.x, feed);
+    const bool full = h - s * kStripeRows >= kStripeRows;
+    const int j0 = bj.x, w = bj.y - bj.x;
+    if (g.sub == 1) {
+      if (full)
+        sweep_stripe<kR, true, true>(g, L, k, dir, s, n_str, i0, i1, h, j0, w, feed);
+      else
+        sweep_stripe<kR, false, true>(g, L, k, dir, s, n_str, i0, i1, h, j0, w, feed);
+    } else {
+      if (full)
+        sweep_stripe<kR, true, false>(g, L, k, dir, s, n_str, i0, i1, h, j0, w, feed);
+      else
+        sweep_stripe<kR, false, false>(g, L, k, dir, s, n_str, i0, i1, h, j0, w, feed);
+    }
   }
 }
 
@@ -617,12 +643,16 @@ dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t
   ED_TRY(hipGetLastError());
   for (int L = 0; L < y.levels; ++L) {
     const int64_t half = (M + ((int64_t)2 << L) - 1) >> (L + 1);  // ceil(M / 2^(L+1)): tallest half sweep
-    const int max_str = (int)((half + kStripeRows - 1) / kStripeRows);
+    const int rows = kWave * (M <= kSmallM ? 2 : 4);
+    const int max_str = (int)((half + rows - 1) / rows);
     const int n_sweeps = 2 << L;
     const int64_t n_tk = (int64_t)n_sweeps * max_str;
     const int grid = (int)std::min<int64_t>(n_tk, (int64_t)cus * 32);
     if (stats) ED_TRY(hipEventRecord(ev[2 * L], s));
-    hipLaunchKernelGGL(ed_sweep_kernel, dim3(grid), dim3(kWave), 0, s, g, L, n_sweeps, max_str);
+    if (M <= kSmallM)
+      hipLaunchKernelGGL(ed_sweep_kernel<2>, dim3(grid), dim3(kWave), 0, s, g, L, n_sweeps, max_str);
+    else
+      hipLaunchKernelGGL(ed_sweep_kernel<4>, dim3(grid), dim3(kWave), 0, s, g, L, n_sweeps, max_str);
     ED_TRY(hipGetLastError());
     if (stats) ED_TRY(hipEventRecord(ev[2 * L + 1], s));
     hipLaunchKernelGGL(ed_split_kernel, dim3(1 << L), dim3(256), 0, s, g, L);

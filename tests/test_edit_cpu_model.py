@@ -21,14 +21,26 @@ MODEL = os.path.join(ROOT, "tests", "cpu_model")
 CSRC = os.path.join(ROOT, "paper_2008_02734_amd", "csrc")
 
 
-@pytest.fixture(scope="module")
-def edit_model(tmp_path_factory):
-    exe = str(tmp_path_factory.mktemp("edit_model") / "edit_model")
+def _build(d, extra=()):
+    exe = str(d / "edit_model")
     subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-                    "-fno-omit-frame-pointer", "-Wno-unknown-pragmas", "-pthread", "-I", MODEL,
+                    "-fno-omit-frame-pointer", "-Wno-unknown-pragmas", "-pthread", *extra, "-I", MODEL,
                     "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-x", "c++",
                     os.path.join(MODEL, "edit_driver.cpp"), "-o", exe], check=True)
     return exe
+
+
+@pytest.fixture(scope="module")
+def edit_model(tmp_path_factory):
+    # problems up to 65536 rows take 128-row stripes (two rows per lane)
+    return _build(tmp_path_factory.mktemp("edit_model"))
+
+
+@pytest.fixture(scope="module")
+def edit_model_r4(tmp_path_factory):
+    # the 256-row stripes (four rows per lane) of taller problems, forced here
+    # for small ones by lowering the threshold
+    return _build(tmp_path_factory.mktemp("edit_model_r4"), ["-DED_SMALL_M=0"])
 
 
 def run_edit_model(exe, a, b, sub, gap, leaf_rows):
@@ -69,7 +81,7 @@ def oracle_cells(M, N, h, pivots):
 # (M, N, sub, gap, leaf_rows): empty strings, one leaf, leaves of two rows,
 # several levels, and half sweeps of two stripes (more than 256 rows) whose
 # second stripe reads the first one's bottom row through the ring
-CASES = [(0, 5, 1, 1, 2), (5, 0, 1, 1, 2), (1, 1, 1, 1, 2), (7, 9, 1, 1, 2), (40, 33, 1, 1, 3),
+CASES = [(0, 5, 1, 1, 2), (5, 0, 1, 1, 2), (1, 1, 1, 1, 2), (7, 9, 1, 1, 2), (40, 33, 1, 1, 3), (300, 20, 1, 1, 40),
          (600, 90, 3, 2, 64), (90, 300, 1, 1, 5), (530, 41, 0, 1, 40)]
 
 
@@ -83,6 +95,16 @@ def test_edit_model_equals_oracle(edit_model, M, N, sub, gap, h):
     r = edit.linear(a, b, sub, gap, leaf_rows=h, pivots=True)
     assert path.tolist() == r["path"].tolist()
     assert run_edit_model.cells == oracle_cells(M, N, h, r["pivots"])
+
+
+@pytest.mark.parametrize("M,N,sub,gap,h", [(7, 9, 1, 1, 2), (600, 90, 3, 2, 64), (530, 41, 1, 1, 40),
+                                           (300, 20, 1, 1, 40)])
+def test_edit_model_four_rows_per_lane(edit_model_r4, M, N, sub, gap, h):
+    a, b = synth.string_pair(8100 + M + N, M, N, k=4, p=0.2)
+    rc, levels, dist, path = run_edit_model(edit_model_r4, a, b, sub, gap, h)
+    assert rc == 0
+    assert dist == edit.full(a, b, sub, gap)[0]
+    assert path.tolist() == edit.linear(a, b, sub, gap, leaf_rows=h)["path"].tolist()
 
 
 def test_edit_model_rejects_bad_arguments(edit_model):
