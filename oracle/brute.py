@@ -167,3 +167,30 @@ def brute_lcs(a, b):
             if is_subseq([a[i] for i in idx], b):
                 return k
     return 0
+
+
+def brute_local(a, b, match=2, mismatch=1, gap=1):
+    """Smith-Waterman by enumeration: the best score of a global alignment
+    (every lattice path) of every pair of substrings a[i0:i1], b[j0:j1],
+    M, N <= 5, and the end (i1, j1) of the first best pair in row-major order
+    of the end cell ((0, 0) for score 0; an empty pair scores 0)."""
+    M, N = len(a), len(b)
+    if M > 5 or N > 5:
+        raise ValueError("brute force is limited to M, N <= 5")
+    best, end = 0, (0, 0)
+    for i1 in range(1, M + 1):
+        for j1 in range(1, N + 1):
+            for i0 in range(i1):
+                for j0 in range(j1):
+                    sa, sb = a[i0:i1], b[j0:j1]
+                    for p in enumerate_paths(len(sa) + 1, len(sb) + 1):
+                        s = 0
+                        for q in range(1, len(p)):
+                            (i, j), (pi, pj) = p[q], p[q - 1]
+                            if (i - pi, j - pj) == (1, 1):
+                                s += match if sa[i - 1] == sb[j - 1] else -mismatch
+                            else:
+                                s -= gap
+                        if s > best:
+                            best, end = s, (i1, j1)
+    return best, end

@@ -62,6 +62,8 @@ def load(path: str):
     L.edo_levels.argtypes = [i64, i32]
     L.edo_linear.restype = ctypes.c_int
     L.edo_linear.argtypes = [u8, i64, u8, i64, i32, i32, i32, lp, ip, lp, lp, i64, lp]
+    L.edo_local_score.restype = ctypes.c_int
+    L.edo_local_score.argtypes = [u8, i64, u8, i64, i32, i32, i32, lp, lp, lp]
     L.edo_path_cost.restype = i64
     L.edo_path_cost.argtypes = [u8, i64, u8, i64, i32, i32, ip, i64]
     return L
@@ -155,3 +157,15 @@ def path_cost(a, b, path, sub: int = 1, gap: int = 1, L=None) -> int:
     p = np.ascontiguousarray(np.asarray(path, dtype=np.int32))
     return int(L.edo_path_cost(_p(a, ctypes.c_uint8), a.size, _p(b, ctypes.c_uint8), b.size, sub, gap,
                                _p(p, ctypes.c_int32), p.shape[0]))
+
+
+def local_score(a, b, match=2, mismatch=1, gap=1, L=None):
+    """Smith-Waterman: (best local score, i_end, j_end), the end cell the first
+    maximum of the table in row-major order ((0, 0) when the score is 0)."""
+    L = L or lib()
+    a, b = _u8(a), _u8(b)
+    sc, ie, je = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    if L.edo_local_score(_p(a, ctypes.c_uint8), a.size, _p(b, ctypes.c_uint8), b.size, match, mismatch, gap,
+                         ctypes.byref(sc), ctypes.byref(ie), ctypes.byref(je)):
+        raise MemoryError("edo_local_score")
+    return int(sc.value), int(ie.value), int(je.value)

@@ -258,3 +258,43 @@ int64_t edo_path_cost(const uint8_t* a, int64_t M, const uint8_t* b, int64_t N, 
   }
   return s;
 }
+
+/*
+ * Local alignment (Smith-Waterman), the other problem Sec. 6 names: the best
+ * score over all pairs of substrings, a match scoring +match, a mismatch
+ * -mismatch, every gap letter -gap.  Table H[0][j] = H[i][0] = 0,
+ * H[i][j] = max(0, H[i-1][j-1] + s, H[i-1][j] - gap, H[i][j-1] - gap).  The
+ * end cell is the first cell holding the maximum in row-major order ((0,0)
+ * when the maximum is 0).  Returns 0, or -1 when memory runs out.
+ */
+int edo_local_score(const uint8_t* a, int64_t M, const uint8_t* b, int64_t N, int32_t match, int32_t mismatch,
+                    int32_t gap, int64_t* score, int64_t* i_end, int64_t* j_end) {
+  int64_t* row = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N + 1));
+  if (!row) return -1;
+  for (int64_t j = 0; j <= N; ++j) row[j] = 0;
+  int64_t best = 0, bi = 0, bj = 0;
+  for (int64_t i = 1; i <= M; ++i) {
+    int64_t diag = row[0];
+    row[0] = 0;
+    for (int64_t j = 1; j <= N; ++j) {
+      const int64_t s = a[i - 1] == b[j - 1] ? match : -(int64_t)mismatch;
+      int64_t h = diag + s;
+      const int64_t up = row[j] - gap, lf = row[j - 1] - gap;
+      if (up > h) h = up;
+      if (lf > h) h = lf;
+      if (h < 0) h = 0;
+      diag = row[j];
+      row[j] = h;
+      if (h > best) {
+        best = h;
+        bi = i;
+        bj = j;
+      }
+    }
+  }
+  free(row);
+  *score = best;
+  *i_end = bi;
+  *j_end = bj;
+  return 0;
+}

@@ -168,6 +168,61 @@ def test_pivots_lie_on_optimal_paths():
         assert len(r["pivots"]) == 2 ** edit.levels(300, 4) - 1
 
 
+# ------------------------------------------------------------------ local alignment (Smith-Waterman)
+
+LOCAL_SCORES = [(2, 1, 1), (1, 1, 1), (3, 2, 2), (1, 3, 1), (2, 0, 0), (5, 1, 3)]
+
+
+@pytest.mark.parametrize("match,mismatch,gap", LOCAL_SCORES)
+def test_local_score_equals_brute_force(match, mismatch, gap):
+    # every size up to 5 x 5 on 2- and 3-letter alphabets: the best score over
+    # all substring pairs and all their alignments, and its first end cell
+    from oracle.brute import brute_local
+    for M in range(0, 6):
+        for N in range(0, 6):
+            for k in (2, 3):
+                a, b = _rand(700 + 100 * M + 10 * N + k, M, N, k)
+                sc, i, j = edit.local_score(a, b, match, mismatch, gap)
+                bs, (bi, bj) = brute_local(a.tolist(), b.tolist(), match, mismatch, gap)
+                assert (sc, i, j) == (bs, bi, bj)
+
+
+def test_local_score_closed_forms():
+    a, _ = _rand(21, 57, 1, 4)
+    for match, mismatch, gap in LOCAL_SCORES:
+        # a string against itself: every letter matched, ending at (M, M)
+        assert edit.local_score(a, a, match, mismatch, gap) == (match * 57, 57, 57)
+        # no common letter: nothing scores above 0
+        assert edit.local_score(np.full(9, 1, np.uint8), np.full(12, 2, np.uint8), match, mismatch, gap) == (0, 0, 0)
+        assert edit.local_score(a, b"", match, mismatch, gap) == (0, 0, 0)
+        # one common letter at the end of both: a single match
+        x = np.array([1, 1, 1, 3], np.uint8)
+        y = np.array([2, 2, 3], np.uint8)
+        assert edit.local_score(x, y, match, mismatch, gap) == (match, 4, 3)
+        # a planted common substring in unrelated text scores at least its matches
+        p = np.arange(40, 40 + 30, dtype=np.uint8)
+        u = np.concatenate([np.full(50, 1, np.uint8), p, np.full(20, 2, np.uint8)])
+        w = np.concatenate([np.full(35, 3, np.uint8), p, np.full(10, 4, np.uint8)])
+        assert edit.local_score(u, w, match, mismatch, gap) == (30 * match, 80, 65)
+
+
+def test_local_score_symmetry_and_global_bound():
+    # the score is symmetric in a and b, and at least the global alignment
+    # score of the whole strings: with m, x, g the match score and the two
+    # penalties, 2 x global score = m (M + N) - d, d the edit distance with
+    # sub = 2 (m + x) and gap = 2 g + m (matches + mismatches + gaps/2 = (M+N)/2)
+    for s in range(30):
+        rng = np.random.default_rng([16, s])
+        M, N = (int(v) for v in rng.integers(0, 60, 2))
+        a, b = synth.string_pair(7000 + s, M, N, k=4, p=0.3)
+        for m, x, g in ((2, 1, 1), (3, 2, 2)):
+            sc, i, j = edit.local_score(a, b, m, x, g)
+            assert sc == edit.local_score(b, a, m, x, g)[0]
+            d = edit.full(a, b, 2 * (m + x), 2 * g + m)[0]
+            assert 2 * sc >= m * (M + N) - d
+            assert sc >= 0 and 0 <= i <= M and 0 <= j <= N
+
+
 # ------------------------------------------------------------------ planted mistakes
 
 MUTANTS = {
@@ -184,6 +239,10 @@ MUTANTS = {
                               "const uint8_t x = a[i0 + r - 1];"),
     "split_forward_only": ("const int64_t s = c->F[j - j0] + c->B[j - j0];", "const int64_t s = c->F[j - j0];"),
     "leaf_node_duplicated": ("c->n += c->n > 0 ? m - 1 : m;", "c->n += m;"),
+    "local_no_floor_at_zero": ("      if (h < 0) h = 0;\n", "      if (h < -1000000) h = 0;\n"),
+    "local_mismatch_added": ("const int64_t s = a[i - 1] == b[j - 1] ? match : -(int64_t)mismatch;",
+                             "const int64_t s = a[i - 1] == b[j - 1] ? match : (int64_t)mismatch;"),
+    "local_end_last_maximum": ("      if (h > best) {\n        best = h;", "      if (h >= best && h > 0) {\n        best = h;"),
     "reversed_row_not_flipped": ("for (int64_t p = 0, q = W; p < q; ++p, --q) {\n      int64_t t = row[p];",
                                  "for (int64_t p = 0, q = -1; p < q; ++p, --q) {\n      int64_t t = row[p];"),
 }
@@ -219,6 +278,20 @@ CHECKS = textwrap.dedent(r'''
                   and edit.path_cost(a, b, r["path"], sub, gap, L=L) == d)
             rr = edit.row(a, b, 5, 3, 40, 50, sub, gap, rev=True, L=L)
             check("row_rev", rr.tolist() == [edit.full(a[5:40], b[j:50], sub, gap, L=L)[0] for j in range(3, 51)])
+    from oracle.brute import brute_local
+    for s in range(40):
+        rng = np.random.default_rng([17, s])
+        M, N = int(rng.integers(0, 6)), int(rng.integers(0, 6))
+        a = rng.integers(0, 3, M).astype(np.uint8); b = rng.integers(0, 3, N).astype(np.uint8)
+        for m, x, gp in ((2, 1, 1), (1, 3, 1)):
+            bs, (bi, bj) = brute_local(a.tolist(), b.tolist(), m, x, gp)
+            check("local_brute", edit.local_score(a, b, m, x, gp, L=L) == (bs, bi, bj))
+    # a common substring after unrelated text: the best alignment starts where
+    # every earlier cell has fallen to zero
+    p = np.arange(40, 70, dtype=np.uint8)
+    u = np.concatenate([np.full(50, 1, np.uint8), p, np.full(20, 2, np.uint8)])
+    w = np.concatenate([np.full(35, 3, np.uint8), p, np.full(10, 4, np.uint8)])
+    check("local_planted", edit.local_score(u, w, 2, 1, 1, L=L) == (60, 80, 65))
     print(json.dumps(fails))
 ''')
 
