@@ -408,6 +408,31 @@ dtw_status dtw_edit_align(const uint8_t* a, int64_t M, const uint8_t* b, int64_t
                           int64_t* dist_out, int32_t* path_out, int64_t path_cap,
                           int64_t* path_len_out, dtw_edit_stats* stats, void* stream);
 
+/* Local alignment score (Smith-Waterman), the other problem Sec. 6 names:
+ * the best score over all pairs of substrings, H[0][j] = H[i][0] = 0,
+ * H[i][j] = max(0, H[i-1][j-1] + s, H[i-1][j] - gap, H[i][j-1] - gap) with
+ * s = +match on equal letters and -mismatch otherwise, and the end of a best
+ * local alignment: the first cell holding the maximum in row-major order,
+ * (0, 0) when the maximum is 0.  Working memory O(N) (two boundary rows and
+ * one record per 256 rows of a).
+ *   a, b        device, M and N bytes (may be NULL when the length is 0)
+ *   match       1 .. 2^20 and (min(M, N) + 1) * match < 2^30
+ *   mismatch, gap  0 .. 2^20 (penalties)
+ *   workspace   device, at least dtw_local_workspace_size() bytes, any contents
+ *   out         device, 3 int64: score, i_end, j_end (the end cell is the node
+ *               after the last aligned letters: a[i_end - 1] and b[j_end - 1]);
+ *               a negative score -1 after a boundary wait expired
+ *   stream      hipStream_t or NULL; stream-ordered, allocates nothing
+ * Errors before any work: DTW_ERR_INVALID_ARG, DTW_ERR_WORKSPACE; DTW_ERR_HIP
+ * when a launch fails.  Calls that share a workspace must not overlap.
+ * In this build dtw_local_score returns DTW_ERR_UNSUPPORTED after checking its
+ * arguments: the device launch is switched off (its first launch did not
+ * finish on the device; the cause is not yet found). */
+dtw_status dtw_local_workspace_size(int64_t M, int64_t N, size_t* bytes);
+dtw_status dtw_local_score(const uint8_t* a, int64_t M, const uint8_t* b, int64_t N, int32_t match,
+                           int32_t mismatch, int32_t gap, void* workspace, size_t ws_bytes,
+                           int64_t* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

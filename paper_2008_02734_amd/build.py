@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdtw_hip.so")
-SOURCES = ["dtw_wave.hip", "dtw_plan.hip", "dtw_api.hip", "dtw_server.hip", "dtw_edit.hip"]
+SOURCES = ["dtw_wave.hip", "dtw_plan.hip", "dtw_api.hip", "dtw_server.hip", "dtw_edit.hip", "dtw_local.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",

@@ -98,6 +98,10 @@ def lib():
         L.dtw_edit_align.argtypes = [vp, i64, vp, i64, i32, i32, i32, vp, sz, vp, vp, i64, vp,
                                      ctypes.POINTER(EditStats), vp]
         L.dtw_edit_align.restype = i32
+        L.dtw_local_workspace_size.argtypes = [i64, i64, ctypes.POINTER(sz)]
+        L.dtw_local_workspace_size.restype = i32
+        L.dtw_local_score.argtypes = [vp, i64, vp, i64, i32, i32, i32, vp, sz, vp, vp]
+        L.dtw_local_score.restype = i32
         _lib = L
     return _lib
 
@@ -502,3 +506,40 @@ def edit_align(a, b, sub=1, gap=1, leaf_rows=64, stream=None):
     if d < 0:
         raise DeviceError(-d, "dtw_edit_align")
     return d, al.path[:n]
+
+
+# ----------------------------------------------------------------- local alignment score
+
+class LocalScorer:
+    """Reusable workspace and output for Smith-Waterman scores of strings of M
+    and N bytes (dtw_local_score)."""
+
+    def __init__(self, M, N, device="cuda"):
+        self.M, self.N = int(M), int(N)
+        n = ctypes.c_size_t()
+        _check(lib().dtw_local_workspace_size(self.M, self.N, ctypes.byref(n)), "dtw_local_workspace_size")
+        self.ws_bytes = n.value
+        self.ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=device)
+        self.out = torch.empty(3, dtype=torch.int64, device=device)
+
+    def run(self, a, b, match=2, mismatch=1, gap=1, stream=None):
+        for t in (a, b):
+            if t.dtype != torch.uint8 or t.dim() != 1 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("a and b must be contiguous 1-D uint8 device tensors")
+        if (a.shape[0], b.shape[0]) != (self.M, self.N):
+            raise ValueError(f"sized for {self.M} x {self.N}, got {a.shape[0]} x {b.shape[0]}")
+        _check(lib().dtw_local_score(ctypes.c_void_p(a.data_ptr() if self.M else 0), self.M,
+                                     ctypes.c_void_p(b.data_ptr() if self.N else 0), self.N, int(match),
+                                     int(mismatch), int(gap), ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                     ctypes.c_void_p(self.out.data_ptr()), _stream_ptr(stream)), "dtw_local_score")
+
+
+def local_score(a, b, match=2, mismatch=1, gap=1, stream=None):
+    """Smith-Waterman score of device uint8 tensors a and b and the end cell of
+    a best local alignment: (score, i_end, j_end).  Synchronises the stream."""
+    sc = LocalScorer(a.shape[0], b.shape[0], device=a.device)
+    sc.run(a, b, match, mismatch, gap, stream)
+    s, i, j = (int(v) for v in sc.out.cpu().tolist())
+    if s < 0:
+        raise DeviceError(-s, "dtw_local_score")
+    return s, i, j

@@ -2,7 +2,9 @@
 // (dtw_edit.hip, kernels and host entry points) compiled for the host
 // against the thread-based HIP stand-in, one OS thread per lane; blocks of a
 // launch run one after another.
-//   input : int64 M, N; int32 sub, gap, leaf_rows, pad; M bytes a; N bytes b
+//   input : int64 M, N; int32 sub, gap, leaf_rows, mode; M bytes a; N bytes b
+//           (mode 1: the local alignment score, with match, mismatch, gap in
+//           place of sub, gap, leaf_rows)
 //   output: int32 status, levels; int64 dist, len, sweep cells, leaf cells;
 //           len x 2 int32
 #include <barrier>
@@ -37,6 +39,7 @@ uint64_t cpu_wave_slots[16][64];
 unsigned char cpu_dynamic_lds[1];
 
 #include "dtw_edit.hip"
+#include "dtw_local.hip"
 
 namespace dtw {
 int g_model_hip = 0;
@@ -56,6 +59,21 @@ int main(int argc, char** argv) {
   std::vector<uint8_t> a(M + 1), b(N + 1);
   if (std::fread(a.data(), 1, M, f) != (size_t)M || std::fread(b.data(), 1, N, f) != (size_t)N) return 2;
   std::fclose(f);
+  if (p[3] == 1) {
+    // local alignment score: p[0..2] = match, mismatch, gap -> int32 status, int64 score, i_end, j_end
+    size_t lws = 0;
+    int lrc = dtw_local_workspace_size(M, N, &lws);
+    std::vector<unsigned char> LW(lrc == 0 ? lws : 1);
+    int64_t out[3] = {0, 0, 0};
+    if (lrc == 0)
+      lrc = dtw_local_score(M ? a.data() : nullptr, M, N ? b.data() : nullptr, N, p[0], p[1], p[2], LW.data(), lws, out,
+                            nullptr);
+    FILE* g = std::fopen(argv[2], "wb");
+    std::fwrite(&lrc, 4, 1, g);
+    std::fwrite(out, 8, 3, g);
+    std::fclose(g);
+    return 0;
+  }
   size_t ws = 0;
   int rc = dtw_edit_workspace_size(M, N, p[2], &ws);
   std::vector<unsigned char> W(rc == 0 ? ws : 1);

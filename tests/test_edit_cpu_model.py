@@ -32,8 +32,9 @@ def _build(d, extra=()):
 
 @pytest.fixture(scope="module")
 def edit_model(tmp_path_factory):
-    # problems up to 65536 rows take 128-row stripes (two rows per lane)
-    return _build(tmp_path_factory.mktemp("edit_model"))
+    # problems up to 65536 rows take 128-row stripes (two rows per lane); the
+    # local score's launch, switched off in the library, is switched on here
+    return _build(tmp_path_factory.mktemp("edit_model"), ["-DDTW_LOCAL_SCORE_ENABLED=1"])
 
 
 @pytest.fixture(scope="module")
@@ -113,3 +114,30 @@ def test_edit_model_rejects_bad_arguments(edit_model):
     assert run_edit_model(edit_model, a, b, 1, 1, 65)[0] == -1   # above one wave
     assert run_edit_model(edit_model, a, b, -1, 1, 8)[0] == -1   # negative cost
     assert run_edit_model(edit_model, a, b, 1 << 21, 1, 8)[0] == -1
+
+
+def run_local_model(exe, a, b, match, mismatch, gap):
+    with tempfile.TemporaryDirectory() as td:
+        fi, fo = os.path.join(td, "in"), os.path.join(td, "out")
+        with open(fi, "wb") as f:
+            f.write(struct.pack("2q4i", a.size, b.size, match, mismatch, gap, 1))
+            f.write(a.tobytes())
+            f.write(b.tobytes())
+        r = subprocess.run([exe, fi, fo], capture_output=True, timeout=600,
+                           env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+        assert r.returncode == 0, r.stderr.decode()[-3000:]
+        buf = open(fo, "rb").read()
+    (rc,) = struct.unpack_from("i", buf, 0)
+    return rc, struct.unpack_from("3q", buf, 4)
+
+
+# the local alignment score kernels (dtw_local.hip): empty strings, one
+# stripe, maxima in a later stripe, three stripes of identical strings
+@pytest.mark.parametrize("M,N,p", [(0, 5, 0.3), (5, 0, 0.3), (7, 9, 0.3), (300, 280, 0.3), (90, 600, 0.3),
+                                   (600, 90, 0.3), (530, 530, 0.0)])
+def test_local_model_equals_oracle(edit_model, M, N, p):
+    a, b = synth.string_pair(8300 + M + N, M, N, k=4, p=p)
+    for match, mismatch, gap in ((2, 1, 1), (3, 2, 2)):
+        rc, out = run_local_model(edit_model, a, b, match, mismatch, gap)
+        assert rc == 0
+        assert tuple(out) == edit.local_score(a, b, match, mismatch, gap)

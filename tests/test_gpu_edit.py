@@ -103,3 +103,63 @@ def test_edit_rejects_bad_arguments():
     for kw in (dict(leaf_rows=1), dict(leaf_rows=65), dict(sub=-1), dict(gap=1 << 21)):
         with pytest.raises(dtw.DtwError):
             dtw.edit_align(a, b, **{"sub": 1, "gap": 1, "leaf_rows": 64, **kw})
+
+
+# ------------------------------------------------------------------ local alignment score
+#
+# The device launch of dtw_local_score is switched off: its first launch (the
+# 1 x 1 case below) did not finish, and no cause has been shown.  Its kernels
+# run to the oracle's results in the CPU model (tests/test_edit_cpu_model.py);
+# these tests stay skipped until a cause is found and fixed.
+
+LOCAL_OFF = "dtw_local_score's device launch is switched off: its first launch did not finish on the device, cause not found"
+
+
+def test_local_score_reports_unsupported():
+    # the switched-off entry point checks its arguments and launches nothing
+    x = _dev(np.zeros(10, np.uint8))
+    with pytest.raises(dtw.DtwError) as e:
+        dtw.local_score(x, x, 2, 1, 1)
+    assert e.value.status == -8  # DTW_ERR_UNSUPPORTED
+    with pytest.raises(dtw.DtwError) as e:
+        dtw.local_score(x, x, 0, 1, 1)
+    assert e.value.status == -1  # DTW_ERR_INVALID_ARG: a match score below 1
+
+
+
+@pytest.mark.skip(reason=LOCAL_OFF)
+@pytest.mark.parametrize("M,N,p", [(0, 0, 0.1), (0, 9, 0.1), (9, 0, 0.1), (1, 1, 0.1), (63, 64, 0.3), (257, 300, 0.3),
+                                   (1000, 700, 0.2), (5000, 50, 0.1), (50, 20000, 0.1), (2000, 2000, 0.0),
+                                   (20000, 16000, 0.1), (60000, 50000, 0.1)])
+def test_local_score_equals_oracle(M, N, p):
+    print(f"local {M}x{N}", flush=True)
+    a, b = synth.string_pair(9500 + M + 3 * N, M, N, k=4, p=p)
+    for match, mismatch, gap in ((2, 1, 1), (1, 3, 2)):
+        assert dtw.local_score(_dev(a), _dev(b), match, mismatch, gap) == edit.local_score(a, b, match, mismatch, gap)
+
+
+@pytest.mark.skip(reason=LOCAL_OFF)
+def test_local_score_planted_substring():
+    # a common substring inside unrelated text, found at its end
+    rng = np.random.default_rng(3)
+    p = rng.integers(0, 4, 5000).astype(np.uint8)
+    u = np.concatenate([rng.integers(10, 14, 30000).astype(np.uint8), p, rng.integers(10, 14, 4000).astype(np.uint8)])
+    w = np.concatenate([rng.integers(20, 24, 12000).astype(np.uint8), p, rng.integers(20, 24, 900).astype(np.uint8)])
+    assert dtw.local_score(_dev(u), _dev(w), 2, 1, 1) == (10000, 35000, 17000)
+    assert edit.local_score(u, w, 2, 1, 1) == (10000, 35000, 17000)
+
+
+@pytest.mark.skip(reason=LOCAL_OFF)
+def test_local_score_reuse_and_bad_arguments():
+    a, b = synth.string_pair(31, 3000, 2500, k=4, p=0.2)
+    sc = dtw.LocalScorer(3000, 2500)
+    outs = []
+    for m in (2, 3, 2):
+        sc.run(_dev(a), _dev(b), m, 1, 1)
+        outs.append(tuple(sc.out.cpu().tolist()))
+    assert outs[0] == outs[2] == edit.local_score(a, b, 2, 1, 1)
+    assert outs[1] == edit.local_score(a, b, 3, 1, 1)
+    x = _dev(np.zeros(10, np.uint8))
+    for args in ((0, 1, 1), (2, -1, 1), (2, 1, 1 << 21)):
+        with pytest.raises(dtw.DtwError):
+            dtw.local_score(x, x, *args)
