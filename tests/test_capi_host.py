@@ -119,3 +119,48 @@ def test_noalloc_rejects_before_any_device_work():
     assert _noalloc(L, opts=dtw.make_opts(profile=1)) == -1
     assert "#define DTW_NOALLOC_SCRATCH_BYTES (64u << 20)" in open(dtw.HEADER).read()
     assert dtw.NOALLOC_SCRATCH_BYTES == 64 << 20
+
+
+def test_edit_and_local_argument_checks_before_any_device_work():
+    # every check below returns before a HIP call, so host buffers stand in
+    L = dtw.lib()
+    n = ctypes.c_size_t()
+    i64 = ctypes.c_int64
+    # workspace sizing: leaf height within 2..64, sizes within 0..2^30, linear in M + N
+    assert L.dtw_edit_workspace_size(100, 80, 1, ctypes.byref(n)) == -1
+    assert L.dtw_edit_workspace_size(100, 80, 65, ctypes.byref(n)) == -1
+    assert L.dtw_edit_workspace_size(-1, 80, 64, ctypes.byref(n)) == -1
+    assert L.dtw_edit_workspace_size(100, 80, 64, None) == -1
+    sizes = []
+    for M in (10000, 20000, 40000):
+        assert L.dtw_edit_workspace_size(M, M, 64, ctypes.byref(n)) == 0
+        sizes.append(n.value)
+    assert sizes[2] - sizes[1] < 2.2 * (sizes[1] - sizes[0])
+    assert sizes[2] < 200 * (40000 + 40000) < 40000 * 40000  # bytes: linear in M + N, never the M x N table
+    buf = (ctypes.c_uint8 * 4096)()
+    a = ctypes.cast(buf, ctypes.c_void_p)
+    d, ln = i64(0), i64(0)
+    path = (ctypes.c_int32 * 64)()
+    assert L.dtw_edit_workspace_size(10, 12, 8, ctypes.byref(n)) == 0
+    ws = n.value
+    args = lambda **k: dict(dict(M=10, N=12, sub=1, gap=1, h=8, wsb=ws, cap=23), **k)
+    def call(**k):
+        c = args(**k)
+        return L.dtw_edit_align(a, c["M"], a, c["N"], c["sub"], c["gap"], c["h"], a, c["wsb"],
+                                ctypes.byref(d), path, c["cap"], ctypes.byref(ln), None, None)
+    assert call(cap=22) == -2                # capacity below M + N + 1 nodes
+    assert call(wsb=ws - 1) == -3            # workspace below dtw_edit_workspace_size
+    assert call(sub=-1) == -1
+    assert call(gap=1 << 21) == -1
+    assert call(h=1) == -1
+    assert call(sub=1 << 20, M=2000, N=2000) == -1  # (M + N + 1) max(sub, gap) reaches 2^30
+    assert L.dtw_edit_align(None, 10, a, 12, 1, 1, 8, a, ws, ctypes.byref(d), path, 23, ctypes.byref(ln), None,
+                            None) == -1
+    # the local score: argument checks, then DTW_ERR_UNSUPPORTED (its device launch is switched off)
+    out = (i64 * 3)()
+    assert L.dtw_local_workspace_size(10, 12, ctypes.byref(n)) == 0
+    lws = n.value
+    assert L.dtw_local_score(a, 10, a, 12, 0, 1, 1, a, lws, out, None) == -1
+    assert L.dtw_local_score(a, 10, a, 12, 2, -1, 1, a, lws, out, None) == -1
+    assert L.dtw_local_score(a, 10, a, 12, 2, 1, 1, a, lws - 1, out, None) == -3
+    assert L.dtw_local_score(a, 10, a, 12, 2, 1, 1, a, lws, out, None) == -8
